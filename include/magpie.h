@@ -1,0 +1,205 @@
+/*
+ * magpie.h -- C ABI of the MI355X (gfx950) MAGPIE ptychography hot path.
+ *
+ * MAGPIE (arXiv 2504.10118) reconstructs a complex object z (n_rows x n_cols)
+ * from far-field intensities d_k = |F(Q * P_k z)|^2 measured at N scan
+ * positions (Section 2.1, problem statement), by minimising the exit-wave
+ * misfit of eq. (2.1) with the stochastic multigrid surrogate solver of
+ * Alg 4 (MAGPIE), whose per-position step is the V-cycle of Alg 3 (MAGPS).
+ * This library runs that solver with minibatches of positions on one GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status: MAGPIE_OK (0) or a negative
+ *   MAGPIE_ERR_* code.  magpie_last_error() returns a message describing
+ *   the last failure on the calling thread (valid until the next failing
+ *   call on that thread).  On error no output argument is written unless
+ *   stated otherwise.
+ * - Complex arrays are interleaved (re, im), row-major, i.e. the memory
+ *   layout of torch.complex64 (MAGPIE_C64) or torch.complex128 (MAGPIE_C128).
+ * - The 2-D DFT F is unnormalised with kernel exp(-2 pi i (a y + b x) / m)
+ *   and zero frequency at index [0][0] (no fftshift); F^{-1} = F^* / m^2.
+ * - Host pointers (on_device = 0) are read or written before the call
+ *   returns.  Device pointers (on_device = 1, e.g. torch's data_ptr() on the
+ *   same device) are used in stream order on the context's stream: inputs
+ *   must stay valid and unmodified until the next call that synchronises the
+ *   stream (any get_* into host memory, magpie_objective, magpie_sync,
+ *   magpie_destroy).  The library never frees caller memory.
+ * - A context owns all device memory it allocates and releases it in
+ *   magpie_destroy.  A context is not thread-safe; distinct contexts are
+ *   independent.
+ * - Call order: magpie_create -> magpie_set_probe -> magpie_set_positions ->
+ *   magpie_load_intensities -> [magpie_set_object] -> magpie_run_epochs ...
+ *   Out-of-order calls return MAGPIE_ERR_BAD_STATE.  The initial object is
+ *   all ones.
+ */
+#ifndef MAGPIE_H
+#define MAGPIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MAGPIE_OK               0
+#define MAGPIE_ERR_INVALID_ARG (-1)  /* null/out-of-range argument, bad offsets */
+#define MAGPIE_ERR_BAD_STATE   (-2)  /* call made before its prerequisites */
+#define MAGPIE_ERR_OOM         (-3)  /* device or pinned-host allocation failed */
+#define MAGPIE_ERR_HIP         (-4)  /* a HIP runtime call failed */
+#define MAGPIE_ERR_NUMERIC     (-5)  /* non-finite value found in inputs or objective */
+#define MAGPIE_ERR_UNSUPPORTED (-6)  /* m not in {8,16,32,64,128}, bad level count */
+
+/* complex element types */
+#define MAGPIE_C64  0   /* float  (re, im) */
+#define MAGPIE_C128 1   /* double (re, im) */
+
+/* flags for magpie_set_flags */
+#define MAGPIE_UPDATE_PROBE 0x1u  /* also update the probe each minibatch (beyond the paper) */
+
+typedef struct magpie_ctx magpie_ctx;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* magpie_last_error(void);
+
+/*
+ * Create a reconstruction context on HIP device `device`.
+ *   n_rows, n_cols : object size (>= m each).
+ *   m              : probe / patch side; one of 8, 16, 32, 64, 128.
+ *   n_levels       : number of grids of the MAGPS V-cycle (Alg 3): the fine
+ *                    grid plus n_levels-1 coarse grids, 1 <= n_levels <=
+ *                    log2(m)+1.  n_levels = 1 is rPIE (Alg 1, eq. 2.3).
+ *   alpha          : rPIE constant of u = alpha (max|Q|^2 - |Q|^2)
+ *                    (Section 2.1, the u^rPIE definition; Section 5), >= 0.
+ *   hip_stream     : hipStream_t to run on, or NULL to create a private one.
+ * Errors: INVALID_ARG, UNSUPPORTED, HIP, OOM.
+ */
+int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
+                  double alpha, int device, void* hip_stream);
+
+/* Synchronise the stream and release every device allocation.  NULL is a no-op. */
+int magpie_destroy(magpie_ctx* ctx);
+
+/*
+ * Set the probe Q (m x m complex, dtype MAGPIE_C64 or MAGPIE_C128) and build
+ * the level hierarchy of Alg 3 in FP64 on the device: Q_{l+1} = I_h^H Q_l,
+ * the weights of eq. (4.4), u_{l+1} = W_u^H (I_h^H u_l), and the per-level
+ * coefficients of the gradient form of the coarse step (eq. 4.6).  The
+ * regularisation is reset to u^rPIE with the context's alpha.
+ * Errors: INVALID_ARG (null, Q identically zero), NUMERIC (non-finite), HIP.
+ */
+int magpie_set_probe(magpie_ctx* ctx, const void* probe, int dtype, int on_device);
+
+/*
+ * Replace the fine-grid regularisation vector (Section 2.1, eq. 2.4).
+ * u == NULL: u = alpha (max|Q|^2 - |Q|^2) (u^rPIE).  Otherwise u is a host
+ * array of m*m doubles >= 0.  Coarse-level vectors follow automatically
+ * (Prop 4.4).  Requires a probe.  Errors: INVALID_ARG, BAD_STATE, HIP.
+ */
+int magpie_set_regularization(magpie_ctx* ctx, double alpha, const double* u);
+
+/*
+ * Scan positions: offsets is a host array [n_pos][2] of int32 (row, col)
+ * top-left corners of the m x m windows P_k (Section 2.1), with
+ * 0 <= row <= n_rows - m and 0 <= col <= n_cols - m.  Resets loaded
+ * intensities.  Errors: INVALID_ARG (bounds, n_pos < 1), OOM, HIP.
+ */
+int magpie_set_positions(magpie_ctx* ctx, int n_pos, const int32_t* offsets);
+
+/*
+ * Measured data: float32 [n_pos][m][m], zero frequency at [0][0].
+ * is_sqrt = 0: intensities d_k (>= 0), the library takes square roots;
+ * is_sqrt = 1: amplitudes sqrt(d_k).  Stored internally in the order the
+ * kernels consume.  Errors: BAD_STATE (no positions), INVALID_ARG, HIP.
+ */
+int magpie_load_intensities(magpie_ctx* ctx, const float* d, int is_sqrt, int on_device);
+
+/* Set the object z (n_rows x n_cols complex).  Errors: INVALID_ARG, HIP. */
+int magpie_set_object(magpie_ctx* ctx, const void* z, int dtype, int on_device);
+
+/*
+ * Run n_epochs epochs of minibatch MAGPIE (Alg 4 with the minibatch
+ * combination): each epoch draws a uniformly random permutation of the
+ * positions and cuts it into consecutive minibatches of `batch` positions
+ * (the last one shorter).  In a minibatch every position reads the same z,
+ * computes its revised exit wave (Definition 2.1) and its MAGPS update
+ * dz_k (Alg 3), and the object becomes
+ *     z <- z + sum_k P_k^T (w0 dz_k) / sum_k P_k^T w0,   w0 = u + |Q|^2,
+ * on pixels covered by the minibatch.  batch = 1 is Alg 4 exactly.
+ *   order : NULL -> permutations from splitmix64-driven Fisher-Yates seeded
+ *           with seed XOR epoch_index (epoch_index counts epochs run on this
+ *           context); otherwise a host array [n_epochs][n_pos] of
+ *           permutations of 0..n_pos-1, used as given.
+ * Asynchronous: returns after enqueuing.  Errors: BAD_STATE, INVALID_ARG
+ * (batch < 1, order not a permutation), HIP.
+ */
+int magpie_run_epochs(magpie_ctx* ctx, int n_epochs, int batch, uint64_t seed,
+                      const int32_t* order);
+
+/*
+ * Objective pass over all positions at the current object (eq. 2.1, reported
+ * in exit-wave form (1 / (2 m^2)) sum_k || |F(Q z_k)| - sqrt(d_k) ||^2),
+ * reduced in FP64 in a fixed order.  grad_stat (nullable) receives the
+ * stopping statistic (1 / (N m)) sum_k ||conj(Q)(Q z_k - R_k(z_k))||_2
+ * (Section 5, "Stopping criterion").  Synchronises.
+ * Errors: BAD_STATE, NUMERIC (non-finite objective), HIP.
+ */
+int magpie_objective(magpie_ctx* ctx, double* phi, double* grad_stat);
+
+/*
+ * Per-position objective terms Phi_k (FP64, [n_pos]) at the object as it was
+ * when each position was last visited by magpie_run_epochs (NaN if never).
+ * Host output; synchronises.
+ */
+int magpie_get_step_phi(magpie_ctx* ctx, double* phi_k);
+
+/* Copy the object / probe out (dtype C64 or C128).  Host outputs synchronise. */
+int magpie_get_object(magpie_ctx* ctx, void* out, int dtype, int on_device);
+int magpie_get_probe(magpie_ctx* ctx, void* out, int dtype, int on_device);
+
+/* Wait for all work enqueued on the context's stream. */
+int magpie_sync(magpie_ctx* ctx);
+
+/* Set behaviour flags (MAGPIE_UPDATE_PROBE).  beta: probe-step proximal weight. */
+int magpie_set_flags(magpie_ctx* ctx, uint32_t flags, double beta);
+
+/*
+ * Forward model (Section 2.1): d_k = |F(Q * P_k z)|^2 for every position, at
+ * the given object z (n_rows x n_cols, dtype C64, host or device) with the
+ * context's probe and positions, written to d_out float32 [n_pos][m][m]
+ * (zero frequency at [0][0]).  Errors: BAD_STATE, INVALID_ARG, HIP.
+ */
+int magpie_forward_model(magpie_ctx* ctx, const void* z, int z_on_device,
+                         float* d_out, int out_on_device);
+
+/*
+ * The library's epoch permutation: Fisher-Yates over 0..n-1, for
+ * i = n-1 .. 1 swapping entries i and (next mod (i+1)), where next are the
+ * outputs of splitmix64 (Steele, Lea & Flood 2014) started from state
+ * seed XOR epoch.  Host output [n].  Errors: INVALID_ARG.
+ */
+int magpie_permutation(uint64_t seed, uint64_t epoch, int n, int32_t* out);
+
+/* Number of epochs run so far on this context (drives the seeded permutations). */
+int magpie_get_epoch_index(magpie_ctx* ctx, uint64_t* epoch_index);
+int magpie_set_epoch_index(magpie_ctx* ctx, uint64_t epoch_index);
+
+/*
+ * Kernel timing for measurement.  While enabled, magpie_run_epochs brackets
+ * every launch of the per-position step kernel and of the accumulation
+ * kernel with HIP events on the context's stream.  magpie_get_timing
+ * synchronises, returns the summed event times (milliseconds), the number
+ * of launches of each kernel and the number of positions processed by the
+ * step kernel since timing was last read or enabled, and resets the sums.
+ * Errors: INVALID_ARG, HIP.
+ */
+int magpie_set_timing(magpie_ctx* ctx, int enable);
+int magpie_get_timing(magpie_ctx* ctx, double* step_ms, double* accum_ms, int64_t* step_launches,
+                      int64_t* accum_launches, int64_t* positions);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAGPIE_H */

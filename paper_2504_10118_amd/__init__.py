@@ -1,0 +1,17 @@
+"""MI355X (gfx950) MAGPIE ptychography hot path: HIP kernels behind a C ABI.
+
+The solver (arXiv 2504.10118, Alg 3 and Alg 4 with minibatches) runs in
+``lib/libmagpie.so``, built from ``csrc/`` by ``python -m
+paper_2504_10118_amd.build``.  This package only marshals arguments.
+"""
+
+from .magpie import (  # noqa: F401
+    C64,
+    C128,
+    UPDATE_PROBE,
+    LIB_PATH,
+    Magpie,
+    MagpieError,
+    load_library,
+    permutation,
+)

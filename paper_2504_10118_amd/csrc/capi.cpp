@@ -1,0 +1,781 @@
+// Host runtime of the MAGPIE C ABI (include/magpie.h): context, device
+// buffers, input validation, epoch scheduling and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/magpie.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define MG_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(MAGPIE_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+bool valid_m(int m) { return m == 8 || m == 16 || m == 32 || m == 64 || m == 128; }
+
+int ilog2(int m) {
+  int l = 0;
+  while ((1 << l) < m) ++l;
+  return l;
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return MAGPIE_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(MAGPIE_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  return MAGPIE_OK;
+}
+
+template <typename T>
+void dev_free(T*& p) {
+  if (p) hipFree((void*)p);
+  p = nullptr;
+}
+
+uint64_t splitmix64_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void fisher_yates(uint64_t seed, uint64_t epoch, int n, int32_t* out) {
+  for (int i = 0; i < n; ++i) out[i] = i;
+  uint64_t st = seed ^ epoch;
+  for (int i = n - 1; i > 0; --i) {
+    const uint64_t j = splitmix64_next(st) % (uint64_t)(i + 1);
+    std::swap(out[i], out[(size_t)j]);
+  }
+}
+
+}  // namespace
+
+struct magpie_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int nr = 0, nc = 0, m = 0, L = 1;
+  double alpha = 0.0;
+  uint32_t flags = 0;
+  double beta = 0.0;
+  bool u_given = false;
+  int n_pos = 0;
+  bool has_probe = false, has_pos = false, has_data = false;
+  uint64_t epoch_index = 0;
+
+  // device buffers
+  float2* z = nullptr;
+  float2* qf = nullptr;
+  double2* q64 = nullptr;
+  double* u0 = nullptr;
+  double* w0 = nullptr;
+  float* u0f = nullptr;
+  double* lvl = nullptr;
+  double2* scr_q = nullptr;
+  double* scr_u = nullptr;
+  int* flag = nullptr;
+  double* red = nullptr;
+
+  int2* offs = nullptr;
+  float* sqrtd = nullptr;
+  double* phi_step = nullptr;
+  double* phi_obj = nullptr;
+  double* gnorm = nullptr;
+  int* tile_ptr = nullptr;
+  int* tile_pos = nullptr;
+  int tiles_x = 0, tiles_y = 0;
+  std::vector<int32_t> h_offs;
+
+  float2* stage = nullptr;
+  size_t stage_cap = 0;  // in float2
+  int* perm = nullptr;   // [E][N]
+  int* inv = nullptr;    // [E][N]
+  size_t perm_cap = 0;   // ints per array
+  int32_t* h_pin = nullptr;
+  size_t h_pin_cap = 0;  // ints
+  hipEvent_t pin_done = nullptr;
+  bool pin_pending = false;
+
+  // optional per-launch timing
+  bool timing = false;
+  struct Timed {
+    hipEvent_t a, b;
+    int kind;   // 0 = step kernel, 1 = accumulate kernel
+    int count;  // positions (step kernel)
+  };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Timed> timed;
+};
+
+namespace {
+
+int set_dev(magpie_ctx* c) {
+  MG_HIP(hipSetDevice(c->device));
+  return MAGPIE_OK;
+}
+
+int free_positions(magpie_ctx* c) {
+  dev_free(c->offs);
+  dev_free(c->sqrtd);
+  dev_free(c->phi_step);
+  dev_free(c->phi_obj);
+  dev_free(c->gnorm);
+  dev_free(c->tile_ptr);
+  dev_free(c->tile_pos);
+  c->has_pos = false;
+  c->has_data = false;
+  c->n_pos = 0;
+  return MAGPIE_OK;
+}
+
+int rebuild_levels(magpie_ctx* c) {
+  MG_HIP(mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->u0f,
+                                    c->qf, c->lvl, c->scr_q, c->scr_u, c->stream));
+  return MAGPIE_OK;
+}
+
+hipEvent_t take_event(magpie_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Record the start event of a timed launch; returns index into c->timed or -1.
+int timed_begin(magpie_ctx* c, int kind, int count) {
+  if (!c->timing) return -1;
+  magpie_ctx::Timed t{take_event(c), take_event(c), kind, count};
+  if (!t.a || !t.b || hipEventRecord(t.a, c->stream) != hipSuccess) return -1;
+  c->timed.push_back(t);
+  return (int)c->timed.size() - 1;
+}
+
+void timed_end(magpie_ctx* c, int idx) {
+  if (idx >= 0) hipEventRecord(c->timed[idx].b, c->stream);
+}
+
+int read_flag(magpie_ctx* c, int* out) {
+  int h = 0;
+  MG_HIP(hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  *out = h;
+  return MAGPIE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* magpie_last_error(void) { return g_last_error.c_str(); }
+
+int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels, double alpha, int device,
+                  void* hip_stream) {
+  if (!out) return fail(MAGPIE_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!valid_m(m)) return fail(MAGPIE_ERR_UNSUPPORTED, "m must be one of 8, 16, 32, 64, 128");
+  if (n_levels < 1 || n_levels > ilog2(m) + 1)
+    return fail(MAGPIE_ERR_UNSUPPORTED, "n_levels must be in [1, log2(m)+1]");
+  if (n_rows < m || n_cols < m) return fail(MAGPIE_ERR_INVALID_ARG, "object smaller than the probe");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MAGPIE_ERR_INVALID_ARG, "alpha must be finite, >= 0");
+  int ndev = 0;
+  MG_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(MAGPIE_ERR_INVALID_ARG, "no such device");
+
+  magpie_ctx* c = new magpie_ctx();
+  c->device = device;
+  c->nr = n_rows;
+  c->nc = n_cols;
+  c->m = m;
+  c->L = n_levels;
+  c->alpha = alpha;
+  int rc = set_dev(c);
+  if (rc) { delete c; return rc; }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(MAGPIE_ERR_HIP, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  const size_t mm = (size_t)m * m;
+  const size_t half = (size_t)(m / 2) * (m / 2);
+  size_t nlvl = 0;
+  for (int l = 1; l < n_levels; ++l) nlvl += 3 * (size_t)(m >> l) * (m >> l);
+  rc = dev_alloc(&c->z, (size_t)n_rows * n_cols);
+  if (!rc) rc = dev_alloc(&c->qf, mm);
+  if (!rc) rc = dev_alloc(&c->q64, mm);
+  if (!rc) rc = dev_alloc(&c->u0, mm);
+  if (!rc) rc = dev_alloc(&c->w0, mm);
+  if (!rc) rc = dev_alloc(&c->u0f, mm);
+  if (!rc) rc = dev_alloc(&c->lvl, std::max<size_t>(nlvl, 1));
+  if (!rc) rc = dev_alloc(&c->scr_q, 2 * half);
+  if (!rc) rc = dev_alloc(&c->scr_u, 2 * half);
+  if (!rc) rc = dev_alloc(&c->flag, 1);
+  if (!rc) rc = dev_alloc(&c->red, 4);
+  if (!rc && hipEventCreateWithFlags(&c->pin_done, hipEventDisableTiming) != hipSuccess)
+    rc = fail(MAGPIE_ERR_HIP, "hipEventCreate failed");
+  if (rc) {
+    magpie_destroy(c);
+    return rc;
+  }
+  // initial object: all ones
+  {
+    std::vector<float2> ones((size_t)n_rows * n_cols, make_float2(1.0f, 0.0f));
+    if (hipMemcpy(c->z, ones.data(), ones.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+      magpie_destroy(c);
+      return fail(MAGPIE_ERR_HIP, "object init copy failed");
+    }
+  }
+  if (mg::init_twiddles(c->stream) != hipSuccess) {
+    magpie_destroy(c);
+    return fail(MAGPIE_ERR_HIP, "twiddle init failed");
+  }
+  *out = c;
+  return MAGPIE_OK;
+}
+
+int magpie_destroy(magpie_ctx* c) {
+  if (!c) return MAGPIE_OK;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_positions(c);
+  dev_free(c->z);
+  dev_free(c->qf);
+  dev_free(c->q64);
+  dev_free(c->u0);
+  dev_free(c->w0);
+  dev_free(c->u0f);
+  dev_free(c->lvl);
+  dev_free(c->scr_q);
+  dev_free(c->scr_u);
+  dev_free(c->flag);
+  dev_free(c->red);
+  dev_free(c->stage);
+  dev_free(c->perm);
+  dev_free(c->inv);
+  if (c->h_pin) hipHostFree(c->h_pin);
+  if (c->pin_done) hipEventDestroy(c->pin_done);
+  for (auto& t : c->timed) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto e : c->ev_pool) hipEventDestroy(e);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+  return MAGPIE_OK;
+}
+
+int magpie_set_probe(magpie_ctx* c, const void* probe, int dtype, int on_device) {
+  if (!c || !probe) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  if (dtype != MAGPIE_C64 && dtype != MAGPIE_C128) return fail(MAGPIE_ERR_INVALID_ARG, "bad dtype");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  const size_t mm = (size_t)c->m * c->m;
+  std::vector<double2> h(mm);
+  if (on_device) {
+    if (dtype == MAGPIE_C64) {
+      std::vector<float2> t(mm);
+      MG_HIP(hipMemcpyAsync(t.data(), probe, mm * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
+      MG_HIP(hipStreamSynchronize(c->stream));
+      for (size_t i = 0; i < mm; ++i) h[i] = make_double2(t[i].x, t[i].y);
+    } else {
+      MG_HIP(hipMemcpyAsync(h.data(), probe, mm * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+      MG_HIP(hipStreamSynchronize(c->stream));
+    }
+  } else if (dtype == MAGPIE_C64) {
+    const float2* p = (const float2*)probe;
+    for (size_t i = 0; i < mm; ++i) h[i] = make_double2(p[i].x, p[i].y);
+  } else {
+    std::memcpy(h.data(), probe, mm * sizeof(double2));
+  }
+  double mx = 0.0;
+  for (size_t i = 0; i < mm; ++i) {
+    if (!std::isfinite(h[i].x) || !std::isfinite(h[i].y)) return fail(MAGPIE_ERR_NUMERIC, "non-finite probe");
+    mx = std::max(mx, h[i].x * h[i].x + h[i].y * h[i].y);
+  }
+  if (!(mx > 0.0)) return fail(MAGPIE_ERR_INVALID_ARG, "probe is identically zero");
+  MG_HIP(hipMemcpyAsync(c->q64, h.data(), mm * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  c->u_given = false;
+  rc = rebuild_levels(c);
+  if (rc) return rc;
+  c->has_probe = true;
+  return MAGPIE_OK;
+}
+
+int magpie_set_regularization(magpie_ctx* c, double alpha, const double* u) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (!c->has_probe) return fail(MAGPIE_ERR_BAD_STATE, "set the probe first");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  if (u) {
+    const size_t mm = (size_t)c->m * c->m;
+    for (size_t i = 0; i < mm; ++i)
+      if (!(u[i] >= 0.0) || !std::isfinite(u[i])) return fail(MAGPIE_ERR_INVALID_ARG, "u must be finite, >= 0");
+    MG_HIP(hipMemcpyAsync(c->u0, u, mm * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    MG_HIP(hipStreamSynchronize(c->stream));
+    c->u_given = true;
+  } else {
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MAGPIE_ERR_INVALID_ARG, "alpha must be finite, >= 0");
+    c->alpha = alpha;
+    c->u_given = false;
+  }
+  return rebuild_levels(c);
+}
+
+int magpie_set_positions(magpie_ctx* c, int n_pos, const int32_t* offsets) {
+  if (!c || !offsets) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  if (n_pos < 1) return fail(MAGPIE_ERR_INVALID_ARG, "n_pos must be >= 1");
+  for (int k = 0; k < n_pos; ++k) {
+    const int r = offsets[2 * k], cc = offsets[2 * k + 1];
+    if (r < 0 || r > c->nr - c->m || cc < 0 || cc > c->nc - c->m)
+      return fail(MAGPIE_ERR_INVALID_ARG, "scan offset " + std::to_string(k) + " out of bounds");
+  }
+  int rc = set_dev(c);
+  if (rc) return rc;
+  MG_HIP(hipStreamSynchronize(c->stream));
+  free_positions(c);
+  const int m = c->m;
+  c->tiles_x = (c->nc + mg::ACC_TILE_W - 1) / mg::ACC_TILE_W;
+  c->tiles_y = (c->nr + mg::ACC_TILE_H - 1) / mg::ACC_TILE_H;
+  const int nt = c->tiles_x * c->tiles_y;
+  std::vector<std::vector<int>> lists(nt);
+  for (int k = 0; k < n_pos; ++k) {
+    const int r = offsets[2 * k], cc = offsets[2 * k + 1];
+    for (int ty = r / mg::ACC_TILE_H; ty <= (r + m - 1) / mg::ACC_TILE_H; ++ty)
+      for (int tx = cc / mg::ACC_TILE_W; tx <= (cc + m - 1) / mg::ACC_TILE_W; ++tx)
+        lists[ty * c->tiles_x + tx].push_back(k);
+  }
+  std::vector<int> ptr(nt + 1, 0), pos;
+  for (int t = 0; t < nt; ++t) {
+    ptr[t + 1] = ptr[t] + (int)lists[t].size();
+    pos.insert(pos.end(), lists[t].begin(), lists[t].end());
+  }
+  rc = dev_alloc(&c->offs, n_pos);
+  if (!rc) rc = dev_alloc(&c->sqrtd, (size_t)n_pos * m * m);
+  if (!rc) rc = dev_alloc(&c->phi_step, n_pos);
+  if (!rc) rc = dev_alloc(&c->phi_obj, n_pos);
+  if (!rc) rc = dev_alloc(&c->gnorm, n_pos);
+  if (!rc) rc = dev_alloc(&c->tile_ptr, nt + 1);
+  if (!rc) rc = dev_alloc(&c->tile_pos, std::max<size_t>(pos.size(), 1));
+  if (rc) {
+    free_positions(c);
+    return rc;
+  }
+  MG_HIP(hipMemcpyAsync(c->offs, offsets, (size_t)n_pos * sizeof(int2), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipMemcpyAsync(c->tile_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  if (!pos.empty())
+    MG_HIP(hipMemcpyAsync(c->tile_pos, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  std::vector<double> nan(n_pos, std::nan(""));
+  MG_HIP(hipMemcpyAsync(c->phi_step, nan.data(), n_pos * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  c->h_offs.assign(offsets, offsets + 2 * (size_t)n_pos);
+  c->n_pos = n_pos;
+  c->has_pos = true;
+  return MAGPIE_OK;
+}
+
+int magpie_load_intensities(magpie_ctx* c, const float* d, int is_sqrt, int on_device) {
+  if (!c || !d) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  if (!c->has_pos) return fail(MAGPIE_ERR_BAD_STATE, "set positions first");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  const size_t cnt = (size_t)c->n_pos * c->m * c->m;
+  const float* src = d;
+  float* tmp = nullptr;
+  if (!on_device) {
+    rc = dev_alloc(&tmp, cnt);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(tmp, d, cnt * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+      dev_free(tmp);
+      return fail(MAGPIE_ERR_HIP, "intensity upload failed");
+    }
+    src = tmp;
+  }
+  MG_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  hipError_t e = mg::launch_permute_sqrt(c->m, c->n_pos, src, is_sqrt ? 1 : 0, c->sqrtd, c->flag, c->stream);
+  int bad = 0;
+  rc = (e == hipSuccess) ? read_flag(c, &bad) : fail(MAGPIE_ERR_HIP, "permute kernel launch failed");
+  dev_free(tmp);
+  if (rc) return rc;
+  if (bad) {
+    c->has_data = false;
+    return fail(MAGPIE_ERR_NUMERIC, "intensities contain negative or non-finite values");
+  }
+  c->has_data = true;
+  return MAGPIE_OK;
+}
+
+int magpie_set_object(magpie_ctx* c, const void* z, int dtype, int on_device) {
+  if (!c || !z) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  if (dtype != MAGPIE_C64 && dtype != MAGPIE_C128) return fail(MAGPIE_ERR_INVALID_ARG, "bad dtype");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  const size_t n = (size_t)c->nr * c->nc;
+  if (on_device) {
+    if (dtype == MAGPIE_C64) {
+      MG_HIP(hipMemcpyAsync(c->z, z, n * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      MG_HIP(mg::launch_convert_c128_c64((const double2*)z, c->z, n, c->stream));
+    }
+  } else {
+    if (dtype == MAGPIE_C64) {
+      MG_HIP(hipMemcpyAsync(c->z, z, n * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+      MG_HIP(hipStreamSynchronize(c->stream));
+    } else {
+      std::vector<float2> t(n);
+      const double2* p = (const double2*)z;
+      for (size_t i = 0; i < n; ++i) t[i] = make_float2((float)p[i].x, (float)p[i].y);
+      MG_HIP(hipMemcpyAsync(c->z, t.data(), n * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+      MG_HIP(hipStreamSynchronize(c->stream));
+    }
+  }
+  MG_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  MG_HIP(mg::launch_check_finite_c64(c->z, n, c->flag, c->stream));
+  int bad = 0;
+  rc = read_flag(c, &bad);
+  if (rc) return rc;
+  if (bad) return fail(MAGPIE_ERR_NUMERIC, "object contains non-finite values");
+  return MAGPIE_OK;
+}
+
+int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (!c->has_probe || !c->has_pos || !c->has_data)
+    return fail(MAGPIE_ERR_BAD_STATE, "set probe, positions and intensities first");
+  if (n_epochs < 0 || batch < 1) return fail(MAGPIE_ERR_INVALID_ARG, "n_epochs >= 0 and batch >= 1 required");
+  if (n_epochs == 0) return MAGPIE_OK;
+  int rc = set_dev(c);
+  if (rc) return rc;
+  const int N = c->n_pos, m = c->m;
+  const int B = std::min(batch, N);
+  const int nbatch = (N + B - 1) / B;
+  const size_t need_stage = (size_t)B * m * m;
+  if (need_stage > c->stage_cap) {
+    MG_HIP(hipStreamSynchronize(c->stream));
+    dev_free(c->stage);
+    rc = dev_alloc(&c->stage, need_stage);
+    if (rc) {
+      c->stage_cap = 0;
+      return rc;
+    }
+    c->stage_cap = need_stage;
+  }
+  const size_t nperm = (size_t)n_epochs * N;
+  if (nperm > c->perm_cap) {
+    MG_HIP(hipStreamSynchronize(c->stream));
+    dev_free(c->perm);
+    dev_free(c->inv);
+    rc = dev_alloc(&c->perm, nperm);
+    if (!rc) rc = dev_alloc(&c->inv, nperm);
+    if (rc) {
+      dev_free(c->perm);
+      c->perm_cap = 0;
+      return rc;
+    }
+    c->perm_cap = nperm;
+  }
+  if (c->pin_pending) {
+    MG_HIP(hipEventSynchronize(c->pin_done));
+    c->pin_pending = false;
+  }
+  if (2 * nperm > c->h_pin_cap) {
+    if (c->h_pin) hipHostFree(c->h_pin);
+    c->h_pin = nullptr;
+    c->h_pin_cap = 0;
+    if (hipHostMalloc((void**)&c->h_pin, 2 * nperm * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+      c->h_pin = nullptr;
+      return fail(MAGPIE_ERR_OOM, "pinned host allocation failed");
+    }
+    c->h_pin_cap = 2 * nperm;
+  }
+  int32_t* hp = c->h_pin;
+  int32_t* hi = c->h_pin + nperm;
+  for (int e = 0; e < n_epochs; ++e) {
+    int32_t* p = hp + (size_t)e * N;
+    int32_t* q = hi + (size_t)e * N;
+    if (order) {
+      std::memcpy(p, order + (size_t)e * N, (size_t)N * sizeof(int32_t));
+    } else {
+      fisher_yates(seed, c->epoch_index + (uint64_t)e, N, p);
+    }
+    for (int i = 0; i < N; ++i) q[i] = -1;
+    for (int i = 0; i < N; ++i) {
+      const int k = p[i];
+      if (k < 0 || k >= N || q[k] != -1)
+        return fail(MAGPIE_ERR_INVALID_ARG, "order row " + std::to_string(e) + " is not a permutation");
+      q[k] = i;
+    }
+  }
+  MG_HIP(hipMemcpyAsync(c->perm, hp, nperm * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipMemcpyAsync(c->inv, hi, nperm * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipEventRecord(c->pin_done, c->stream));
+  c->pin_pending = true;
+
+  mg::StepArgs sa{};
+  sa.z = c->z;
+  sa.n_cols = c->nc;
+  sa.q = c->qf;
+  sa.sqrtd = c->sqrtd;
+  sa.offs = c->offs;
+  sa.stage = c->stage;
+  sa.u0f = c->u0f;
+  sa.lvl = c->lvl;
+  sa.levels = c->L;
+  sa.phi_k = c->phi_step;
+  mg::AccumArgs aa{};
+  aa.z = c->z;
+  aa.n_rows = c->nr;
+  aa.n_cols = c->nc;
+  aa.m = m;
+  aa.tiles_x = c->tiles_x;
+  aa.tile_ptr = c->tile_ptr;
+  aa.tile_pos = c->tile_pos;
+  aa.batch = B;
+  aa.stage = c->stage;
+  aa.offs = c->offs;
+  aa.w0 = c->w0;
+  const int n_tiles = c->tiles_x * c->tiles_y;
+  for (int e = 0; e < n_epochs; ++e) {
+    for (int t = 0; t < nbatch; ++t) {
+      sa.perm = c->perm + (size_t)e * N + (size_t)t * B;
+      sa.count = std::min(B, N - t * B);
+      int ti = timed_begin(c, 0, sa.count);
+      MG_HIP(mg::launch_step(m, mg::MODE_STEP, sa, c->stream));
+      timed_end(c, ti);
+      aa.inv = c->inv + (size_t)e * N;
+      aa.batch_index = t;
+      ti = timed_begin(c, 1, 0);
+      MG_HIP(mg::launch_accumulate(aa, n_tiles, c->stream));
+      timed_end(c, ti);
+    }
+  }
+  c->epoch_index += (uint64_t)n_epochs;
+  return MAGPIE_OK;
+}
+
+int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {
+  if (!c || !phi) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  if (!c->has_probe || !c->has_pos || !c->has_data)
+    return fail(MAGPIE_ERR_BAD_STATE, "set probe, positions and intensities first");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  mg::StepArgs sa{};
+  sa.z = c->z;
+  sa.n_cols = c->nc;
+  sa.q = c->qf;
+  sa.sqrtd = c->sqrtd;
+  sa.offs = c->offs;
+  sa.perm = nullptr;
+  sa.count = c->n_pos;
+  sa.u0f = c->u0f;
+  sa.lvl = c->lvl;
+  sa.levels = c->L;
+  sa.phi_k = c->phi_obj;
+  sa.gnorm_k = c->gnorm;
+  MG_HIP(mg::launch_step(c->m, mg::MODE_OBJECTIVE, sa, c->stream));
+  MG_HIP(mg::launch_reduce_sum(c->phi_obj, c->n_pos, c->red, c->stream));
+  MG_HIP(mg::launch_reduce_sum(c->gnorm, c->n_pos, c->red + 1, c->stream));
+  double h[2];
+  MG_HIP(hipMemcpyAsync(h, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(MAGPIE_ERR_NUMERIC, "non-finite objective");
+  *phi = h[0];
+  if (grad_stat) *grad_stat = h[1] / ((double)c->n_pos * c->m);
+  return MAGPIE_OK;
+}
+
+int magpie_get_step_phi(magpie_ctx* c, double* phi_k) {
+  if (!c || !phi_k) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  if (!c->has_pos) return fail(MAGPIE_ERR_BAD_STATE, "no positions");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  MG_HIP(hipMemcpyAsync(phi_k, c->phi_step, (size_t)c->n_pos * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  return MAGPIE_OK;
+}
+
+static int copy_out_c64(magpie_ctx* c, const float2* src, size_t n, void* out, int dtype, int on_device) {
+  if (dtype != MAGPIE_C64 && dtype != MAGPIE_C128) return fail(MAGPIE_ERR_INVALID_ARG, "bad dtype");
+  if (on_device) {
+    if (dtype == MAGPIE_C64) {
+      MG_HIP(hipMemcpyAsync(out, src, n * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      MG_HIP(mg::launch_convert_c64_c128(src, (double2*)out, n, c->stream));
+    }
+    return MAGPIE_OK;
+  }
+  if (dtype == MAGPIE_C64) {
+    MG_HIP(hipMemcpyAsync(out, src, n * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
+    MG_HIP(hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float2> t(n);
+    MG_HIP(hipMemcpyAsync(t.data(), src, n * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
+    MG_HIP(hipStreamSynchronize(c->stream));
+    double2* o = (double2*)out;
+    for (size_t i = 0; i < n; ++i) o[i] = make_double2(t[i].x, t[i].y);
+  }
+  return MAGPIE_OK;
+}
+
+int magpie_get_object(magpie_ctx* c, void* out, int dtype, int on_device) {
+  if (!c || !out) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  return copy_out_c64(c, c->z, (size_t)c->nr * c->nc, out, dtype, on_device);
+}
+
+int magpie_get_probe(magpie_ctx* c, void* out, int dtype, int on_device) {
+  if (!c || !out) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  if (!c->has_probe) return fail(MAGPIE_ERR_BAD_STATE, "no probe set");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  return copy_out_c64(c, c->qf, (size_t)c->m * c->m, out, dtype, on_device);
+}
+
+int magpie_sync(magpie_ctx* c) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  MG_HIP(hipStreamSynchronize(c->stream));
+  return MAGPIE_OK;
+}
+
+int magpie_set_flags(magpie_ctx* c, uint32_t flags, double beta) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (flags & ~MAGPIE_UPDATE_PROBE) return fail(MAGPIE_ERR_INVALID_ARG, "unknown flag");
+  if (flags & MAGPIE_UPDATE_PROBE) return fail(MAGPIE_ERR_UNSUPPORTED, "probe update is not available yet");
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(MAGPIE_ERR_INVALID_ARG, "beta must be finite, >= 0");
+  c->flags = flags;
+  c->beta = beta;
+  return MAGPIE_OK;
+}
+
+int magpie_forward_model(magpie_ctx* c, const void* z, int z_on_device, float* d_out, int out_on_device) {
+  if (!c || !z || !d_out) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  if (!c->has_probe || !c->has_pos) return fail(MAGPIE_ERR_BAD_STATE, "set probe and positions first");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  const size_t nz = (size_t)c->nr * c->nc;
+  const size_t nd = (size_t)c->n_pos * c->m * c->m;
+  float2* zt = nullptr;
+  float* dt = nullptr;
+  const float2* zsrc = (const float2*)z;
+  if (!z_on_device) {
+    rc = dev_alloc(&zt, nz);
+    if (rc) return rc;
+    if (hipMemcpyAsync(zt, z, nz * sizeof(float2), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+      dev_free(zt);
+      return fail(MAGPIE_ERR_HIP, "object upload failed");
+    }
+    zsrc = zt;
+  }
+  float* dst = d_out;
+  if (!out_on_device) {
+    rc = dev_alloc(&dt, nd);
+    if (rc) {
+      dev_free(zt);
+      return rc;
+    }
+    dst = dt;
+  }
+  mg::StepArgs sa{};
+  sa.z = zsrc;
+  sa.n_cols = c->nc;
+  sa.q = c->qf;
+  sa.offs = c->offs;
+  sa.perm = nullptr;
+  sa.count = c->n_pos;
+  sa.d_out = dst;
+  hipError_t e = mg::launch_step(c->m, mg::MODE_FORWARD, sa, c->stream);
+  if (e == hipSuccess && !out_on_device)
+    e = hipMemcpyAsync(d_out, dt, nd * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(zt);
+  dev_free(dt);
+  if (e != hipSuccess) return fail(MAGPIE_ERR_HIP, std::string("forward model: ") + hipGetErrorString(e));
+  return MAGPIE_OK;
+}
+
+int magpie_set_timing(magpie_ctx* c, int enable) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  c->timing = enable != 0;
+  return MAGPIE_OK;
+}
+
+int magpie_get_timing(magpie_ctx* c, double* step_ms, double* accum_ms, int64_t* step_launches,
+                      int64_t* accum_launches, int64_t* positions) {
+  if (!c || !step_ms || !accum_ms || !step_launches || !accum_launches || !positions)
+    return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  MG_HIP(hipStreamSynchronize(c->stream));
+  double ms[2] = {0.0, 0.0};
+  int64_t nl[2] = {0, 0}, pos = 0;
+  for (auto& t : c->timed) {
+    float f = 0.0f;
+    MG_HIP(hipEventElapsedTime(&f, t.a, t.b));
+    ms[t.kind] += f;
+    nl[t.kind] += 1;
+    if (t.kind == 0) pos += t.count;
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->timed.clear();
+  *step_ms = ms[0];
+  *accum_ms = ms[1];
+  *step_launches = nl[0];
+  *accum_launches = nl[1];
+  *positions = pos;
+  return MAGPIE_OK;
+}
+
+int magpie_permutation(uint64_t seed, uint64_t epoch, int n, int32_t* out) {
+  if (!out || n < 1) return fail(MAGPIE_ERR_INVALID_ARG, "n >= 1 and out required");
+  fisher_yates(seed, epoch, n, out);
+  return MAGPIE_OK;
+}
+
+int magpie_get_epoch_index(magpie_ctx* c, uint64_t* epoch_index) {
+  if (!c || !epoch_index) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  *epoch_index = c->epoch_index;
+  return MAGPIE_OK;
+}
+
+int magpie_set_epoch_index(magpie_ctx* c, uint64_t epoch_index) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  c->epoch_index = epoch_index;
+  return MAGPIE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Complex helpers and register-resident small DFTs for gfx950 kernels.
+//
+// Complex values are float2 (re, im).  dft<R, DIR> transforms R values held
+// in registers of one thread, natural order in and out:
+//     v[k] <- sum_j v[j] exp(-DIR * 2 pi i j k / R),   DIR = +1 forward, -1 inverse
+// (unnormalised, the sign convention of the 2-D DFT in Section 2.1 of
+// arXiv 2504.10118; the inverse uses the conjugate kernel, Appendix A).
+// R is a power of two up to 16; the recursion is radix-2 decimation in time
+// with compile-time twiddles, fully unrolled so that the reordering costs
+// nothing but register renaming.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mg {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// a * exp(-DIR * i pi / 2): forward multiplies by -i, inverse by +i.
+template <int DIR>
+__device__ __forceinline__ float2 mul_quarter(float2 a) {
+  return DIR > 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// a * exp(-DIR * 2 pi i j / 16) for a compile-time j in [0, 8).
+template <int J, int DIR>
+__device__ __forceinline__ float2 mul_w16(float2 a) {
+  constexpr float C1 = 0.92387953251128675613f;   // cos(pi/8)
+  constexpr float S1 = 0.38268343236508977173f;   // sin(pi/8)
+  constexpr float H = 0.70710678118654752440f;    // cos(pi/4)
+  constexpr float s = DIR > 0 ? -1.0f : 1.0f;     // sign of the sine part
+  if constexpr (J == 0) {
+    return a;
+  } else if constexpr (J == 4) {
+    return mul_quarter<DIR>(a);
+  } else if constexpr (J == 2) {
+    // (c + i s c) with c = H
+    return make_float2(H * (a.x - s * a.y), H * (a.y + s * a.x));
+  } else if constexpr (J == 6) {
+    // (-c + i s c)
+    return make_float2(H * (-a.x - s * a.y), H * (-a.y + s * a.x));
+  } else {
+    constexpr float c = (J == 1) ? C1 : (J == 3) ? S1 : (J == 5) ? -S1 : -C1;
+    constexpr float sn = (J == 1) ? S1 : (J == 3) ? C1 : (J == 5) ? C1 : S1;
+    // a * (c + i s sn)
+    return make_float2(a.x * c - a.y * (s * sn), a.x * (s * sn) + a.y * c);
+  }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    float2 t = v[0];
+    v[0] = cadd(t, v[1]);
+    v[1] = csub(t, v[1]);
+  } else if constexpr (R == 4) {
+    float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    float2 t2 = cadd(v[1], v[3]), t3 = mul_quarter<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  } else {
+    constexpr int H = R / 2;
+    float2 e[H], o[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    dft<H, DIR>(e);
+    dft<H, DIR>(o);
+    // twiddle W_R^k = W_16^(k * 16 / R)
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      float2 t;
+      constexpr int step = 16 / R;
+      switch (k * step) {
+        case 0: t = mul_w16<0, DIR>(o[k]); break;
+        case 1: t = mul_w16<1, DIR>(o[k]); break;
+        case 2: t = mul_w16<2, DIR>(o[k]); break;
+        case 3: t = mul_w16<3, DIR>(o[k]); break;
+        case 4: t = mul_w16<4, DIR>(o[k]); break;
+        case 5: t = mul_w16<5, DIR>(o[k]); break;
+        case 6: t = mul_w16<6, DIR>(o[k]); break;
+        default: t = mul_w16<7, DIR>(o[k]); break;
+      }
+      v[k] = cadd(e[k], t);
+      v[k + H] = csub(e[k], t);
+    }
+  }
+}
+
+}  // namespace mg

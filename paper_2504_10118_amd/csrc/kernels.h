@@ -1,0 +1,67 @@
+// Launch wrappers of the gfx950 kernels (plain C++ signatures, no HIP types
+// beyond the stream) used by the host runtime in capi.cpp.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mg {
+
+enum StepMode { MODE_STEP = 0, MODE_OBJECTIVE = 1, MODE_FORWARD = 2 };
+
+// Arguments of the per-position kernel (one workgroup per scan position).
+struct StepArgs {
+  const float2* z;        // object [n_rows][n_cols]
+  int n_cols;
+  const float2* q;        // probe FP32 [m][m]
+  const float* sqrtd;     // sqrt(d) in kernel order [N][m*m]
+  const int2* offs;       // (row, col) per position [N]
+  const int* perm;        // positions handled, one per workgroup; NULL = identity
+  int count;              // number of workgroups / positions
+  float2* stage;          // MODE_STEP: c_k = w0 * dz_k, natural order [count][m][m]
+  const float* u0f;       // fine-grid u [m][m]
+  const double* lvl;      // coarse-level constants (V, rho, r per level)
+  int levels;             // number of grids L
+  double* phi_k;          // per-position Phi_k, indexed by position (nullable)
+  double* gnorm_k;        // MODE_OBJECTIVE: ||grad_k||_2 per position
+  float* d_out;           // MODE_FORWARD: |F(Q z_k)|^2 natural order [N][m][m]
+  float2* probe_num;      // probe update numerator partials [count][m][m] (nullable)
+  float* probe_den;       // probe update denominator partials [count][m][m]
+};
+
+struct AccumArgs {
+  float2* z;              // object, updated in place
+  int n_rows, n_cols, m;
+  int tiles_x;            // number of 64-wide tile columns
+  const int* tile_ptr;    // CSR over tiles: positions overlapping each tile, ascending
+  const int* tile_pos;
+  const int* inv;         // position -> index in this epoch's permutation
+  int batch_index, batch; // minibatch t and size B
+  const float2* stage;    // [B][m][m]
+  const int2* offs;
+  const double* w0;       // u + |Q|^2 [m][m]
+};
+
+constexpr int ACC_TILE_W = 64;
+constexpr int ACC_TILE_H = 16;
+constexpr int ACC_THREADS = 256;
+
+int step_threads(int m);                 // workgroup size of the per-position kernel
+size_t step_lds_bytes(int m);            // dynamic LDS of the per-position kernel
+
+hipError_t init_twiddles(hipStream_t s);
+hipError_t launch_step(int m, int mode, const StepArgs& a, hipStream_t s);
+hipError_t launch_accumulate(const AccumArgs& a, int n_tiles, hipStream_t s);
+hipError_t launch_level_constants(int m, int levels, double alpha, int u_given,
+                                  const double2* q64, double* u0, double* w0, float* u0f,
+                                  float2* qf, double* lvl, double2* scr_q, double* scr_u,
+                                  hipStream_t s);
+hipError_t launch_permute_sqrt(int m, int n_pos, const float* src, int is_sqrt, float* dst,
+                               int* bad_flag, hipStream_t s);
+hipError_t launch_reduce_sum(const double* x, int n, double* out, hipStream_t s);
+hipError_t launch_convert_c64_c128(const float2* src, double2* dst, size_t n, hipStream_t s);
+hipError_t launch_convert_c128_c64(const double2* src, float2* dst, size_t n, hipStream_t s);
+hipError_t launch_check_finite_c64(const float2* src, size_t n, int* bad_flag, hipStream_t s);
+hipError_t launch_probe_apply(int m, int count, const float2* num, const float* den,
+                              double beta_unused, float2* q, hipStream_t s);
+
+}  // namespace mg

@@ -1,0 +1,254 @@
+"""ctypes binding of libmagpie.so (C ABI declared in include/magpie.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+NumPy arrays are passed as host pointers; torch tensors that live on a GPU
+are passed as device pointers (``data_ptr()``), which the library reads in
+stream order on the context's stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libmagpie.so")
+
+MAGPIE_OK = 0
+ERRORS = {
+    -1: "INVALID_ARG", -2: "BAD_STATE", -3: "OOM", -4: "HIP", -5: "NUMERIC", -6: "UNSUPPORTED",
+}
+C64, C128 = 0, 1
+UPDATE_PROBE = 0x1
+
+_lib = None
+
+
+class MagpieError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+def _bind(lib):
+    vp, i, d, u32, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "magpie_last_error": (ctypes.c_char_p, []),
+        "magpie_create": (i, [ctypes.POINTER(vp), i, i, i, i, d, i, vp]),
+        "magpie_destroy": (i, [vp]),
+        "magpie_set_probe": (i, [vp, vp, i, i]),
+        "magpie_set_regularization": (i, [vp, d, vp]),
+        "magpie_set_positions": (i, [vp, i, vp]),
+        "magpie_load_intensities": (i, [vp, vp, i, i]),
+        "magpie_set_object": (i, [vp, vp, i, i]),
+        "magpie_run_epochs": (i, [vp, i, i, u64, vp]),
+        "magpie_objective": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(d)]),
+        "magpie_get_step_phi": (i, [vp, vp]),
+        "magpie_get_object": (i, [vp, vp, i, i]),
+        "magpie_get_probe": (i, [vp, vp, i, i]),
+        "magpie_sync": (i, [vp]),
+        "magpie_set_flags": (i, [vp, u32, d]),
+        "magpie_forward_model": (i, [vp, vp, i, vp, i]),
+        "magpie_permutation": (i, [u64, u64, i, vp]),
+        "magpie_get_epoch_index": (i, [vp, ctypes.POINTER(u64)]),
+        "magpie_set_epoch_index": (i, [vp, u64]),
+        "magpie_set_timing": (i, [vp, i]),
+        "magpie_get_timing": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def load_library(path: str | None = None):
+    """Load the built HIP library; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libmagpie.so not built at {p}; run `python -m paper_2504_10118_amd.build`")
+    lib = _bind(ctypes.CDLL(p))
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != MAGPIE_OK:
+        raise MagpieError(rc, _lib.magpie_last_error().decode())
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype, shape=None):
+    """(pointer, on_device, keepalive) for a numpy array or torch tensor."""
+    if _is_torch(x):
+        import torch
+        tdt = {np.complex64: torch.complex64, np.complex128: torch.complex128,
+               np.float32: torch.float32, np.float64: torch.float64, np.int32: torch.int32}[dtype]
+        if x.is_cuda:
+            if x.dtype != tdt or not x.is_contiguous():
+                raise ValueError(f"device tensor must be contiguous {tdt}")
+            if shape is not None and tuple(x.shape) != tuple(shape):
+                raise ValueError(f"expected shape {shape}, got {tuple(x.shape)}")
+            return ctypes.c_void_p(x.data_ptr()), 1, x
+        x = x.detach().numpy()
+    a = np.ascontiguousarray(x, dtype=dtype)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a.ctypes.data_as(ctypes.c_void_p), 0, a
+
+
+def permutation(seed: int, epoch: int, n: int) -> np.ndarray:
+    """The library's splitmix64 Fisher-Yates permutation for (seed, epoch)."""
+    lib = load_library()
+    out = np.empty(n, dtype=np.int32)
+    _check(lib.magpie_permutation(seed, epoch, n, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+class Magpie:
+    """One reconstruction context (object n_rows x n_cols, probe m x m, L grids)."""
+
+    def __init__(self, n_rows: int, n_cols: int, m: int, levels: int, alpha: float,
+                 device: int = 0, stream=None):
+        self.lib = load_library()
+        self.n_rows, self.n_cols, self.m, self.levels = n_rows, n_cols, m, levels
+        self.n_pos = 0
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        _check(self.lib.magpie_create(ctypes.byref(h), n_rows, n_cols, m, levels, float(alpha), device, st))
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.magpie_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- inputs
+    def set_probe(self, probe):
+        dt = np.complex128 if getattr(probe, "dtype", None) in (np.complex128, "complex128") or \
+            str(getattr(probe, "dtype", "")) == "torch.complex128" else np.complex64
+        p, dev, keep = _ptr(probe, dt, (self.m, self.m))
+        _check(self.lib.magpie_set_probe(self._h, p, C128 if dt is np.complex128 else C64, dev))
+
+    def set_regularization(self, alpha: float = 0.0, u=None):
+        if u is None:
+            _check(self.lib.magpie_set_regularization(self._h, float(alpha), None))
+        else:
+            a = np.ascontiguousarray(u, dtype=np.float64).reshape(self.m, self.m)
+            _check(self.lib.magpie_set_regularization(self._h, float(alpha), a.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_positions(self, offsets):
+        a = np.ascontiguousarray(offsets, dtype=np.int32)
+        if a.ndim != 2 or a.shape[1] != 2:
+            raise ValueError("offsets must be [N, 2]")
+        _check(self.lib.magpie_set_positions(self._h, a.shape[0], a.ctypes.data_as(ctypes.c_void_p)))
+        self.n_pos = a.shape[0]
+
+    def load_intensities(self, d, is_sqrt: bool = False):
+        p, dev, keep = _ptr(d, np.float32, (self.n_pos, self.m, self.m))
+        _check(self.lib.magpie_load_intensities(self._h, p, int(bool(is_sqrt)), dev))
+        self._keep_d = keep if dev else None
+
+    def set_object(self, z):
+        dt = np.complex128 if str(getattr(z, "dtype", "")) in ("complex128", "torch.complex128") else np.complex64
+        p, dev, keep = _ptr(z, dt, (self.n_rows, self.n_cols))
+        _check(self.lib.magpie_set_object(self._h, p, C128 if dt is np.complex128 else C64, dev))
+        self._keep_z = keep if dev else None
+
+    def set_flags(self, flags: int, beta: float = 0.0):
+        _check(self.lib.magpie_set_flags(self._h, flags, float(beta)))
+
+    # -- solver
+    def run_epochs(self, n_epochs: int, batch: int, seed: int = 0, order=None):
+        if order is None:
+            _check(self.lib.magpie_run_epochs(self._h, n_epochs, batch, seed, None))
+        else:
+            o = np.ascontiguousarray(order, dtype=np.int32).reshape(n_epochs, self.n_pos)
+            _check(self.lib.magpie_run_epochs(self._h, n_epochs, batch, seed, o.ctypes.data_as(ctypes.c_void_p)))
+
+    def objective(self):
+        phi, st = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.magpie_objective(self._h, ctypes.byref(phi), ctypes.byref(st)))
+        return phi.value, st.value
+
+    def step_phi(self):
+        out = np.empty(self.n_pos, dtype=np.float64)
+        _check(self.lib.magpie_get_step_phi(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def sync(self):
+        _check(self.lib.magpie_sync(self._h))
+
+    @property
+    def epoch_index(self) -> int:
+        v = ctypes.c_uint64()
+        _check(self.lib.magpie_get_epoch_index(self._h, ctypes.byref(v)))
+        return v.value
+
+    @epoch_index.setter
+    def epoch_index(self, value: int):
+        _check(self.lib.magpie_set_epoch_index(self._h, int(value)))
+
+    def set_timing(self, enable: bool = True):
+        _check(self.lib.magpie_set_timing(self._h, int(bool(enable))))
+
+    def get_timing(self) -> dict:
+        """Summed HIP-event times of the kernels launched since the last read (ms)."""
+        sm, am = ctypes.c_double(), ctypes.c_double()
+        sl, al, pos = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(self.lib.magpie_get_timing(self._h, ctypes.byref(sm), ctypes.byref(am), ctypes.byref(sl),
+                                          ctypes.byref(al), ctypes.byref(pos)))
+        return {"step_ms": sm.value, "accum_ms": am.value, "step_launches": sl.value,
+                "accum_launches": al.value, "positions": pos.value}
+
+    # -- outputs
+    def get_object(self, out=None, dtype=np.complex64):
+        if out is None:
+            out = np.empty((self.n_rows, self.n_cols), dtype=dtype)
+        dt = np.complex128 if str(out.dtype) in ("complex128", "torch.complex128") else np.complex64
+        if _is_torch(out) and out.is_cuda:
+            _check(self.lib.magpie_get_object(self._h, ctypes.c_void_p(out.data_ptr()),
+                                              C128 if dt is np.complex128 else C64, 1))
+            return out
+        _check(self.lib.magpie_get_object(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                          C128 if dt is np.complex128 else C64, 0))
+        return out
+
+    def get_probe(self, dtype=np.complex64):
+        out = np.empty((self.m, self.m), dtype=dtype)
+        _check(self.lib.magpie_get_probe(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                         C128 if dtype is np.complex128 else C64, 0))
+        return out
+
+    def forward_model(self, z, out=None):
+        p, dev, keep = _ptr(z, np.complex64, (self.n_rows, self.n_cols))
+        if out is not None and _is_torch(out) and out.is_cuda:
+            _check(self.lib.magpie_forward_model(self._h, p, dev, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        res = np.empty((self.n_pos, self.m, self.m), dtype=np.float32)
+        _check(self.lib.magpie_forward_model(self._h, p, dev, res.ctypes.data_as(ctypes.c_void_p), 0))
+        return res
