@@ -7,15 +7,20 @@ A step is one epoch of minibatch MAGPIE over the workload's synthetic scan
 minibatch the fixed-order accumulation and object update.  Inputs are
 resident in HBM before the timed region starts.
 
-Prints one JSON line.  ``roofline`` covers the per-position step kernel (the
-dominant kernel) from HIP events recorded around each of its launches inside
-the timed region; ``cpu_baseline`` times the FP64 oracle on a bounded sample
-of the same workload on the host cores.
+Prints one JSON line.  ``value`` is from the timed region, which runs the
+production path.  ``roofline`` covers the per-position step kernel (the
+dominant kernel): the same epochs are run a second time with HIP events
+recorded by each launch's own dispatch on the context's stream, and the
+algorithmic bytes per launch are divided by the mean event duration.
+``cpu_baseline`` times the FP64 oracle on a bounded sample of the same
+workload on the host cores.
 """
 
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import platform
@@ -25,6 +30,43 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash() -> str:
+    """sha256 (16 hex digits) over the HIP/C++ sources of the library."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2504_10118_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(f, "rb") as fh:
+                h.update(os.path.basename(f).encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(cfg_id: int, m: int):
+    """Counter-measured HBM bytes per full launch of the step kernel, from the
+    committed rocprofv3 summary, if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"step_kernel_m{m}_cfg{cfg_id}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith(("source_sha256", "traffic_bytes_per_launch",
+                                                         "traffic_fetch_bytes", "traffic_write_bytes",
+                                                         "patterns_per_launch")):
+                k, v = line.strip().split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return {"bytes_per_full_launch": float(vals["traffic_bytes_per_launch"]),
+                "fetch": float(vals["traffic_fetch_bytes"]), "write": float(vals["traffic_write_bytes"]),
+                "patterns_per_launch": int(vals["patterns_per_launch"]), "summary": os.path.basename(path)}
+    except (KeyError, ValueError):
+        return None
 
 
 def workload_inputs(cfg_id: int):
@@ -87,6 +129,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2504)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -102,6 +146,14 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
+
+    if args.copy_calibration_mb:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cfg, z_true, Q32, offs, r_noise = workload_inputs(args.config)
     batch = args.batch or cfg.batch
@@ -119,19 +171,28 @@ def main():
     if args.warmup:
         ctx.run_epochs(args.warmup, batch, seed=args.seed + 1)
     ctx.sync()
+    # timed region: the production path (no per-kernel events)
     ctx.set_object(np.ones((cfg.n, cfg.n), dtype=np.complex64))
     ctx.epoch_index = 0
-    ctx.set_timing(True)
-    ctx.get_timing()                                         # reset
-
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.run_epochs(args.steps, batch, seed=args.seed)
     ctx.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tm = ctx.get_timing()
     phi, stat = ctx.objective()
+
+    # kernel timing: the same epochs again, every launch bracketed by HIP events
+    # that its own dispatch records on the context's stream
+    ctx.set_object(np.ones((cfg.n, cfg.n), dtype=np.complex64))
+    ctx.epoch_index = 0
+    ctx.set_timing(True)
+    ctx.get_timing()                                         # reset
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.run_epochs(args.steps, batch, seed=args.seed)
+    tm = ctx.get_timing()                                    # synchronises
+    t3 = time.perf_counter()
     ctx.close()
 
     wall = t1 - t0
@@ -141,6 +202,7 @@ def main():
     step_s = tm["step_ms"] * 1e-3
     achieved = tm["positions"] * bytes_per_pattern / step_s / 1e9 if step_s > 0 else None
     n_tiles = ((cfg.n + 63) // 64) * ((cfg.n + 15) // 16)
+    traffic = stored_traffic(args.config, m) if batch == cfg.batch and levels == cfg.levels else None
     out = {
         "metric": "diffraction patterns/s (fused step)",
         "value": value,
@@ -166,7 +228,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
+            "traffic": None if traffic is None else traffic["bytes_per_full_launch"],
+            "traffic_detail": traffic,
+            "algorithmic_bytes_per_full_launch": bytes_per_pattern * min(batch, N),
             "bytes_per_pattern": bytes_per_pattern,
             "avg_launch_us": tm["step_ms"] * 1e3 / max(1, tm["step_launches"]),
             "launches": tm["step_launches"],
@@ -175,9 +239,11 @@ def main():
             "avg_launch_us": tm["accum_ms"] * 1e3 / max(1, tm["accum_launches"]),
             "launches": tm["accum_launches"], "tiles_per_launch": n_tiles,
         },
-        "kernel_share": {
-            "step": step_s / wall,
-            "accumulate": tm["accum_ms"] * 1e-3 / wall,
+        "event_pass": {
+            "note": "second pass over the same epochs with per-launch HIP events (slower: events serialise dispatch)",
+            "ms_per_step": (t3 - t2) * 1e3 / args.steps,
+            "step_share": step_s / (t3 - t2),
+            "accumulate_share": tm["accum_ms"] * 1e-3 / (t3 - t2),
         },
         "objective_after": phi,
         "stopping_statistic_after": stat,

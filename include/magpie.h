@@ -57,6 +57,8 @@ extern "C" {
 
 /* flags for magpie_set_flags */
 #define MAGPIE_UPDATE_PROBE 0x1u  /* also update the probe each minibatch (beyond the paper) */
+#define MAGPIE_GRAPH        0x2u  /* replay a captured per-epoch hipGraph instead of
+                                     launching each kernel directly (same results) */
 
 typedef struct magpie_ctx magpie_ctx;
 
@@ -161,7 +163,10 @@ int magpie_get_probe(magpie_ctx* ctx, void* out, int dtype, int on_device);
 /* Wait for all work enqueued on the context's stream. */
 int magpie_sync(magpie_ctx* ctx);
 
-/* Set behaviour flags (MAGPIE_UPDATE_PROBE).  beta: probe-step proximal weight. */
+/* Set behaviour flags (MAGPIE_UPDATE_PROBE, MAGPIE_GRAPH).  beta: probe-step
+ * proximal weight.  With MAGPIE_GRAPH (and timing off) an epoch is one replay
+ * of a hipGraph captured on first use for the current minibatch size; the
+ * graph reads the epoch's permutation through a device counter. */
 int magpie_set_flags(magpie_ctx* ctx, uint32_t flags, double beta);
 
 /*

@@ -9,6 +9,7 @@ from .magpie import (  # noqa: F401
     C64,
     C128,
     UPDATE_PROBE,
+    GRAPH,
     LIB_PATH,
     Magpie,
     MagpieError,

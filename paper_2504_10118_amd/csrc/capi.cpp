@@ -92,6 +92,7 @@ struct magpie_ctx {
   double2* q64 = nullptr;
   double* u0 = nullptr;
   double* w0 = nullptr;
+  float* w0f = nullptr;
   float* u0f = nullptr;
   double* lvl = nullptr;
   double2* scr_q = nullptr;
@@ -101,17 +102,22 @@ struct magpie_ctx {
 
   int2* offs = nullptr;
   float* sqrtd = nullptr;
-  double* phi_step = nullptr;
+  double* phi_step = nullptr;   // per position, reduced on demand
   double* phi_obj = nullptr;
   double* gnorm = nullptr;
+  double* step_part = nullptr;  // per-wave partials [N][MAX_WAVES]
+  double* obj_part = nullptr;
+  double* gn_part = nullptr;
+  int lvl_a_off = 0;
   int* tile_ptr = nullptr;
-  int* tile_pos = nullptr;
+  int4* tile_ent = nullptr;
   int tiles_x = 0, tiles_y = 0;
   std::vector<int32_t> h_offs;
 
   float2* stage = nullptr;
   size_t stage_cap = 0;  // in float2
   int* perm = nullptr;   // [E][N]
+  int4* posrec = nullptr;  // [E][N] (k, row, col, 0) in processing order
   int* inv = nullptr;    // [E][N]
   size_t perm_cap = 0;   // ints per array
   int32_t* h_pin = nullptr;
@@ -128,6 +134,13 @@ struct magpie_ctx {
   };
   std::vector<hipEvent_t> ev_pool;
   std::vector<Timed> timed;
+
+  // captured epoch graph (replayed once per epoch); the epoch index is read
+  // by the kernels from epoch_ctr, which the graph's last node advances
+  hipGraphExec_t gexec = nullptr;
+  int g_batch = 0;
+  const void* g_key[3] = {nullptr, nullptr, nullptr};  // perm, inv, stage buffers it was built on
+  int* epoch_ctr = nullptr;
 };
 
 namespace {
@@ -137,14 +150,24 @@ int set_dev(magpie_ctx* c) {
   return MAGPIE_OK;
 }
 
+void drop_graph(magpie_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->g_batch = 0;
+}
+
 int free_positions(magpie_ctx* c) {
+  drop_graph(c);
   dev_free(c->offs);
   dev_free(c->sqrtd);
   dev_free(c->phi_step);
   dev_free(c->phi_obj);
   dev_free(c->gnorm);
+  dev_free(c->step_part);
+  dev_free(c->obj_part);
+  dev_free(c->gn_part);
   dev_free(c->tile_ptr);
-  dev_free(c->tile_pos);
+  dev_free(c->tile_ent);
   c->has_pos = false;
   c->has_data = false;
   c->n_pos = 0;
@@ -152,7 +175,7 @@ int free_positions(magpie_ctx* c) {
 }
 
 int rebuild_levels(magpie_ctx* c) {
-  MG_HIP(mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->u0f,
+  MG_HIP(mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->w0f, c->u0f,
                                     c->qf, c->lvl, c->scr_q, c->scr_u, c->stream));
   return MAGPIE_OK;
 }
@@ -168,17 +191,14 @@ hipEvent_t take_event(magpie_ctx* c) {
   return e;
 }
 
-// Record the start event of a timed launch; returns index into c->timed or -1.
-int timed_begin(magpie_ctx* c, int kind, int count) {
+// Events for a timed launch (recorded by the dispatch itself at kernel start
+// and end); returns the index into c->timed or -1 when timing is off.
+int timed_slot(magpie_ctx* c, int kind, int count) {
   if (!c->timing) return -1;
   magpie_ctx::Timed t{take_event(c), take_event(c), kind, count};
-  if (!t.a || !t.b || hipEventRecord(t.a, c->stream) != hipSuccess) return -1;
+  if (!t.a || !t.b) return -1;
   c->timed.push_back(t);
   return (int)c->timed.size() - 1;
-}
-
-void timed_end(magpie_ctx* c, int idx) {
-  if (idx >= 0) hipEventRecord(c->timed[idx].b, c->stream);
 }
 
 int read_flag(magpie_ctx* c, int* out) {
@@ -230,17 +250,22 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   const size_t half = (size_t)(m / 2) * (m / 2);
   size_t nlvl = 0;
   for (int l = 1; l < n_levels; ++l) nlvl += 3 * (size_t)(m >> l) * (m >> l);
+  c->lvl_a_off = (int)nlvl;
+  nlvl += (size_t)(n_levels - 1) * half;   // A_l coefficients per level-1 bin
+  for (int l = 1; l <= n_levels - 2; ++l) nlvl += (size_t)(m >> l) * (m >> l);  // copies of V_l
   rc = dev_alloc(&c->z, (size_t)n_rows * n_cols);
   if (!rc) rc = dev_alloc(&c->qf, mm);
   if (!rc) rc = dev_alloc(&c->q64, mm);
   if (!rc) rc = dev_alloc(&c->u0, mm);
   if (!rc) rc = dev_alloc(&c->w0, mm);
+  if (!rc) rc = dev_alloc(&c->w0f, mm);
   if (!rc) rc = dev_alloc(&c->u0f, mm);
   if (!rc) rc = dev_alloc(&c->lvl, std::max<size_t>(nlvl, 1));
   if (!rc) rc = dev_alloc(&c->scr_q, 2 * half);
   if (!rc) rc = dev_alloc(&c->scr_u, 2 * half);
   if (!rc) rc = dev_alloc(&c->flag, 1);
   if (!rc) rc = dev_alloc(&c->red, 4);
+  if (!rc) rc = dev_alloc(&c->epoch_ctr, 1);
   if (!rc && hipEventCreateWithFlags(&c->pin_done, hipEventDisableTiming) != hipSuccess)
     rc = fail(MAGPIE_ERR_HIP, "hipEventCreate failed");
   if (rc) {
@@ -273,14 +298,17 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->q64);
   dev_free(c->u0);
   dev_free(c->w0);
+  dev_free(c->w0f);
   dev_free(c->u0f);
   dev_free(c->lvl);
   dev_free(c->scr_q);
   dev_free(c->scr_u);
   dev_free(c->flag);
   dev_free(c->red);
+  dev_free(c->epoch_ctr);
   dev_free(c->stage);
   dev_free(c->perm);
+  dev_free(c->posrec);
   dev_free(c->inv);
   if (c->h_pin) hipHostFree(c->h_pin);
   if (c->pin_done) hipEventDestroy(c->pin_done);
@@ -375,18 +403,22 @@ int magpie_set_positions(magpie_ctx* c, int n_pos, const int32_t* offsets) {
       for (int tx = cc / mg::ACC_TILE_W; tx <= (cc + m - 1) / mg::ACC_TILE_W; ++tx)
         lists[ty * c->tiles_x + tx].push_back(k);
   }
-  std::vector<int> ptr(nt + 1, 0), pos;
+  std::vector<int> ptr(nt + 1, 0);
+  std::vector<int4> pos;
   for (int t = 0; t < nt; ++t) {
     ptr[t + 1] = ptr[t] + (int)lists[t].size();
-    pos.insert(pos.end(), lists[t].begin(), lists[t].end());
+    for (int k : lists[t]) pos.push_back(make_int4(k, offsets[2 * k], offsets[2 * k + 1], 0));
   }
   rc = dev_alloc(&c->offs, n_pos);
   if (!rc) rc = dev_alloc(&c->sqrtd, (size_t)n_pos * m * m);
   if (!rc) rc = dev_alloc(&c->phi_step, n_pos);
   if (!rc) rc = dev_alloc(&c->phi_obj, n_pos);
   if (!rc) rc = dev_alloc(&c->gnorm, n_pos);
+  if (!rc) rc = dev_alloc(&c->step_part, (size_t)n_pos * mg::MAX_WAVES);
+  if (!rc) rc = dev_alloc(&c->obj_part, (size_t)n_pos * mg::MAX_WAVES);
+  if (!rc) rc = dev_alloc(&c->gn_part, (size_t)n_pos * mg::MAX_WAVES);
   if (!rc) rc = dev_alloc(&c->tile_ptr, nt + 1);
-  if (!rc) rc = dev_alloc(&c->tile_pos, std::max<size_t>(pos.size(), 1));
+  if (!rc) rc = dev_alloc(&c->tile_ent, std::max<size_t>(pos.size(), 1));
   if (rc) {
     free_positions(c);
     return rc;
@@ -394,9 +426,9 @@ int magpie_set_positions(magpie_ctx* c, int n_pos, const int32_t* offsets) {
   MG_HIP(hipMemcpyAsync(c->offs, offsets, (size_t)n_pos * sizeof(int2), hipMemcpyHostToDevice, c->stream));
   MG_HIP(hipMemcpyAsync(c->tile_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
   if (!pos.empty())
-    MG_HIP(hipMemcpyAsync(c->tile_pos, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-  std::vector<double> nan(n_pos, std::nan(""));
-  MG_HIP(hipMemcpyAsync(c->phi_step, nan.data(), n_pos * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    MG_HIP(hipMemcpyAsync(c->tile_ent, pos.data(), pos.size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+  std::vector<double> nan((size_t)n_pos * mg::MAX_WAVES, std::nan(""));
+  MG_HIP(hipMemcpyAsync(c->step_part, nan.data(), nan.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   MG_HIP(hipStreamSynchronize(c->stream));
   c->h_offs.assign(offsets, offsets + 2 * (size_t)n_pos);
   c->n_pos = n_pos;
@@ -495,11 +527,15 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   if (nperm > c->perm_cap) {
     MG_HIP(hipStreamSynchronize(c->stream));
     dev_free(c->perm);
+    dev_free(c->posrec);
     dev_free(c->inv);
     rc = dev_alloc(&c->perm, nperm);
     if (!rc) rc = dev_alloc(&c->inv, nperm);
+    if (!rc) rc = dev_alloc(&c->posrec, nperm);
     if (rc) {
       dev_free(c->perm);
+      dev_free(c->inv);
+      dev_free(c->posrec);
       c->perm_cap = 0;
       return rc;
     }
@@ -509,18 +545,19 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
     MG_HIP(hipEventSynchronize(c->pin_done));
     c->pin_pending = false;
   }
-  if (2 * nperm > c->h_pin_cap) {
+  if (6 * nperm > c->h_pin_cap) {   // perm, inv, then 4 ints per position record
     if (c->h_pin) hipHostFree(c->h_pin);
     c->h_pin = nullptr;
     c->h_pin_cap = 0;
-    if (hipHostMalloc((void**)&c->h_pin, 2 * nperm * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->h_pin, 6 * nperm * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
       c->h_pin = nullptr;
       return fail(MAGPIE_ERR_OOM, "pinned host allocation failed");
     }
-    c->h_pin_cap = 2 * nperm;
+    c->h_pin_cap = 6 * nperm;
   }
   int32_t* hp = c->h_pin;
   int32_t* hi = c->h_pin + nperm;
+  int32_t* hr = c->h_pin + 2 * nperm;
   for (int e = 0; e < n_epochs; ++e) {
     int32_t* p = hp + (size_t)e * N;
     int32_t* q = hi + (size_t)e * N;
@@ -530,20 +567,27 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
       fisher_yates(seed, c->epoch_index + (uint64_t)e, N, p);
     }
     for (int i = 0; i < N; ++i) q[i] = -1;
+    int32_t* r = hr + (size_t)e * N * 4;
     for (int i = 0; i < N; ++i) {
       const int k = p[i];
       if (k < 0 || k >= N || q[k] != -1)
         return fail(MAGPIE_ERR_INVALID_ARG, "order row " + std::to_string(e) + " is not a permutation");
       q[k] = i;
+      r[4 * i] = k;
+      r[4 * i + 1] = c->h_offs[2 * (size_t)k];
+      r[4 * i + 2] = c->h_offs[2 * (size_t)k + 1];
+      r[4 * i + 3] = 0;
     }
   }
   MG_HIP(hipMemcpyAsync(c->perm, hp, nperm * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   MG_HIP(hipMemcpyAsync(c->inv, hi, nperm * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipMemcpyAsync(c->posrec, hr, nperm * sizeof(int4), hipMemcpyHostToDevice, c->stream));
   MG_HIP(hipEventRecord(c->pin_done, c->stream));
   c->pin_pending = true;
 
   mg::StepArgs sa{};
   sa.z = c->z;
+  sa.n_rows = c->nr;
   sa.n_cols = c->nc;
   sa.q = c->qf;
   sa.sqrtd = c->sqrtd;
@@ -552,7 +596,8 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   sa.u0f = c->u0f;
   sa.lvl = c->lvl;
   sa.levels = c->L;
-  sa.phi_k = c->phi_step;
+  sa.lvl_a_off = c->lvl_a_off;
+  sa.phi_part = c->step_part;
   mg::AccumArgs aa{};
   aa.z = c->z;
   aa.n_rows = c->nr;
@@ -560,24 +605,65 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   aa.m = m;
   aa.tiles_x = c->tiles_x;
   aa.tile_ptr = c->tile_ptr;
-  aa.tile_pos = c->tile_pos;
+  aa.tile_ent = c->tile_ent;
   aa.batch = B;
   aa.stage = c->stage;
   aa.offs = c->offs;
-  aa.w0 = c->w0;
+  aa.w0f = c->w0f;
   const int n_tiles = c->tiles_x * c->tiles_y;
+  const bool use_graph = !c->timing && (c->flags & MAGPIE_GRAPH);
+  if (use_graph) {
+    const void* key[3] = {c->posrec, c->inv, c->stage};
+    if (!c->gexec || c->g_batch != B || std::memcmp(key, c->g_key, sizeof(key)) != 0) {
+      drop_graph(c);
+      hipGraph_t graph = nullptr;
+      MG_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+      hipError_t ce = hipSuccess;
+      sa.epoch = c->epoch_ctr;
+      sa.epoch_stride = N;
+      aa.epoch = c->epoch_ctr;
+      aa.epoch_stride = N;
+      aa.inv = c->inv;
+      for (int t = 0; t < nbatch && ce == hipSuccess; ++t) {
+        sa.pos = c->posrec + (size_t)t * B;
+        sa.count = std::min(B, N - t * B);
+        ce = mg::launch_step(m, mg::MODE_STEP, sa, c->stream);
+        aa.batch_index = t;
+        if (ce == hipSuccess) ce = mg::launch_accumulate(aa, n_tiles, c->stream);
+      }
+      if (ce == hipSuccess) ce = mg::launch_advance_counter(c->epoch_ctr, c->stream);
+      hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return fail(MAGPIE_ERR_HIP, std::string("epoch graph capture failed: ") +
+                                        hipGetErrorString(ce != hipSuccess ? ce : ee));
+      }
+      hipError_t ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(MAGPIE_ERR_HIP, std::string("epoch graph instantiate failed: ") + hipGetErrorString(ie));
+      }
+      c->g_batch = B;
+      std::memcpy(c->g_key, key, sizeof(key));
+    }
+    MG_HIP(mg::launch_set_counter(c->epoch_ctr, 0, c->stream));
+    for (int e = 0; e < n_epochs; ++e) MG_HIP(hipGraphLaunch(c->gexec, c->stream));
+    c->epoch_index += (uint64_t)n_epochs;
+    return MAGPIE_OK;
+  }
   for (int e = 0; e < n_epochs; ++e) {
     for (int t = 0; t < nbatch; ++t) {
-      sa.perm = c->perm + (size_t)e * N + (size_t)t * B;
+      sa.pos = c->posrec + (size_t)e * N + (size_t)t * B;
       sa.count = std::min(B, N - t * B);
-      int ti = timed_begin(c, 0, sa.count);
-      MG_HIP(mg::launch_step(m, mg::MODE_STEP, sa, c->stream));
-      timed_end(c, ti);
+      int ti = timed_slot(c, 0, sa.count);
+      MG_HIP(mg::launch_step(m, mg::MODE_STEP, sa, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
+                             ti >= 0 ? c->timed[ti].b : nullptr));
       aa.inv = c->inv + (size_t)e * N;
       aa.batch_index = t;
-      ti = timed_begin(c, 1, 0);
-      MG_HIP(mg::launch_accumulate(aa, n_tiles, c->stream));
-      timed_end(c, ti);
+      ti = timed_slot(c, 1, 0);
+      MG_HIP(mg::launch_accumulate(aa, n_tiles, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
+                                   ti >= 0 ? c->timed[ti].b : nullptr));
     }
   }
   c->epoch_index += (uint64_t)n_epochs;
@@ -592,6 +678,7 @@ int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {
   if (rc) return rc;
   mg::StepArgs sa{};
   sa.z = c->z;
+  sa.n_rows = c->nr;
   sa.n_cols = c->nc;
   sa.q = c->qf;
   sa.sqrtd = c->sqrtd;
@@ -601,11 +688,13 @@ int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {
   sa.u0f = c->u0f;
   sa.lvl = c->lvl;
   sa.levels = c->L;
-  sa.phi_k = c->phi_obj;
-  sa.gnorm_k = c->gnorm;
+  sa.lvl_a_off = c->lvl_a_off;
+  sa.phi_part = c->obj_part;
+  sa.gn_part = c->gn_part;
+  const int nw = mg::step_waves(c->m);
   MG_HIP(mg::launch_step(c->m, mg::MODE_OBJECTIVE, sa, c->stream));
-  MG_HIP(mg::launch_reduce_sum(c->phi_obj, c->n_pos, c->red, c->stream));
-  MG_HIP(mg::launch_reduce_sum(c->gnorm, c->n_pos, c->red + 1, c->stream));
+  MG_HIP(mg::launch_reduce_parts(c->obj_part, c->n_pos, nw, 0, c->phi_obj, c->red, c->stream));
+  MG_HIP(mg::launch_reduce_parts(c->gn_part, c->n_pos, nw, 1, c->gnorm, c->red + 1, c->stream));
   double h[2];
   MG_HIP(hipMemcpyAsync(h, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   MG_HIP(hipStreamSynchronize(c->stream));
@@ -620,6 +709,7 @@ int magpie_get_step_phi(magpie_ctx* c, double* phi_k) {
   if (!c->has_pos) return fail(MAGPIE_ERR_BAD_STATE, "no positions");
   int rc = set_dev(c);
   if (rc) return rc;
+  MG_HIP(mg::launch_reduce_parts(c->step_part, c->n_pos, mg::step_waves(c->m), 0, c->phi_step, nullptr, c->stream));
   MG_HIP(hipMemcpyAsync(phi_k, c->phi_step, (size_t)c->n_pos * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   MG_HIP(hipStreamSynchronize(c->stream));
   return MAGPIE_OK;
@@ -673,7 +763,7 @@ int magpie_sync(magpie_ctx* c) {
 
 int magpie_set_flags(magpie_ctx* c, uint32_t flags, double beta) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
-  if (flags & ~MAGPIE_UPDATE_PROBE) return fail(MAGPIE_ERR_INVALID_ARG, "unknown flag");
+  if (flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_GRAPH)) return fail(MAGPIE_ERR_INVALID_ARG, "unknown flag");
   if (flags & MAGPIE_UPDATE_PROBE) return fail(MAGPIE_ERR_UNSUPPORTED, "probe update is not available yet");
   if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(MAGPIE_ERR_INVALID_ARG, "beta must be finite, >= 0");
   c->flags = flags;
@@ -711,6 +801,7 @@ int magpie_forward_model(magpie_ctx* c, const void* z, int z_on_device, float* d
   }
   mg::StepArgs sa{};
   sa.z = zsrc;
+  sa.n_rows = c->nr;
   sa.n_cols = c->nc;
   sa.q = c->qf;
   sa.offs = c->offs;

@@ -102,3 +102,77 @@ __device__ __forceinline__ void dft(float2* v) {
 }
 
 }  // namespace mg
+
+namespace mg {
+
+// Value of the lane whose id differs from this lane's in bit MASK (a power of
+// two below 64).  Masks 1, 2 and 8 use DPP (quad_perm, row_ror:8), 4 and 16
+// ds_swizzle in bit-mask mode; 32 crosses the half-waves with ds_bpermute.
+template <int MASK>
+__device__ __forceinline__ int xor_lane(int v) {
+  static_assert(MASK > 0 && MASK < 64 && (MASK & (MASK - 1)) == 0, "power of two below 64");
+  if constexpr (MASK == 1) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  } else if constexpr (MASK == 2) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  } else if constexpr (MASK == 4) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x101F);                      // and 0x1f, xor 4
+  } else if constexpr (MASK == 8) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (MASK == 16) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x401F);                      // and 0x1f, xor 16
+  } else {
+    return __shfl_xor(v, MASK);
+  }
+}
+
+template <int MASK>
+__device__ __forceinline__ double xor_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = xor_lane<MASK>((int)(b & 0xffffffffll));
+  const int hi = xor_lane<MASK>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int MASK>
+__device__ __forceinline__ double2 xor_lane(double2 v) {
+  return make_double2(xor_lane<MASK>(v.x), xor_lane<MASK>(v.y));
+}
+
+// Runtime mask dispatch (the mask is uniform and comes from a small set).
+__device__ __forceinline__ double2 xor_lane_rt(double2 v, int mask) {
+  switch (mask) {
+    case 1: return xor_lane<1>(v);
+    case 2: return xor_lane<2>(v);
+    case 4: return xor_lane<4>(v);
+    case 8: return xor_lane<8>(v);
+    case 16: return xor_lane<16>(v);
+    default: return xor_lane<32>(v);
+  }
+}
+
+}  // namespace mg
+
+namespace mg {
+
+// Raw buffer access: a scalar 128-bit resource (base, size in bytes), a
+// 32-bit per-lane byte offset and a scalar byte offset.  Loads outside the
+// resource return zero and stores there are dropped.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kBufferFlags = 0x00020000;   // gfx9 descriptor word 3 (32-bit raw data)
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferFlags);
+}
+__device__ __forceinline__ float2 bload2(rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ float4 bload4(rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore2(rsrc_t r, float2 v, int voff, int soff) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+}  // namespace mg

@@ -8,21 +8,27 @@ namespace mg {
 
 enum StepMode { MODE_STEP = 0, MODE_OBJECTIVE = 1, MODE_FORWARD = 2 };
 
+constexpr int MAX_WAVES = 16;   // per-position partial sums (one per wave of a workgroup)
+
 // Arguments of the per-position kernel (one workgroup per scan position).
 struct StepArgs {
   const float2* z;        // object [n_rows][n_cols]
-  int n_cols;
+  int n_rows, n_cols;
   const float2* q;        // probe FP32 [m][m]
   const float* sqrtd;     // sqrt(d) in kernel order [N][m*m]
   const int2* offs;       // (row, col) per position [N]
-  const int* perm;        // positions handled, one per workgroup; NULL = identity
+  const int4* pos;        // MODE_STEP: (k, row, col, 0) of the positions handled, one per workgroup
+  const int* perm;        // other modes: positions handled; NULL = identity
+  const int* epoch;       // nullable: perm is advanced by (*epoch) * epoch_stride (graph replays)
+  int epoch_stride;
   int count;              // number of workgroups / positions
   float2* stage;          // MODE_STEP: c_k = w0 * dz_k, natural order [count][m][m]
   const float* u0f;       // fine-grid u [m][m]
-  const double* lvl;      // coarse-level constants (V, rho, r per level)
+  const double* lvl;      // coarse-level constants (V, rho, r per level), then A_l
+  int lvl_a_off;          // offset in lvl of the in-wave V-cycle block: A_1..A_{L-1}, then V_1..V_{L-2}
   int levels;             // number of grids L
-  double* phi_k;          // per-position Phi_k, indexed by position (nullable)
-  double* gnorm_k;        // MODE_OBJECTIVE: ||grad_k||_2 per position
+  double* phi_part;       // per-wave partials of Phi_k [N][MAX_WAVES] (nullable)
+  double* gn_part;        // MODE_OBJECTIVE: per-wave partials of ||grad_k||^2 [N][MAX_WAVES]
   float* d_out;           // MODE_FORWARD: |F(Q z_k)|^2 natural order [N][m][m]
   float2* probe_num;      // probe update numerator partials [count][m][m] (nullable)
   float* probe_den;       // probe update denominator partials [count][m][m]
@@ -33,12 +39,14 @@ struct AccumArgs {
   int n_rows, n_cols, m;
   int tiles_x;            // number of 64-wide tile columns
   const int* tile_ptr;    // CSR over tiles: positions overlapping each tile, ascending
-  const int* tile_pos;
+  const int4* tile_ent;   // (k, row, col, 0) of each overlapping position
   const int* inv;         // position -> index in this epoch's permutation
+  const int* epoch;       // nullable: inv is advanced by (*epoch) * epoch_stride (graph replays)
+  int epoch_stride;
   int batch_index, batch; // minibatch t and size B
   const float2* stage;    // [B][m][m]
   const int2* offs;
-  const double* w0;       // u + |Q|^2 [m][m]
+  const float* w0f;       // u + |Q|^2 [m][m], FP32 copy
 };
 
 constexpr int ACC_TILE_W = 64;
@@ -49,19 +57,26 @@ int step_threads(int m);                 // workgroup size of the per-position k
 size_t step_lds_bytes(int m);            // dynamic LDS of the per-position kernel
 
 hipError_t init_twiddles(hipStream_t s);
-hipError_t launch_step(int m, int mode, const StepArgs& a, hipStream_t s);
-hipError_t launch_accumulate(const AccumArgs& a, int n_tiles, hipStream_t s);
+// ev0/ev1 (nullable): events the dispatch itself records at kernel start and end
+hipError_t launch_step(int m, int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
+hipError_t launch_accumulate(const AccumArgs& a, int n_tiles, hipStream_t s, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given,
-                                  const double2* q64, double* u0, double* w0, float* u0f,
+                                  const double2* q64, double* u0, double* w0, float* w0f, float* u0f,
                                   float2* qf, double* lvl, double2* scr_q, double* scr_u,
                                   hipStream_t s);
 hipError_t launch_permute_sqrt(int m, int n_pos, const float* src, int is_sqrt, float* dst,
                                int* bad_flag, hipStream_t s);
 hipError_t launch_reduce_sum(const double* x, int n, double* out, hipStream_t s);
+// per position: sum of nw partials (optionally sqrt), then a fixed-order total
+hipError_t launch_reduce_parts(const double* parts, int n, int nw, int take_sqrt, double* per_pos,
+                               double* total, hipStream_t s);
+int step_waves(int m);
+hipError_t launch_set_counter(int* counter, int value, hipStream_t s);
+hipError_t launch_advance_counter(int* counter, hipStream_t s);
 hipError_t launch_convert_c64_c128(const float2* src, double2* dst, size_t n, hipStream_t s);
 hipError_t launch_convert_c128_c64(const double2* src, float2* dst, size_t n, hipStream_t s);
 hipError_t launch_check_finite_c64(const float2* src, size_t n, int* bad_flag, hipStream_t s);
-hipError_t launch_probe_apply(int m, int count, const float2* num, const float* den,
-                              double beta_unused, float2* q, hipStream_t s);
 
 }  // namespace mg

@@ -11,16 +11,17 @@
 //                       coefficients of the gradient-form V-cycle.
 //
 // 2-D FFT layout.  M = RA * RB.  A workgroup has M * RB threads; thread
-// tid = lo + M * g (lo in [0, M), g in [0, RB)).  Each 1-D pass along an axis
-// is two register stages: stage A, a radix-RA DFT over elements RB apart,
-// then the twiddle W_M^(n2 k1); stage B, CB = RA / RB radix-RB DFTs.  Data
-// move between stages through one padded LDS tile [M][M + 1] of float2.
-// Columns are transformed first with lo = x (lanes read whole object rows);
-// rows second with lo = ky.  The forward output lands with thread (ky, g)
-// holding kx = g*CB + c + RA*k2, which is the order sqrt(d) is stored in, so
-// the irreducible sqrt(d) stream is read as contiguous per-thread vectors.
-// The inverse transform retraces the forward steps backwards and returns the
-// data to the gather layout (thread (x, g) holds rows y = RB*n1 + g).
+// tid = g + RB * col.  Each 1-D pass along an axis is two register stages:
+// stage A, a radix-RA DFT over the RA elements RB apart that a thread holds,
+// then the twiddle W_M^(n2 k1); stage B, CB = RA / RB radix-RB DFTs after
+// the RB threads of a transform have exchanged data through LDS.  Columns
+// are transformed first (col = x), rows second (col = ky), with one LDS
+// transpose between.  The forward output lands with thread (ky, g) holding
+// kx = g*CB + c + RA*k2, the order sqrt(d) is stored in, so the irreducible
+// sqrt(d) stream is read as contiguous per-thread vectors.  The inverse
+// retraces the forward steps and returns the data to the gather layout
+// (thread (x, g) holds rows y = RB*n1 + g).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -47,332 +48,494 @@ hipError_t init_twiddles(hipStream_t s) {
 }
 
 template <int M> struct Plan;
-template <> struct Plan<8>   { static constexpr int RB = 2, RA = 4; };
-template <> struct Plan<16>  { static constexpr int RB = 4, RA = 4; };
-template <> struct Plan<32>  { static constexpr int RB = 4, RA = 8; };
-template <> struct Plan<64>  { static constexpr int RB = 8, RA = 8; };
-template <> struct Plan<128> { static constexpr int RB = 8, RA = 16; };
+// RB: threads per 1-D transform; RA: points per thread; PAD: row padding of
+// the LDS transpose tile (float2 units).
+template <> struct Plan<8>   { static constexpr int RB = 2, RA = 4, PAD = 2; };
+template <> struct Plan<16>  { static constexpr int RB = 4, RA = 4, PAD = 2; };
+template <> struct Plan<32>  { static constexpr int RB = 4, RA = 8, PAD = 2; };
+template <> struct Plan<64>  { static constexpr int RB = 8, RA = 8, PAD = 2; };
+template <> struct Plan<128> { static constexpr int RB = 8, RA = 16, PAD = 2; };
 
 template <int M>
 __device__ __forceinline__ float2 twiddle(int j) {
   return g_twiddle[(j & (M - 1)) * (128 / M)];
 }
 
-// Sum over the workgroup, fixed reduction order (deterministic).
-template <int TPB>
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  constexpr int W = TPB < 64 ? TPB : 64;
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
-  if constexpr (TPB <= 64) {
-    return v;
-  } else {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int w = 0; w < TPB / 64; ++w) s += red[w];
-    }
-    return s;
-  }
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+// In-wave V-cycle block (doubles): A_1..A_{L-1} at level-1 resolution, then
+// V_1..V_{L-2} at their own resolutions.
+__host__ __device__ constexpr int cst_count(int M, int L) {
+  int n = (L - 1) * (M / 2) * (M / 2);
+  for (int l = 1; l <= L - 2; ++l) n += (M >> l) * (M >> l);
+  return n;
+}
+__host__ __device__ constexpr int cst_v_off(int M, int L, int l) {
+  int n = (L - 1) * (M / 2) * (M / 2);
+  for (int j = 1; j < l; ++j) n += (M >> j) * (M >> j);
+  return n;
+}
+constexpr int cst_count_max(int M, int LW) { return cst_count(M, LW + 1); }
+
+// Orders this wave's LDS accesses around the call (LDS executes one wave's
+// operations in issue order; the fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int M, int MODE>
-__global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
-  constexpr int RB = Plan<M>::RB, RA = Plan<M>::RA;
-  constexpr int TPB = M * RB, CB = RA / RB, P = M + 1;
-  extern __shared__ double2 smem_d2[];
-  float2* buf = reinterpret_cast<float2*>(smem_d2);
-  __shared__ double red[16];
+// Sum over the lanes of one wave (LANES active lanes), fixed order.
+template <int LANES>
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LANES);
+  return v;
+}
 
+// MAGPS V-cycle through LDS for hierarchies whose coarse bins span several
+// waves.  On entry g0 is in T[y][x] (pitch P) and in v (thread (x, g) holds
+// rows RB*n1 + g).  Coarse grids (FP64) overwrite the start of the LDS tile.
+template <int M, int TPB, int P, int RB, int RA>
+__device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const float2* v, int col, int g,
+                          float2* outp) {
   const int tid = threadIdx.x;
-  const int lo = tid & (M - 1);
-  int g = tid / M;
-  if constexpr (M >= 64) g = __builtin_amdgcn_readfirstlane(g);
-  const int k = a.perm ? a.perm[blockIdx.x] : (int)blockIdx.x;
-  const int2 off = a.offs[k];
-
-  // ---- gather z_k and form the exit wave Q * z_k (layout: thread (x=lo, g), rows RB*n1+g)
-  float2 v[RA];
-  const float2* zp = a.z + (size_t)off.x * a.n_cols + off.y + lo;
+  const int L = a.levels;
+  constexpr int M1 = M / 2;
+  constexpr int E1 = (M1 * M1 + TPB - 1) / TPB;
+  double2 gh1[E1];
+#pragma unroll
+  for (int i = 0; i < E1; ++i) {
+    const int e = tid + i * TPB;
+    gh1[i] = make_double2(0.0, 0.0);
+    if (e < M1 * M1) {
+      const int Y = e / M1, X = e % M1;
+      const float2 p0 = T[(2 * Y) * P + 2 * X], p1 = T[(2 * Y) * P + 2 * X + 1];
+      const float2 p2 = T[(2 * Y + 1) * P + 2 * X], p3 = T[(2 * Y + 1) * P + 2 * X + 1];
+      gh1[i].x = 0.25 * (((double)p0.x + p1.x) + ((double)p2.x + p3.x));
+      gh1[i].y = 0.25 * (((double)p0.y + p1.y) + ((double)p2.y + p3.y));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < E1; ++i)
+    if (tid + i * TPB < M1 * M1) C[tid + i * TPB] = gh1[i];
+  // restriction down: g^_l = I(V_{l-1} g^_{l-1}); coarsest: e = -r g^
+  int off_prev = 0, lv_prev = 0, Mp = M1;
+  for (int l = 2; l < L; ++l) {
+    __syncthreads();
+    const int Ml = Mp >> 1;
+    const int off_cur = off_prev + Mp * Mp;
+    const int lv_cur = lv_prev + 3 * Mp * Mp;
+    const double* Vp = a.lvl + lv_prev;
+    const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
+    for (int e = tid; e < Ml * Ml; e += TPB) {
+      const int Y = e / Ml, X = e % Ml;
+      const int c0 = off_prev + (2 * Y) * Mp + 2 * X, c1 = c0 + Mp;
+      const int i0 = (2 * Y) * Mp + 2 * X, i1 = i0 + Mp;
+      double2 s;
+      s.x = 0.25 * ((Vp[i0] * C[c0].x + Vp[i0 + 1] * C[c0 + 1].x) + (Vp[i1] * C[c1].x + Vp[i1 + 1] * C[c1 + 1].x));
+      s.y = 0.25 * ((Vp[i0] * C[c0].y + Vp[i0 + 1] * C[c0 + 1].y) + (Vp[i1] * C[c1].y + Vp[i1 + 1] * C[c1 + 1].y));
+      if (l == L - 1) {
+        const double rr = rl[e];
+        s.x = -rr * s.x;
+        s.y = -rr * s.y;
+      }
+      C[off_cur + e] = s;
+    }
+    off_prev = off_cur;
+    lv_prev = lv_cur;
+    Mp = Ml;
+  }
+  // prolongation up: e_l = rho_l P(e_{l+1}) - r_l g^_l for l = L-2 .. 1
+  for (int l = L - 2; l >= 1; --l) {
+    __syncthreads();
+    const int Ml = Mp << 1;
+    const int off_cur = off_prev - Ml * Ml;
+    const int lv_cur = lv_prev - 3 * Ml * Ml;
+    const double* rhol = a.lvl + lv_cur + Ml * Ml;
+    const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
+    for (int e = tid; e < Ml * Ml; e += TPB) {
+      const int Y = e / Ml, X = e % Ml;
+      const double2 ec = C[off_prev + (Y >> 1) * Mp + (X >> 1)];
+      const double2 gh = C[off_cur + e];
+      const double rh = rhol[e], rr = rl[e];
+      C[off_cur + e] = make_double2(rh * ec.x - rr * gh.x, rh * ec.y - rr * gh.y);
+    }
+    off_prev = off_cur;
+    lv_prev = lv_cur;
+    Mp = Ml;
+  }
+  __syncthreads();
 #pragma unroll
   for (int n1 = 0; n1 < RA; ++n1) {
     const int y = RB * n1 + g;
-    v[n1] = cmul(a.q[y * M + lo], zp[(size_t)y * a.n_cols]);
+    const double2 e1 = C[(y >> 1) * M1 + (col >> 1)];
+    const double uu = (double)a.u0f[y * M + col];
+    outp[y * M] = make_float2((float)(uu * e1.x - (double)v[n1].x), (float)(uu * e1.y - (double)v[n1].y));
   }
-  // prefetch this thread's sqrt(d) values (contiguous RA floats)
-  float sd[RA];
-  if constexpr (MODE != MODE_FORWARD) {
-    const float4* sp = reinterpret_cast<const float4*>(a.sqrtd + (size_t)k * M * M + (size_t)tid * RA);
-#pragma unroll
-    for (int i = 0; i < RA / 4; ++i) {
-      float4 t = sp[i];
-      sd[4 * i] = t.x; sd[4 * i + 1] = t.y; sd[4 * i + 2] = t.z; sd[4 * i + 3] = t.w;
-    }
+}
+
+// Per-position kernel.  Thread tid = g + RB * col (g in [0, RB), col in [0, M)):
+// in column passes `col` is the image column x, in row passes it is the
+// frequency row ky.  A wave holds CPW = 64 / RB consecutive columns (rows).
+// Every LDS access of a wave stays inside its own column slice (column passes)
+// or its own row slice (row passes) of the transpose tile T, so the register
+// stages exchange data through LDS without workgroup barriers; only the two
+// transposes (forward and back) synchronise the workgroup.
+template <int M, int MODE>
+__global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
+  constexpr int RB = Plan<M>::RB, RA = Plan<M>::RA;
+  constexpr int TPB = M * RB, CB = RA / RB, P = M + Plan<M>::PAD;
+  constexpr int LANES = TPB < 64 ? TPB : 64;
+  constexpr int CPW = LANES / RB;
+  constexpr int LRB = ilog2c(RB), LW = ilog2c(CPW);
+  constexpr int NW = (TPB + 63) / 64;
+  extern __shared__ double2 smem_d2[];
+  float2* T = reinterpret_cast<float2*>(smem_d2);
+
+  const int tid = threadIdx.x;
+  const int g = tid & (RB - 1);
+  const int col = tid / RB;
+  const int cl = col & (CPW - 1);
+  const int c0w = col - cl;
+  const int wave = tid >> 6;
+  const size_t eoff = a.epoch ? (size_t)(*a.epoch) * a.epoch_stride : 0;
+  int k;
+  int2 off;
+  if (a.pos) {
+    const int4 pr = a.pos[eoff + blockIdx.x];
+    k = pr.x;
+    off = make_int2(pr.y, pr.z);
+  } else {
+    k = a.perm ? a.perm[eoff + blockIdx.x] : (int)blockIdx.x;
+    off = a.offs[k];
   }
 
-  // ---- forward, columns (along y), stage A
+  // exchange index inside the wave's slice: (cl, k1, n2) -> [0, 64 * RA)
+  auto xi = [&](int k1, int n2) { return (cl * RA + k1) * RB + n2; };
+  auto colslice = [&](int i) { return T + (i / CPW) * P + c0w + (i & (CPW - 1)); };
+  auto rowslice = [&](int i) { return T + (c0w + i / M) * P + (i & (M - 1)); };
+
+  // ---- gather z_k, exit wave Q * z_k: thread (x = col, g) holds rows y = RB*n1 + g
+  float2 v[RA];
+  // patch rows y = RB*n1 + g: per-lane byte offset (g, col), per-row scalar offset n1
+  const float2* zbase = a.z + (size_t)off.x * a.n_cols + off.y;
+  const rsrc_t zr = make_rsrc(zbase, (unsigned)(((size_t)(a.n_rows - off.x) * a.n_cols - off.y) * sizeof(float2)));
+  const rsrc_t qr = make_rsrc(a.q, (unsigned)(M * M * sizeof(float2)));
+  const int zvo = (g * a.n_cols + col) * (int)sizeof(float2);
+  const int zso = RB * a.n_cols * (int)sizeof(float2);
+  const int qvo = (g * M + col) * (int)sizeof(float2);
+  constexpr int qso = RB * M * (int)sizeof(float2);
+  constexpr bool KEEP = (M <= 64);
+  float2 zk[KEEP ? RA : 1], qk[KEEP ? RA : 1];
+#pragma unroll
+  for (int n1 = 0; n1 < RA; ++n1) {
+    const float2 qq = bload2(qr, qvo, n1 * qso);
+    const float2 zz = bload2(zr, zvo, n1 * zso);
+    if constexpr (KEEP) {
+      zk[n1] = zz;
+      qk[n1] = qq;
+    }
+    v[n1] = cmul(qq, zz);
+  }
+  // twiddles: stage A uses W_M^(g k1); the inverse stage B uses W_M^(n2 (g CB + c)).
+  // At M = 128 (16 points per thread, 128 VGPRs) they are re-read at each use
+  // and sqrt(d) is fetched just before the row pass instead of at the start.
+  constexpr bool LAZY = (M >= 128);
+  float2 twA[RA];
+  auto load_twA = [&]() {
+#pragma unroll
+    for (int k1 = 1; k1 < RA; ++k1) twA[k1] = twiddle<M>(g * k1);
+  };
+  load_twA();
+  float sd[RA];
+  auto load_sd = [&]() {
+    if constexpr (MODE != MODE_FORWARD) {
+      const rsrc_t sr = make_rsrc(a.sqrtd + (size_t)k * M * M, (unsigned)(M * M * sizeof(float)));
+#pragma unroll
+      for (int i = 0; i < RA / 4; ++i) {
+        const float4 t = bload4(sr, tid * RA * (int)sizeof(float), i * 16);
+        sd[4 * i] = t.x; sd[4 * i + 1] = t.y; sd[4 * i + 2] = t.z; sd[4 * i + 3] = t.w;
+      }
+    }
+  };
+  if constexpr (!LAZY) load_sd();
+  // In-wave V-cycle constants (A_l, V_l; M <= 64): fetched now, parked in LDS
+  // at the first barrier, so their latency hides behind the forward FFT.
+  constexpr bool CST = (MODE == MODE_STEP) && (M <= 64);
+  constexpr int M1c = M / 2;
+  constexpr int CST_MAX = CST ? cst_count_max(M, LW) : 1;
+  constexpr int CST_PER = (CST_MAX + TPB - 1) / TPB;
+  double* const Cst = reinterpret_cast<double*>(T + M * P);
+  const int nCst = (CST && a.levels >= 2 && a.levels - 1 <= LW) ? cst_count(M, a.levels) : 0;
+  double cst[CST_PER];
+  float u0k[CST ? RA : 1];
+  if constexpr (CST) {
+#pragma unroll
+    for (int i = 0; i < CST_PER; ++i) {
+      const int e = tid + i * TPB;
+      cst[i] = (e < nCst) ? a.lvl[a.lvl_a_off + e] : 0.0;
+    }
+#pragma unroll
+    for (int n1 = 0; n1 < RA; ++n1) u0k[n1] = a.u0f[(RB * n1 + g) * M + col];
+  }
+
+  // ---- forward, columns: stage A (radix RA over n1), twiddle, exchange, stage B
   dft<RA, 1>(v);
 #pragma unroll
-  for (int k1 = 1; k1 < RA; ++k1) v[k1] = cmul(v[k1], twiddle<M>(g * k1));
+  for (int k1 = 1; k1 < RA; ++k1) v[k1] = cmul(v[k1], twA[k1]);
 #pragma unroll
-  for (int k1 = 0; k1 < RA; ++k1) buf[(k1 * RB + g) * P + lo] = v[k1];
-  __syncthreads();
+  for (int k1 = 0; k1 < RA; ++k1) *colslice(xi(k1, g)) = v[k1];
+  wave_sync();
 #pragma unroll
   for (int c = 0; c < CB; ++c)
 #pragma unroll
-    for (int n2 = 0; n2 < RB; ++n2) v[c * RB + n2] = buf[((g * CB + c) * RB + n2) * P + lo];
-  // stage B
+    for (int n2 = 0; n2 < RB; ++n2) v[c * RB + n2] = *colslice(xi(g * CB + c, n2));
 #pragma unroll
   for (int c = 0; c < CB; ++c) dft<RB, 1>(&v[c * RB]);
-  __syncthreads();
-  // transpose: buf[ky][x]
+  wave_sync();
+  // v[c*RB + k2] = column spectrum at ky = g*CB + c + RA*k2; transpose into T[ky][x]
 #pragma unroll
   for (int c = 0; c < CB; ++c)
 #pragma unroll
-    for (int k2 = 0; k2 < RB; ++k2) buf[((g * CB + c) + RA * k2) * P + lo] = v[c * RB + k2];
-  __syncthreads();
-  // ---- forward, rows (along x), stage A; lo = ky now
+    for (int k2 = 0; k2 < RB; ++k2) T[((g * CB + c) + RA * k2) * P + col] = v[c * RB + k2];
+  if constexpr (CST) {
 #pragma unroll
-  for (int n1 = 0; n1 < RA; ++n1) v[n1] = buf[lo * P + RB * n1 + g];
+    for (int i = 0; i < CST_PER; ++i)
+      if (tid + i * TPB < nCst) Cst[tid + i * TPB] = cst[i];
+  }
+  __syncthreads();
+
+  // ---- forward, rows (col = ky now): stage A over x = RB*n1 + g
+  if constexpr (LAZY) load_sd();
+#pragma unroll
+  for (int n1 = 0; n1 < RA; ++n1) v[n1] = T[col * P + RB * n1 + g];
+  if constexpr (LAZY) load_twA();
   dft<RA, 1>(v);
 #pragma unroll
-  for (int k1 = 1; k1 < RA; ++k1) v[k1] = cmul(v[k1], twiddle<M>(g * k1));
-  __syncthreads();
+  for (int k1 = 1; k1 < RA; ++k1) v[k1] = cmul(v[k1], twA[k1]);
+  wave_sync();
 #pragma unroll
-  for (int k1 = 0; k1 < RA; ++k1) buf[lo * P + k1 * RB + g] = v[k1];
-  __syncthreads();
+  for (int k1 = 0; k1 < RA; ++k1) *rowslice(xi(k1, g)) = v[k1];
+  wave_sync();
 #pragma unroll
   for (int c = 0; c < CB; ++c)
 #pragma unroll
-    for (int n2 = 0; n2 < RB; ++n2) v[c * RB + n2] = buf[lo * P + (g * CB + c) * RB + n2];
+    for (int n2 = 0; n2 < RB; ++n2) v[c * RB + n2] = *rowslice(xi(g * CB + c, n2));
 #pragma unroll
   for (int c = 0; c < CB; ++c) dft<RB, 1>(&v[c * RB]);
-  // v[c*RB + k2] = Psi[ky = lo][kx = g*CB + c + RA*k2]
+  // v[c*RB + k2] = Psi[ky = col][kx = g*CB + c + RA*k2]
 
   if constexpr (MODE == MODE_FORWARD) {
-    float* dp = a.d_out + (size_t)k * M * M + (size_t)lo * M;
+    float* dp = a.d_out + (size_t)k * M * M + (size_t)col * M;
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
       for (int k2 = 0; k2 < RB; ++k2) {
-        float2 t = v[c * RB + k2];
+        const float2 t = v[c * RB + k2];
         dp[g * CB + c + RA * k2] = t.x * t.x + t.y * t.y;
       }
     return;
   } else {
-    // ---- modulus replacement (Definition 2.1, theta(0) = 0) and Phi_k partial (FP64)
+    // ---- modulus replacement (Definition 2.1, theta(0) = 0); Phi_k partial in FP64
     double phis = 0.0;
 #pragma unroll
     for (int j = 0; j < RA; ++j) {
       const float2 t = v[j];
       const float a2 = t.x * t.x + t.y * t.y;
-      const float am = sqrtf(a2);
+      const float ra = __builtin_amdgcn_rsqf(a2);
       const float s = sd[j];
-      const double dlt = (double)am - (double)s;
-      phis += dlt * dlt;
       if (a2 > 0.0f) {
-        const float f = s / am;
+        const double dlt = (double)(a2 * ra) - (double)s;
+        phis += dlt * dlt;
+        const float f = s * ra;
         v[j] = make_float2(t.x * f, t.y * f);
       } else {
+        phis += (double)s * (double)s;
         v[j] = make_float2(s, 0.0f);
       }
     }
-    if (a.phi_k) {
-      double tot = block_sum<TPB>(phis, red);
-      if (tid == 0) a.phi_k[k] = tot * (0.5 / ((double)M * (double)M));
+    if (a.phi_part) {
+      const double tot = wave_sum<LANES>(phis);
+      if ((tid & 63) == 0) a.phi_part[(size_t)k * MAX_WAVES + wave] = tot * (0.5 / ((double)M * (double)M));
     }
 
-    // ---- inverse, rows: stage B^-1, twiddle conj, stage A^-1
+    // ---- inverse, rows: stage B^-1, conj twiddle, exchange, stage A^-1
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       dft<RB, -1>(&v[c * RB]);
-      const int k1 = g * CB + c;
 #pragma unroll
-      for (int n2 = 1; n2 < RB; ++n2) v[c * RB + n2] = cmulc(twiddle<M>(n2 * k1), v[c * RB + n2]);
+      for (int n2 = 1; n2 < RB; ++n2)
+        v[c * RB + n2] = cmulc(CB == 1 ? twA[n2] : twiddle<M>(n2 * (g * CB + c)), v[c * RB + n2]);
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
-      for (int n2 = 0; n2 < RB; ++n2) buf[lo * P + (g * CB + c) * RB + n2] = v[c * RB + n2];
-    __syncthreads();
+      for (int n2 = 0; n2 < RB; ++n2) *rowslice(xi(g * CB + c, n2)) = v[c * RB + n2];
+    wave_sync();
 #pragma unroll
-    for (int k1 = 0; k1 < RA; ++k1) v[k1] = buf[lo * P + k1 * RB + g];
+    for (int k1 = 0; k1 < RA; ++k1) v[k1] = *rowslice(xi(k1, g));
     dft<RA, -1>(v);
-    // v[n1] = row ky=lo, x = RB*n1 + g; transpose back to buf[ky][x]
-    __syncthreads();
+    wave_sync();
+    // v[n1] = row ky = col at x = RB*n1 + g; transpose back into T[ky][x] (own rows)
 #pragma unroll
-    for (int n1 = 0; n1 < RA; ++n1) buf[lo * P + RB * n1 + g] = v[n1];
+    for (int n1 = 0; n1 < RA; ++n1) T[col * P + RB * n1 + g] = v[n1];
     __syncthreads();
-    // ---- inverse, columns; lo = x again
+
+    // ---- inverse, columns (col = x): stage B^-1 over k2, conj twiddle, exchange, stage A^-1
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
-      for (int k2 = 0; k2 < RB; ++k2) v[c * RB + k2] = buf[((g * CB + c) + RA * k2) * P + lo];
+      for (int k2 = 0; k2 < RB; ++k2) v[c * RB + k2] = T[((g * CB + c) + RA * k2) * P + col];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       dft<RB, -1>(&v[c * RB]);
-      const int k1 = g * CB + c;
 #pragma unroll
-      for (int n2 = 1; n2 < RB; ++n2) v[c * RB + n2] = cmulc(twiddle<M>(n2 * k1), v[c * RB + n2]);
+      for (int n2 = 1; n2 < RB; ++n2)
+        v[c * RB + n2] = cmulc(CB == 1 ? twA[n2] : twiddle<M>(n2 * (g * CB + c)), v[c * RB + n2]);
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
-      for (int n2 = 0; n2 < RB; ++n2) buf[((g * CB + c) * RB + n2) * P + lo] = v[c * RB + n2];
-    __syncthreads();
+      for (int n2 = 0; n2 < RB; ++n2) *colslice(xi(g * CB + c, n2)) = v[c * RB + n2];
+    wave_sync();
 #pragma unroll
-    for (int k1 = 0; k1 < RA; ++k1) v[k1] = buf[(k1 * RB + g) * P + lo];
+    for (int k1 = 0; k1 < RA; ++k1) v[k1] = *colslice(xi(k1, g));
     dft<RA, -1>(v);
 
-    // ---- R_k = v / M^2; gradient g0 = conj(Q) (Q z_k - R_k)  (eq. 2.2)
+    // ---- R_k = v / M^2; gradient g0 = conj(Q) (Q z_k - R_k) (eq. 2.2)
     constexpr float inv_m2 = 1.0f / (float)(M * M);
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
-      const int y = RB * n1 + g;
-      const float2 qq = a.q[y * M + lo];
-      const float2 zz = zp[(size_t)y * a.n_cols];
-      const float2 r = cscale(v[n1], inv_m2);
-      v[n1] = cmulc(qq, csub(cmul(qq, zz), r));
+      float2 qq, zz;
+      if constexpr (KEEP) {
+        qq = qk[n1];
+        zz = zk[n1];
+      } else {
+        qq = bload2(qr, qvo, n1 * qso);
+        zz = bload2(zr, zvo, n1 * zso);
+      }
+      v[n1] = cmulc(qq, csub(cmul(qq, zz), cscale(v[n1], inv_m2)));
     }
 
     if constexpr (MODE == MODE_OBJECTIVE) {
       double gs = 0.0;
 #pragma unroll
       for (int n1 = 0; n1 < RA; ++n1) gs += (double)v[n1].x * v[n1].x + (double)v[n1].y * v[n1].y;
-      double tot = block_sum<TPB>(gs, red);
-      if (tid == 0) a.gnorm_k[k] = sqrt(tot);
+      const double tot = wave_sum<LANES>(gs);
+      if ((tid & 63) == 0) a.gn_part[(size_t)k * MAX_WAVES + wave] = tot;
       return;
     } else {
-      // ---- MAGPS V-cycle, gradient form (FP64 on the coarse grids)
-      float2* outp = a.stage + (size_t)blockIdx.x * M * M + lo;
+      float2* outp = a.stage + (size_t)blockIdx.x * M * M + col;
+      const rsrc_t outr = make_rsrc(a.stage + (size_t)blockIdx.x * M * M, (unsigned)(M * M * sizeof(float2)));
+      const int ovo = (g * M + col) * (int)sizeof(float2);
       const int L = a.levels;
       if (L <= 1) {
 #pragma unroll
-        for (int n1 = 0; n1 < RA; ++n1) outp[(RB * n1 + g) * M] = make_float2(-v[n1].x, -v[n1].y);
+        for (int n1 = 0; n1 < RA; ++n1) bstore2(outr, make_float2(-v[n1].x, -v[n1].y), ovo, n1 * qso);
         return;
       }
-      __syncthreads();
+      if (L - 1 <= LW) {
+        // ---- MAGPS V-cycle inside the wave (gradient form, FP64).  Level-l
+        // values are held replicated by every thread of their 2^l x 2^l bin,
+        // so restriction is two cross-lane (or in-thread) pair sums and
+        // prolongation is free.  The upward pass is folded into per-level
+        // coefficients: e_1 = sum_l A_l g^_l with A_l = -r_l prod_{j<l} rho_j.
+        // Chunks of NC register rows: while every restriction pairs rows across
+        // lanes (LW <= log2 RB) the rows n1 are independent.
+        constexpr int NC = (LW > LRB) ? RA : (M >= 128 ? 2 : (RA < 4 ? RA : 4));
+        const double* Abase = a.lvl + a.lvl_a_off;
 #pragma unroll
-      for (int n1 = 0; n1 < RA; ++n1) buf[(RB * n1 + g) * P + lo] = v[n1];
-      __syncthreads();
-      constexpr int M1 = M / 2;
-      constexpr int E1 = (M1 * M1) / TPB;  // level-1 elements per thread (RA / 4)
-      double2 gh1[E1];
+        for (int n0 = 0; n0 < RA; n0 += NC) {
+          double2 cur[NC], e1[NC];
 #pragma unroll
-      for (int i = 0; i < E1; ++i) {
-        const int e = tid + i * TPB;
-        const int Y = e / M1, X = e % M1;
-        const float2 p0 = buf[(2 * Y) * P + 2 * X], p1 = buf[(2 * Y) * P + 2 * X + 1];
-        const float2 p2 = buf[(2 * Y + 1) * P + 2 * X], p3 = buf[(2 * Y + 1) * P + 2 * X + 1];
-        gh1[i].x = 0.25 * (((double)p0.x + p1.x) + ((double)p2.x + p3.x));
-        gh1[i].y = 0.25 * (((double)p0.y + p1.y) + ((double)p2.y + p3.y));
-      }
-      __syncthreads();
-      double2* C = smem_d2;  // coarse grids, level l at offset sum_{j<l} (M>>j)^2 (j >= 1)
-      // level 1 constants
-      const double* V1 = a.lvl;
-      const double* rho1 = a.lvl + M1 * M1;
-      const double* r1 = a.lvl + 2 * M1 * M1;
-      if (L == 2) {
+          for (int i = 0; i < NC; ++i) {
+            cur[i] = make_double2(v[n0 + i].x, v[n0 + i].y);
+            e1[i] = make_double2(0.0, 0.0);
+          }
+          int lv_off = 0;
 #pragma unroll
-        for (int i = 0; i < E1; ++i) {
-          const int e = tid + i * TPB;
-          const double rr = r1[e];
-          C[e] = make_double2(-rr * gh1[i].x, -rr * gh1[i].y);
-        }
-      } else {
+          for (int l = 1; l <= LW; ++l) {
+            if (l < L) {
+              const int Ml = M >> l;
+              double2 s[NC];
+              if (l - 1 < LRB) {
 #pragma unroll
-        for (int i = 0; i < E1; ++i) C[tid + i * TPB] = gh1[i];
-        // restriction down: g^_l = I(V_{l-1} g^_{l-1}); coarsest: e = -r g^
-        int off_prev = 0, lv_prev = 0;
-        int Mp = M1;
-        for (int l = 2; l < L; ++l) {
-          __syncthreads();
-          const int Ml = Mp >> 1;
-          const int off_cur = off_prev + Mp * Mp;
-          const int lv_cur = lv_prev + 3 * Mp * Mp;
-          const double* Vp = a.lvl + lv_prev;
-          const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
-          for (int e = tid; e < Ml * Ml; e += TPB) {
-            const int Y = e / Ml, X = e % Ml;
-            const int c0 = off_prev + (2 * Y) * Mp + 2 * X, c1 = c0 + Mp;
-            const int i0 = (2 * Y) * Mp + 2 * X, i1 = i0 + Mp;
-            double2 s;
-            s.x = 0.25 * ((Vp[i0] * C[c0].x + Vp[i0 + 1] * C[c0 + 1].x) + (Vp[i1] * C[c1].x + Vp[i1 + 1] * C[c1 + 1].x));
-            s.y = 0.25 * ((Vp[i0] * C[c0].y + Vp[i0 + 1] * C[c0 + 1].y) + (Vp[i1] * C[c1].y + Vp[i1 + 1] * C[c1 + 1].y));
-            if (l == L - 1) {
-              const double rr = rl[e];
-              s.x = -rr * s.x;
-              s.y = -rr * s.y;
+                for (int i = 0; i < NC; ++i) {
+                  const double2 o = xor_lane_rt(cur[i], 1 << (l - 1));
+                  s[i] = make_double2(cur[i].x + o.x, cur[i].y + o.y);
+                }
+              } else {
+                const int b = (l - 1 >= LRB) ? (1 << (l - 1 - LRB)) : 0;
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                  const double2 o = cur[(i ^ b) & (NC - 1)];
+                  s[i] = make_double2(cur[i].x + o.x, cur[i].y + o.y);
+                }
+              }
+              const double* A = (CST ? (const double*)Cst : Abase) + (size_t)(l - 1) * M1c * M1c;
+              const double* V = CST ? (const double*)Cst + cst_v_off(M, L, l) : a.lvl + lv_off;
+              const bool more = (l + 1 < L);
+#pragma unroll
+              for (int i = 0; i < NC; ++i) {
+                const double2 o = xor_lane_rt(s[i], RB << (l - 1));
+                const double2 gh = make_double2(0.25 * (s[i].x + o.x), 0.25 * (s[i].y + o.y));
+                const int y = RB * (n0 + i) + g;
+                const double aa = A[(y >> 1) * (M / 2) + (col >> 1)];
+                e1[i] = make_double2(e1[i].x + aa * gh.x, e1[i].y + aa * gh.y);
+                if (more) {
+                  const double vv = V[(y >> l) * Ml + (col >> l)];
+                  cur[i] = make_double2(vv * gh.x, vv * gh.y);
+                }
+              }
+              lv_off += 3 * Ml * Ml;
             }
-            C[off_cur + e] = s;
           }
-          off_prev = off_cur;
-          lv_prev = lv_cur;
-          Mp = Ml;
-        }
-        // prolongation up: e_l = rho_l P(e_{l+1}) - r_l g^_l, levels L-2 .. 1
-        // (off_prev, lv_prev, Mp) describe level L-1 here
-        for (int l = L - 2; l >= 1; --l) {
-          __syncthreads();
-          const int Ml = Mp << 1;
-          const int off_cur = off_prev - Ml * Ml;
-          const int lv_cur = lv_prev - 3 * Ml * Ml;
-          const double* rhol = a.lvl + lv_cur + Ml * Ml;
-          const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
-          for (int e = tid; e < Ml * Ml; e += TPB) {
-            const int Y = e / Ml, X = e % Ml;
-            const double2 ec = C[off_prev + (Y >> 1) * Mp + (X >> 1)];
-            const double2 gh = C[off_cur + e];
-            const double rh = rhol[e], rr = rl[e];
-            C[off_cur + e] = make_double2(rh * ec.x - rr * gh.x, rh * ec.y - rr * gh.y);
-          }
-          off_prev = off_cur;
-          lv_prev = lv_cur;
-          Mp = Ml;
-        }
-      }
-      __syncthreads();
-      // level 0: c_k = u0 P(e_1) - g0
+          // level 0: c_k = u0 P(e_1) - g0
 #pragma unroll
-      for (int n1 = 0; n1 < RA; ++n1) {
-        const int y = RB * n1 + g;
-        const double2 e1 = C[(y >> 1) * M1 + (lo >> 1)];
-        const double uu = (double)a.u0f[y * M + lo];
-        outp[y * M] = make_float2((float)(uu * e1.x - (double)v[n1].x), (float)(uu * e1.y - (double)v[n1].y));
+          for (int i = 0; i < NC; ++i) {
+            const int y = RB * (n0 + i) + g;
+            const double uu = CST ? (double)u0k[n0 + i] : (double)a.u0f[y * M + col];
+            bstore2(outr,
+                    make_float2((float)(uu * e1[i].x - (double)v[n0 + i].x),
+                                (float)(uu * e1[i].y - (double)v[n0 + i].y)),
+                    ovo, (n0 + i) * qso);
+          }
+        }
+        return;
       }
+      // ---- deep hierarchies (coarse bins wider than a wave): V-cycle through LDS
+      __syncthreads();
+#pragma unroll
+      for (int n1 = 0; n1 < RA; ++n1) T[(RB * n1 + g) * P + col] = v[n1];
+      __syncthreads();
+      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, col, g, outp);
     }
   }
 }
 
-template <int M>
-static hipError_t launch_step_m(int mode, const StepArgs& a, hipStream_t s) {
+template <int M, int MODE>
+static void launch_step_mode(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   constexpr int TPB = M * Plan<M>::RB;
-  const size_t lds = (size_t)M * (M + 1) * sizeof(float2);
+  const size_t lds = step_lds_bytes(M);
+  hipFuncSetAttribute((const void*)step_kernel<M, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (ev0)
+    hipExtLaunchKernelGGL((step_kernel<M, MODE>), dim3(a.count), dim3(TPB), lds, s, ev0, ev1, 0, a);
+  else
+    hipLaunchKernelGGL((step_kernel<M, MODE>), dim3(a.count), dim3(TPB), lds, s, a);
+}
+
+template <int M>
+static hipError_t launch_step_m(int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.count <= 0) return hipSuccess;
   switch (mode) {
-    case MODE_STEP:
-      hipFuncSetAttribute((const void*)step_kernel<M, MODE_STEP>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipLaunchKernelGGL((step_kernel<M, MODE_STEP>), dim3(a.count), dim3(TPB), lds, s, a);
-      break;
-    case MODE_OBJECTIVE:
-      hipFuncSetAttribute((const void*)step_kernel<M, MODE_OBJECTIVE>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipLaunchKernelGGL((step_kernel<M, MODE_OBJECTIVE>), dim3(a.count), dim3(TPB), lds, s, a);
-      break;
-    case MODE_FORWARD:
-      hipFuncSetAttribute((const void*)step_kernel<M, MODE_FORWARD>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipLaunchKernelGGL((step_kernel<M, MODE_FORWARD>), dim3(a.count), dim3(TPB), lds, s, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case MODE_STEP: launch_step_mode<M, MODE_STEP>(a, s, ev0, ev1); break;
+    case MODE_OBJECTIVE: launch_step_mode<M, MODE_OBJECTIVE>(a, s, ev0, ev1); break;
+    case MODE_FORWARD: launch_step_mode<M, MODE_FORWARD>(a, s, ev0, ev1); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -388,57 +551,128 @@ int step_threads(int m) {
   }
 }
 
-size_t step_lds_bytes(int m) { return (size_t)m * (m + 1) * sizeof(float2); }
+template <int M>
+static size_t lds_bytes_m() {
+  constexpr int RB = Plan<M>::RB, TPB = M * RB, P = M + Plan<M>::PAD;
+  constexpr int LW = ilog2c((TPB < 64 ? TPB : 64) / RB);
+  size_t b = (size_t)M * P * sizeof(float2);
+  if (M <= 64) b += (size_t)cst_count_max(M, LW) * sizeof(double);
+  return b;
+}
 
-hipError_t launch_step(int m, int mode, const StepArgs& a, hipStream_t s) {
+size_t step_lds_bytes(int m) {
   switch (m) {
-    case 8: return launch_step_m<8>(mode, a, s);
-    case 16: return launch_step_m<16>(mode, a, s);
-    case 32: return launch_step_m<32>(mode, a, s);
-    case 64: return launch_step_m<64>(mode, a, s);
-    case 128: return launch_step_m<128>(mode, a, s);
+    case 8: return lds_bytes_m<8>();
+    case 16: return lds_bytes_m<16>();
+    case 32: return lds_bytes_m<32>();
+    case 64: return lds_bytes_m<64>();
+    case 128: return lds_bytes_m<128>();
+    default: return 0;
+  }
+}
+
+hipError_t launch_step(int m, int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (m) {
+    case 8: return launch_step_m<8>(mode, a, s, ev0, ev1);
+    case 16: return launch_step_m<16>(mode, a, s, ev0, ev1);
+    case 32: return launch_step_m<32>(mode, a, s, ev0, ev1);
+    case 64: return launch_step_m<64>(mode, a, s, ev0, ev1);
+    case 128: return launch_step_m<128>(mode, a, s, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Deterministic segmented accumulation + apply.  One workgroup per 64 x 16
-// tile; lane = column, wave w owns rows w, w+4, w+8, w+12.  Positions
-// overlapping the tile are visited in ascending index; those in minibatch t
-// contribute their staged c_k and w0 (FP64 sums).
+// tile; lane = column, wave w owns rows w, w+4, w+8, w+12.  The positions
+// overlapping the tile (ascending index, with their offsets) are screened 256
+// at a time in parallel: those in minibatch t are compacted, order preserved,
+// into LDS, then every thread sums their staged c_k and w0 over its pixels in
+// that order (FP64 sums of the staged FP32 c_k and an FP32 copy of w0).  Loads are predicated
+// rather than branched so that several positions' loads are in flight.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(ACC_THREADS) void accumulate_kernel(AccumArgs a) {
   constexpr int RPT = ACC_TILE_H / (ACC_THREADS / 64);
+  constexpr int NW = ACC_THREADS / 64;
+  constexpr int U = 4;   // positions whose loads are in flight together
+  __shared__ int s_slot[ACC_THREADS];
+  __shared__ int2 s_off[ACC_THREADS];
+  __shared__ int s_wcnt[NW];
   const int tile = blockIdx.x;
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int X = tx * ACC_TILE_W + lane;
   const int Y0 = ty * ACC_TILE_H + wave;
   const int m = a.m;
+  const size_t mm = (size_t)m * m;
   double nr[RPT], ni[RPT], dd[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) nr[i] = ni[i] = dd[i] = 0.0;
   const int beg = a.tile_ptr[tile], end = a.tile_ptr[tile + 1];
   const int lo_idx = a.batch_index * a.batch;
-  for (int idx = beg; idx < end; ++idx) {
-    const int k = a.tile_pos[idx];
-    const int slot = a.inv[k] - lo_idx;
-    if (slot < 0 || slot >= a.batch) continue;
-    const int2 off = a.offs[k];
-    const int xx = X - off.y;
-    if ((unsigned)xx >= (unsigned)m) continue;
-    const float2* sp = a.stage + (size_t)slot * m * m + xx;
-    const double* wp = a.w0 + xx;
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int yy = Y0 + 4 * i - off.x;
-      if ((unsigned)yy < (unsigned)m) {
-        const float2 c = sp[(size_t)yy * m];
-        nr[i] += (double)c.x;
-        ni[i] += (double)c.y;
-        dd[i] += wp[yy * m];
+  const int* inv = a.inv + (a.epoch ? (size_t)(*a.epoch) * a.epoch_stride : 0);
+  for (int base = beg; base < end; base += ACC_THREADS) {
+    const int idx = base + tid;
+    int slot = -1;
+    int2 off = make_int2(0, 0);
+    if (idx < end) {
+      const int4 te = a.tile_ent[idx];
+      const int s = inv[te.x] - lo_idx;
+      if (s >= 0 && s < a.batch) {
+        slot = s;
+        off = make_int2(te.y, te.z);
       }
     }
+    const bool in = slot >= 0;
+    const unsigned long long mask = __ballot(in);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wcnt[wave] = __popcll(mask);
+    __syncthreads();
+    int wbase = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int c = s_wcnt[w];
+      wbase += (w < wave) ? c : 0;
+      total += c;
+    }
+    if (in) {
+      s_slot[wbase + before] = slot;
+      s_off[wbase + before] = off;
+    }
+    __syncthreads();
+    // sum the compacted entries in order, U positions' loads at a time
+    for (int j = 0; j < total; j += U) {
+      float2 cv[U][RPT];
+      float wv[U][RPT];
+      bool ok[U][RPT];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool have = (j + u) < total;
+        const int sl = have ? s_slot[j + u] : 0;
+        const int2 o = have ? s_off[j + u] : make_int2(-m, -m);
+        const int xx = X - o.y;
+        const bool okx = have && (unsigned)xx < (unsigned)m;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int yy = Y0 + 4 * i - o.x;
+          ok[u][i] = okx && ((unsigned)yy < (unsigned)m);
+          const int e = ok[u][i] ? (yy * m + xx) : 0;
+          cv[u][i] = a.stage[(size_t)sl * mm + e];
+          wv[u][i] = a.w0f[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (ok[u][i]) {
+            nr[i] += (double)cv[u][i].x;
+            ni[i] += (double)cv[u][i].y;
+            dd[i] += (double)wv[u][i];
+          }
+    }
+    __syncthreads();
   }
   if (X < a.n_cols) {
 #pragma unroll
@@ -453,9 +687,12 @@ __global__ __launch_bounds__(ACC_THREADS) void accumulate_kernel(AccumArgs a) {
   }
 }
 
-hipError_t launch_accumulate(const AccumArgs& a, int n_tiles, hipStream_t s) {
+hipError_t launch_accumulate(const AccumArgs& a, int n_tiles, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(accumulate_kernel, dim3(n_tiles), dim3(ACC_THREADS), 0, s, a);
+  if (ev0)
+    hipExtLaunchKernelGGL(accumulate_kernel, dim3(n_tiles), dim3(ACC_THREADS), 0, s, ev0, ev1, 0, a);
+  else
+    hipLaunchKernelGGL(accumulate_kernel, dim3(n_tiles), dim3(ACC_THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -469,7 +706,7 @@ hipError_t launch_accumulate(const AccumArgs& a, int n_tiles, hipStream_t s) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels, double alpha, int u_given,
                                                                const double2* q64, double* u0, double* w0,
-                                                               float* u0f, float2* qf, double* lvl,
+                                                               float* w0f, float* u0f, float2* qf, double* lvl,
                                                                double2* scr_q, double* scr_u) {
   __shared__ double red[1024];
   const int tid = threadIdx.x;
@@ -492,6 +729,7 @@ __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels
     const double uu = u_given ? u0[e] : alpha * (amax - a2);
     u0[e] = uu;
     w0[e] = uu + a2;
+    w0f[e] = (float)(uu + a2);
     u0f[e] = (float)uu;
     qf[e] = make_float2((float)q.x, (float)q.y);
   }
@@ -543,18 +781,48 @@ __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels
     lv += 3 * Ml * Ml;
     Mp = Ml;
   }
+  // A_l = -r_l prod_{j<l} rho_j along the ancestors of each level-1 bin, so
+  // that e_1 = sum_l A_l g^_l (the upward pass of the V-cycle, unrolled).
+  __syncthreads();
+  if (levels > 1) {
+    const int M1 = m / 2;
+    double* A = lvl + lv;
+    for (int e = tid; e < M1 * M1; e += blockDim.x) {
+      const int Y1 = e / M1, X1 = e % M1;
+      double prod = 1.0;
+      int off = 0;
+      for (int l = 1; l < levels; ++l) {
+        const int Ml = m >> l;
+        const int idx = (Y1 >> (l - 1)) * Ml + (X1 >> (l - 1));
+        const double rho = lvl[off + Ml * Ml + idx];
+        const double r = lvl[off + 2 * Ml * Ml + idx];
+        A[(size_t)(l - 1) * M1 * M1 + e] = -r * prod;
+        prod *= rho;
+        off += 3 * Ml * Ml;
+      }
+    }
+    // copies of V_1..V_{L-2} right after the A block (the in-wave V-cycle's block)
+    double* Vc = A + (size_t)(levels - 1) * M1 * M1;
+    int off = 0;
+    for (int l = 1; l <= levels - 2; ++l) {
+      const int Ml = m >> l;
+      for (int e = tid; e < Ml * Ml; e += blockDim.x) Vc[e] = lvl[off + e];
+      Vc += Ml * Ml;
+      off += 3 * Ml * Ml;
+    }
+  }
 }
 
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given, const double2* q64,
-                                  double* u0, double* w0, float* u0f, float2* qf, double* lvl,
+                                  double* u0, double* w0, float* w0f, float* u0f, float2* qf, double* lvl,
                                   double2* scr_q, double* scr_u, hipStream_t s) {
   hipLaunchKernelGGL(level_constants_kernel, dim3(1), dim3(1024), 0, s, m, levels, alpha, u_given, q64, u0,
-                     w0, u0f, qf, lvl, scr_q, scr_u);
+                     w0, w0f, u0f, qf, lvl, scr_q, scr_u);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// sqrt(d) into kernel order: thread tid = ky + M*g of position k reads
+// sqrt(d) into kernel order: thread tid = g + RB*ky of position k reads
 // kx = g*CB + c + RA*k2 for j = c*RB + k2 and writes dst[k][tid*RA + j].
 // Flags negative or non-finite input.
 // ---------------------------------------------------------------------------
@@ -563,7 +831,7 @@ __global__ void permute_sqrt_kernel(int n_pos, const float* src, int is_sqrt, fl
   constexpr int RB = Plan<M>::RB, RA = Plan<M>::RA, CB = RA / RB;
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
-  const int ky = tid & (M - 1), g = tid / M;
+  const int g = tid & (RB - 1), ky = tid / RB;
   const float* sp = src + (size_t)k * M * M + (size_t)ky * M;
   float* dp = dst + (size_t)k * M * M + (size_t)tid * RA;
   int badl = 0;
@@ -571,7 +839,7 @@ __global__ void permute_sqrt_kernel(int n_pos, const float* src, int is_sqrt, fl
   for (int c = 0; c < CB; ++c)
 #pragma unroll
     for (int k2 = 0; k2 < RB; ++k2) {
-      float x = sp[g * CB + c + RA * k2];
+      const float x = sp[g * CB + c + RA * k2];
       if (!(x >= 0.0f) || !isfinite(x)) badl = 1;
       dp[c * RB + k2] = is_sqrt ? x : sqrtf(x);
     }
@@ -609,6 +877,47 @@ __global__ __launch_bounds__(256) void reduce_sum_kernel(const double* x, int n,
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const double* parts, int n, int nw, int take_sqrt,
+                                                           double* per_pos, double* total) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double p = 0.0;
+    for (int w = 0; w < nw; ++w) p += parts[(size_t)i * MAX_WAVES + w];
+    if (take_sqrt) p = sqrt(p);
+    if (per_pos) per_pos[i] = p;
+    s += p;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = red[0];
+}
+
+hipError_t launch_reduce_parts(const double* parts, int n, int nw, int take_sqrt, double* per_pos, double* total,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, s, parts, n, nw, take_sqrt, per_pos, total);
+  return hipGetLastError();
+}
+
+int step_waves(int m) { return (step_threads(m) + 63) / 64; }
+
+// Epoch counter for graph replays (kernels, so that a captured graph holds no memset node).
+__global__ void set_counter_kernel(int* c, int v) { *c = v; }
+__global__ void advance_counter_kernel(int* c) { *c += 1; }
+
+hipError_t launch_set_counter(int* counter, int value, hipStream_t s) {
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, s, counter, value);
+  return hipGetLastError();
+}
+hipError_t launch_advance_counter(int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(advance_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_sum(const double* x, int n, double* out, hipStream_t s) {

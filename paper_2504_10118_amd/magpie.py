@@ -22,6 +22,7 @@ ERRORS = {
 }
 C64, C128 = 0, 1
 UPDATE_PROBE = 0x1
+GRAPH = 0x2
 
 _lib = None
 

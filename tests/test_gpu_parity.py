@@ -37,8 +37,8 @@ def test_forward_model(m):
     assert err <= 2e-6
 
 
-@pytest.mark.parametrize("m,levels", [(8, 1), (8, 4), (16, 2), (16, 5), (32, 1), (32, 2), (32, 3),
-                                      (64, 3), (64, 7), (128, 4), (128, 2)])
+@pytest.mark.parametrize("m,levels", [(8, 1), (8, 4), (16, 2), (16, 5), (32, 1), (32, 2), (32, 3), (32, 6),
+                                      (64, 3), (64, 4), (64, 7), (128, 4), (128, 2), (128, 6)])
 @pytest.mark.parametrize("batch", [1, 5, 10_000])
 def test_one_epoch_parity(m, levels, batch):
     rng = np.random.default_rng(1000 * m + 10 * levels + (batch % 97))
@@ -245,3 +245,23 @@ def test_intensities_not_sqrt_and_explicit_u():
     sd = np.sqrt((c.sd32.astype(np.float64) ** 2).astype(np.float32).astype(np.float64))
     zo = oracle.run_epochs(c.z0, c.Q, c.offs, sd, u, 3, [order], 6)
     assert c.rel(zg, zo) <= 1e-5
+
+
+def test_graph_replays_match_direct_launches():
+    """Epoch-graph replays (with eager work in between) equal direct launches bit for bit."""
+    from paper_2504_10118_amd import GRAPH
+    rng = np.random.default_rng(14)
+    c = Case(rng, 150, 160, 32, 7, noise=0.05)
+    outs = []
+    for flags in (GRAPH, 0):
+        g = c.gpu(3, 0.5)
+        g.set_flags(flags)
+        g.run_epochs(2, 16, seed=3)
+        g.objective()                      # eager work between replays
+        g.run_epochs(1, 16, seed=3)
+        _ = g.get_object()
+        g.run_epochs(2, 16, seed=3)
+        g.run_epochs(1, 40, seed=3)        # another minibatch size: a second graph
+        outs.append(g.get_object())
+        g.close()
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
