@@ -59,7 +59,7 @@ __all__ = [
     "magpie_sequential", "rpie_sequential", "stopping_statistic",
     "illumination", "error_paper", "error_relative", "splitmix64",
     "library_permutation", "batches", "full_batch_surrogate_minimiser",
-    "probe_update_step",
+    "probe_update_step", "blind_minibatch_step", "run_epochs_blind",
 ]
 
 M64 = (1 << 64) - 1
@@ -431,6 +431,27 @@ def probe_update_step(z, Q, offsets, sqrt_d, batch, beta):
     pos = den > 0
     Qn[pos] += num[pos] / den[pos]
     return Qn
+
+
+def blind_minibatch_step(z, Q, offsets, sqrt_d, alpha, levels: int, batch, beta, u=None):
+    """Object step (minibatch MAGPS) and probe step from the same (z, Q), applied together.
+
+    u = u^rPIE(Q, alpha) of the current probe unless a fixed u is given.
+    """
+    uu = u_rpie(Q, alpha) if u is None else u
+    znew = minibatch_step(z, Q, offsets, sqrt_d, uu, levels, batch)
+    Qnew = probe_update_step(z, Q, offsets, sqrt_d, batch, beta)
+    return znew, Qnew
+
+
+def run_epochs_blind(z0, Q0, offsets, sqrt_d, alpha, levels: int, orders, B: int, beta, u=None):
+    """Epochs of minibatch MAGPIE with the simultaneous probe step after every minibatch."""
+    z = np.array(z0, dtype=np.complex128, copy=True)
+    Q = np.array(Q0, dtype=np.complex128, copy=True)
+    for order in orders:
+        for batch in batches(order, B):
+            z, Q = blind_minibatch_step(z, Q, offsets, sqrt_d, alpha, levels, batch, beta, u)
+    return z, Q
 
 
 # --------------------------------------------------------------------------

@@ -116,6 +116,10 @@ struct magpie_ctx {
 
   float2* stage = nullptr;
   size_t stage_cap = 0;  // in float2
+  float2* pnum = nullptr;   // probe step partials (allocated with the staging when the flag is on)
+  float* pden = nullptr;
+  float* pmax = nullptr;
+  size_t pcap = 0;
   int* perm = nullptr;   // [E][N]
   int4* posrec = nullptr;  // [E][N] (k, row, col, 0) in processing order
   int* inv = nullptr;    // [E][N]
@@ -139,7 +143,7 @@ struct magpie_ctx {
   // by the kernels from epoch_ctr, which the graph's last node advances
   hipGraphExec_t gexec = nullptr;
   int g_batch = 0;
-  const void* g_key[3] = {nullptr, nullptr, nullptr};  // perm, inv, stage buffers it was built on
+  const void* g_key[4] = {nullptr, nullptr, nullptr, nullptr};  // buffers it was built on
   int* epoch_ctr = nullptr;
 };
 
@@ -307,6 +311,9 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->red);
   dev_free(c->epoch_ctr);
   dev_free(c->stage);
+  dev_free(c->pnum);
+  dev_free(c->pden);
+  dev_free(c->pmax);
   dev_free(c->perm);
   dev_free(c->posrec);
   dev_free(c->inv);
@@ -516,12 +523,30 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   if (need_stage > c->stage_cap) {
     MG_HIP(hipStreamSynchronize(c->stream));
     dev_free(c->stage);
+  dev_free(c->pnum);
+  dev_free(c->pden);
+  dev_free(c->pmax);
     rc = dev_alloc(&c->stage, need_stage);
     if (rc) {
       c->stage_cap = 0;
       return rc;
     }
     c->stage_cap = need_stage;
+  }
+  const bool probe_step = (c->flags & MAGPIE_UPDATE_PROBE) != 0;
+  if (probe_step && need_stage > c->pcap) {
+    MG_HIP(hipStreamSynchronize(c->stream));
+    dev_free(c->pnum);
+    dev_free(c->pden);
+    dev_free(c->pmax);
+    rc = dev_alloc(&c->pnum, need_stage);
+    if (!rc) rc = dev_alloc(&c->pden, need_stage);
+    if (!rc) rc = dev_alloc(&c->pmax, (size_t)B * mg::MAX_WAVES);
+    if (rc) {
+      c->pcap = 0;
+      return rc;
+    }
+    c->pcap = need_stage;
   }
   const size_t nperm = (size_t)n_epochs * N;
   if (nperm > c->perm_cap) {
@@ -598,6 +623,20 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   sa.levels = c->L;
   sa.lvl_a_off = c->lvl_a_off;
   sa.phi_part = c->step_part;
+  if (probe_step) {
+    sa.probe_num = c->pnum;
+    sa.probe_den = c->pden;
+    sa.probe_max = c->pmax;
+  }
+  const int nw = mg::step_waves(m);
+  // probe step after a minibatch's accumulation: apply, then rebuild the hierarchy
+  auto probe_tail = [&](int count) -> hipError_t {
+    hipError_t e = mg::launch_probe_apply(m, count, nw, c->pnum, c->pden, c->pmax, c->beta, c->q64, c->stream);
+    if (e == hipSuccess)
+      e = mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->w0f,
+                                     c->u0f, c->qf, c->lvl, c->scr_q, c->scr_u, c->stream);
+    return e;
+  };
   mg::AccumArgs aa{};
   aa.z = c->z;
   aa.n_rows = c->nr;
@@ -613,7 +652,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   const int n_tiles = c->tiles_x * c->tiles_y;
   const bool use_graph = !c->timing && (c->flags & MAGPIE_GRAPH);
   if (use_graph) {
-    const void* key[3] = {c->posrec, c->inv, c->stage};
+    const void* key[4] = {c->posrec, c->inv, c->stage, c->pnum};
     if (!c->gexec || c->g_batch != B || std::memcmp(key, c->g_key, sizeof(key)) != 0) {
       drop_graph(c);
       hipGraph_t graph = nullptr;
@@ -630,6 +669,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
         ce = mg::launch_step(m, mg::MODE_STEP, sa, c->stream);
         aa.batch_index = t;
         if (ce == hipSuccess) ce = mg::launch_accumulate(aa, n_tiles, c->stream);
+        if (ce == hipSuccess && probe_step) ce = probe_tail(sa.count);
       }
       if (ce == hipSuccess) ce = mg::launch_advance_counter(c->epoch_ctr, c->stream);
       hipError_t ee = hipStreamEndCapture(c->stream, &graph);
@@ -664,6 +704,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
       ti = timed_slot(c, 1, 0);
       MG_HIP(mg::launch_accumulate(aa, n_tiles, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
                                    ti >= 0 ? c->timed[ti].b : nullptr));
+      if (probe_step) MG_HIP(probe_tail(sa.count));
     }
   }
   c->epoch_index += (uint64_t)n_epochs;
@@ -764,8 +805,8 @@ int magpie_sync(magpie_ctx* c) {
 int magpie_set_flags(magpie_ctx* c, uint32_t flags, double beta) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
   if (flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_GRAPH)) return fail(MAGPIE_ERR_INVALID_ARG, "unknown flag");
-  if (flags & MAGPIE_UPDATE_PROBE) return fail(MAGPIE_ERR_UNSUPPORTED, "probe update is not available yet");
   if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(MAGPIE_ERR_INVALID_ARG, "beta must be finite, >= 0");
+  if (((c->flags ^ flags) & MAGPIE_UPDATE_PROBE) || beta != c->beta) drop_graph(c);
   c->flags = flags;
   c->beta = beta;
   return MAGPIE_OK;

@@ -30,8 +30,9 @@ struct StepArgs {
   double* phi_part;       // per-wave partials of Phi_k [N][MAX_WAVES] (nullable)
   double* gn_part;        // MODE_OBJECTIVE: per-wave partials of ||grad_k||^2 [N][MAX_WAVES]
   float* d_out;           // MODE_FORWARD: |F(Q z_k)|^2 natural order [N][m][m]
-  float2* probe_num;      // probe update numerator partials [count][m][m] (nullable)
-  float* probe_den;       // probe update denominator partials [count][m][m]
+  float2* probe_num;      // probe step: conj(z_k)(R_k - Q z_k) per position [count][m][m] (nullable)
+  float* probe_den;       // probe step: |z_k|^2 per position [count][m][m]
+  float* probe_max;       // probe step: per-wave max |z_k|^2 [count][MAX_WAVES]
 };
 
 struct AccumArgs {
@@ -75,6 +76,10 @@ hipError_t launch_reduce_parts(const double* parts, int n, int nw, int take_sqrt
 int step_waves(int m);
 hipError_t launch_set_counter(int* counter, int value, hipStream_t s);
 hipError_t launch_advance_counter(int* counter, hipStream_t s);
+// Q += sum_s num_s / (sum_s den_s + beta sum_s max_s) where the denominator is
+// positive (FP64, slots in order); q64 is the FP64 master probe.
+hipError_t launch_probe_apply(int m, int count, int nwaves, const float2* num, const float* den,
+                              const float* pmax, double beta, double2* q64, hipStream_t s);
 hipError_t launch_convert_c64_c128(const float2* src, double2* dst, size_t n, hipStream_t s);
 hipError_t launch_convert_c128_c64(const double2* src, float2* dst, size_t n, hipStream_t s);
 hipError_t launch_check_finite_c64(const float2* src, size_t n, int* bad_flag, hipStream_t s);

@@ -93,6 +93,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+template <int LANES>
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = LANES / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, LANES));
+  return v;
+}
+
 // MAGPS V-cycle through LDS for hierarchies whose coarse bins span several
 // waves.  On entry g0 is in T[y][x] (pitch P) and in v (thread (x, g) holds
 // rows RB*n1 + g).  Coarse grids (FP64) overwrite the start of the LDS tile.
@@ -408,6 +415,7 @@ __global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
 
     // ---- R_k = v / M^2; gradient g0 = conj(Q) (Q z_k - R_k) (eq. 2.2)
     constexpr float inv_m2 = 1.0f / (float)(M * M);
+    float pmx = 0.0f;
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
       float2 qq, zz;
@@ -418,7 +426,25 @@ __global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
         qq = bload2(qr, qvo, n1 * qso);
         zz = bload2(zr, zvo, n1 * zso);
       }
-      v[n1] = cmulc(qq, csub(cmul(qq, zz), cscale(v[n1], inv_m2)));
+      const float2 rk = cscale(v[n1], inv_m2);
+      if constexpr (MODE == MODE_STEP) {
+        if (a.probe_num) {
+          // probe step partials: conj(z_k)(R_k - Q z_k) and |z_k|^2
+          const float2 pn = cmulc(zz, csub(rk, cmul(qq, zz)));
+          const float pd = zz.x * zz.x + zz.y * zz.y;
+          const size_t e = (size_t)blockIdx.x * M * M + (size_t)(RB * n1 + g) * M + col;
+          a.probe_num[e] = pn;
+          a.probe_den[e] = pd;
+          pmx = fmaxf(pmx, pd);
+        }
+      }
+      v[n1] = cmulc(qq, csub(cmul(qq, zz), rk));
+    }
+    if constexpr (MODE == MODE_STEP) {
+      if (a.probe_num) {
+        const float wm = wave_max<LANES>(pmx);
+        if ((tid & 63) == 0) a.probe_max[(size_t)blockIdx.x * MAX_WAVES + wave] = wm;
+      }
     }
 
     if constexpr (MODE == MODE_OBJECTIVE) {
@@ -922,6 +948,40 @@ hipError_t launch_advance_counter(int* counter, hipStream_t s) {
 
 hipError_t launch_reduce_sum(const double* x, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+// Probe step (beyond the paper; simultaneous with the object step): per pixel,
+// FP64 sums over the minibatch's slots in order.
+__global__ __launch_bounds__(256) void probe_apply_kernel(int mm, int count, int nwaves, const float2* num,
+                                                          const float* den, const float* pmax, double beta,
+                                                          double2* q64) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= mm) return;
+  double nr = 0.0, ni = 0.0, dd = 0.0, mx = 0.0;
+  for (int s = 0; s < count; ++s) {
+    const float2 c = num[(size_t)s * mm + p];
+    nr += (double)c.x;
+    ni += (double)c.y;
+    dd += (double)den[(size_t)s * mm + p];
+    float w = 0.0f;
+    for (int j = 0; j < nwaves; ++j) w = fmaxf(w, pmax[(size_t)s * MAX_WAVES + j]);
+    mx += (double)w;
+  }
+  dd += beta * mx;
+  if (dd > 0.0) {
+    double2 q = q64[p];
+    q.x += nr / dd;
+    q.y += ni / dd;
+    q64[p] = q;
+  }
+}
+
+hipError_t launch_probe_apply(int m, int count, int nwaves, const float2* num, const float* den, const float* pmax,
+                              double beta, double2* q64, hipStream_t s) {
+  const int mm = m * m;
+  hipLaunchKernelGGL(probe_apply_kernel, dim3((mm + 255) / 256), dim3(256), 0, s, mm, count, nwaves, num, den,
+                     pmax, beta, q64);
   return hipGetLastError();
 }
 

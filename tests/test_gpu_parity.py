@@ -265,3 +265,27 @@ def test_graph_replays_match_direct_launches():
         outs.append(g.get_object())
         g.close()
     assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+
+
+@pytest.mark.parametrize("m,levels,batch", [(16, 3, 6), (64, 3, 5), (128, 2, 4)])
+def test_probe_update_parity(m, levels, batch):
+    """MAGPIE_UPDATE_PROBE: object and probe after one epoch vs the oracle's simultaneous steps."""
+    from paper_2504_10118_amd import UPDATE_PROBE
+    rng = np.random.default_rng(15 + m)
+    c = Case(rng, 2 * m + 9, 2 * m + 4, m, max(2, m // 3), noise=0.05)
+    Q0 = (c.Q32 * (1 + 0.1 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))))).astype(np.complex64)
+    order = rng.permutation(c.n_pos).astype(np.int32)
+    beta = 0.2
+    g = c.gpu(levels, 0.5)
+    g.set_probe(Q0)
+    g.set_flags(UPDATE_PROBE, beta)
+    g.run_epochs(1, batch, order=order[None])
+    zg = g.get_object().astype(np.complex128)
+    Qg = g.get_probe().astype(np.complex128)
+    g.close()
+    zo, Qo = oracle.run_epochs_blind(c.z0, Q0.astype(np.complex128), c.offs, c.sd, 0.5, levels, [order], batch, beta)
+    rz = c.rel(zg, zo)
+    rq = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo)
+    _print("probe update m", m, "object rel", rz, "probe rel", rq)
+    assert rz <= 1e-5
+    assert rq <= 1e-5
