@@ -203,6 +203,42 @@ int magpie_set_timing(magpie_ctx* ctx, int enable);
 int magpie_get_timing(magpie_ctx* ctx, double* step_ms, double* accum_ms, int64_t* step_launches,
                       int64_t* accum_launches, int64_t* positions);
 
+/*
+ * Kernel variants (no effect on the mathematics; results agree to FP32
+ * rounding).  The step kernel's FFT plan is the number of threads per 1-D
+ * transform (each thread then holds m / threads points); the accumulation
+ * kernel works on object tiles of 64 columns x tile_rows rows.
+ * magpie_list_plans writes the compiled plans of m (default first) and
+ * returns their count.  magpie_set_tuning (0 = keep) changes them, moving the
+ * loaded sqrt(d) to the new plan's order.  Errors: UNSUPPORTED, INVALID_ARG.
+ */
+int magpie_list_plans(int m, int32_t* threads_per_transform, int cap);
+int magpie_set_tuning(magpie_ctx* ctx, int threads_per_transform, int tile_rows);
+int magpie_get_tuning(magpie_ctx* ctx, int* threads_per_transform, int* tile_rows);
+
+/*
+ * Autotuner: times trial_epochs epochs of minibatch size `batch` with every
+ * compiled FFT plan (step kernel) and then every tile height (accumulation
+ * kernel), keeps the fastest of each, and restores the object and the epoch
+ * counter (the trials' updates are discarded).  Outputs (nullable): mean
+ * per-launch times in microseconds of the chosen variants.
+ * Errors: BAD_STATE, INVALID_ARG, HIP.
+ */
+int magpie_autotune(magpie_ctx* ctx, int batch, int trial_epochs, double* step_us, double* accum_us);
+
+/*
+ * Many independent reconstructions (contexts of any sizes on one device)
+ * advanced together: each context runs n_epochs epochs of minibatch MAGPIE
+ * with its own minibatch size batch[i] and its own seeded permutations
+ * (seed XOR its epoch counter), exactly as magpie_run_epochs would.  Rounds
+ * pair the t-th minibatches of all contexts still running: one step-kernel
+ * launch per FFT plan and one accumulation launch per tile height cover every
+ * context of the round.  Runs on the first context's stream (the others are
+ * joined with events) and synchronises it.  The probe step is not available
+ * here.  Errors: INVALID_ARG, BAD_STATE, UNSUPPORTED, OOM, HIP.
+ */
+int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, const int* batch, uint64_t seed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,8 @@ from .magpie import (  # noqa: F401
     LIB_PATH,
     Magpie,
     MagpieError,
+    list_plans,
     load_library,
     permutation,
+    run_epochs_multi,
 )

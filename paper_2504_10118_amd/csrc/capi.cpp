@@ -78,6 +78,8 @@ struct magpie_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int nr = 0, nc = 0, m = 0, L = 1;
+  int rb = 0;    // FFT plan of the step kernel (threads per 1-D transform)
+  int th = 16;   // accumulate tile height
   double alpha = 0.0;
   uint32_t flags = 0;
   double beta = 0.0;
@@ -145,6 +147,7 @@ struct magpie_ctx {
   int g_batch = 0;
   const void* g_key[4] = {nullptr, nullptr, nullptr, nullptr};  // buffers it was built on
   int* epoch_ctr = nullptr;
+  int g_rb = 0, g_th = 0;
 };
 
 namespace {
@@ -205,6 +208,40 @@ int timed_slot(magpie_ctx* c, int kind, int count) {
   return (int)c->timed.size() - 1;
 }
 
+// Per-tile ascending lists of overlapping positions (with their offsets) for
+// the context's tile height.
+int build_tiles(magpie_ctx* c) {
+  const int m = c->m, n_pos = c->n_pos;
+  const int32_t* offsets = c->h_offs.data();
+  dev_free(c->tile_ptr);
+  dev_free(c->tile_ent);
+  c->tiles_x = (c->nc + mg::ACC_TILE_W - 1) / mg::ACC_TILE_W;
+  c->tiles_y = (c->nr + c->th - 1) / c->th;
+  const int nt = c->tiles_x * c->tiles_y;
+  std::vector<std::vector<int>> lists(nt);
+  for (int k = 0; k < n_pos; ++k) {
+    const int r = offsets[2 * k], cc = offsets[2 * k + 1];
+    for (int ty = r / c->th; ty <= (r + m - 1) / c->th; ++ty)
+      for (int tx = cc / mg::ACC_TILE_W; tx <= (cc + m - 1) / mg::ACC_TILE_W; ++tx)
+        lists[ty * c->tiles_x + tx].push_back(k);
+  }
+  std::vector<int> ptr(nt + 1, 0);
+  std::vector<int4> pos;
+  for (int t = 0; t < nt; ++t) {
+    ptr[t + 1] = ptr[t] + (int)lists[t].size();
+    for (int k : lists[t]) pos.push_back(make_int4(k, offsets[2 * k], offsets[2 * k + 1], 0));
+  }
+  int rc = dev_alloc(&c->tile_ptr, nt + 1);
+  if (!rc) rc = dev_alloc(&c->tile_ent, std::max<size_t>(pos.size(), 1));
+  if (rc) return rc;
+  MG_HIP(hipMemcpyAsync(c->tile_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  if (!pos.empty())
+    MG_HIP(hipMemcpyAsync(c->tile_ent, pos.data(), pos.size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  return MAGPIE_OK;
+}
+
 int read_flag(magpie_ctx* c, int* out) {
   int h = 0;
   MG_HIP(hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -239,6 +276,7 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   c->m = m;
   c->L = n_levels;
   c->alpha = alpha;
+  c->rb = mg::default_plan(m);
   int rc = set_dev(c);
   if (rc) { delete c; return rc; }
   if (hip_stream) {
@@ -400,22 +438,6 @@ int magpie_set_positions(magpie_ctx* c, int n_pos, const int32_t* offsets) {
   MG_HIP(hipStreamSynchronize(c->stream));
   free_positions(c);
   const int m = c->m;
-  c->tiles_x = (c->nc + mg::ACC_TILE_W - 1) / mg::ACC_TILE_W;
-  c->tiles_y = (c->nr + mg::ACC_TILE_H - 1) / mg::ACC_TILE_H;
-  const int nt = c->tiles_x * c->tiles_y;
-  std::vector<std::vector<int>> lists(nt);
-  for (int k = 0; k < n_pos; ++k) {
-    const int r = offsets[2 * k], cc = offsets[2 * k + 1];
-    for (int ty = r / mg::ACC_TILE_H; ty <= (r + m - 1) / mg::ACC_TILE_H; ++ty)
-      for (int tx = cc / mg::ACC_TILE_W; tx <= (cc + m - 1) / mg::ACC_TILE_W; ++tx)
-        lists[ty * c->tiles_x + tx].push_back(k);
-  }
-  std::vector<int> ptr(nt + 1, 0);
-  std::vector<int4> pos;
-  for (int t = 0; t < nt; ++t) {
-    ptr[t + 1] = ptr[t] + (int)lists[t].size();
-    for (int k : lists[t]) pos.push_back(make_int4(k, offsets[2 * k], offsets[2 * k + 1], 0));
-  }
   rc = dev_alloc(&c->offs, n_pos);
   if (!rc) rc = dev_alloc(&c->sqrtd, (size_t)n_pos * m * m);
   if (!rc) rc = dev_alloc(&c->phi_step, n_pos);
@@ -424,21 +446,21 @@ int magpie_set_positions(magpie_ctx* c, int n_pos, const int32_t* offsets) {
   if (!rc) rc = dev_alloc(&c->step_part, (size_t)n_pos * mg::MAX_WAVES);
   if (!rc) rc = dev_alloc(&c->obj_part, (size_t)n_pos * mg::MAX_WAVES);
   if (!rc) rc = dev_alloc(&c->gn_part, (size_t)n_pos * mg::MAX_WAVES);
-  if (!rc) rc = dev_alloc(&c->tile_ptr, nt + 1);
-  if (!rc) rc = dev_alloc(&c->tile_ent, std::max<size_t>(pos.size(), 1));
   if (rc) {
     free_positions(c);
     return rc;
   }
   MG_HIP(hipMemcpyAsync(c->offs, offsets, (size_t)n_pos * sizeof(int2), hipMemcpyHostToDevice, c->stream));
-  MG_HIP(hipMemcpyAsync(c->tile_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-  if (!pos.empty())
-    MG_HIP(hipMemcpyAsync(c->tile_ent, pos.data(), pos.size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
   std::vector<double> nan((size_t)n_pos * mg::MAX_WAVES, std::nan(""));
   MG_HIP(hipMemcpyAsync(c->step_part, nan.data(), nan.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   MG_HIP(hipStreamSynchronize(c->stream));
   c->h_offs.assign(offsets, offsets + 2 * (size_t)n_pos);
   c->n_pos = n_pos;
+  rc = build_tiles(c);
+  if (rc) {
+    free_positions(c);
+    return rc;
+  }
   c->has_pos = true;
   return MAGPIE_OK;
 }
@@ -462,7 +484,7 @@ int magpie_load_intensities(magpie_ctx* c, const float* d, int is_sqrt, int on_d
     src = tmp;
   }
   MG_HIP(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
-  hipError_t e = mg::launch_permute_sqrt(c->m, c->n_pos, src, is_sqrt ? 1 : 0, c->sqrtd, c->flag, c->stream);
+  hipError_t e = mg::launch_permute_sqrt(c->m, c->rb, c->n_pos, src, is_sqrt ? 1 : 0, c->sqrtd, c->flag, c->stream);
   int bad = 0;
   rc = (e == hipSuccess) ? read_flag(c, &bad) : fail(MAGPIE_ERR_HIP, "permute kernel launch failed");
   dev_free(tmp);
@@ -508,17 +530,17 @@ int magpie_set_object(magpie_ctx* c, const void* z, int dtype, int on_device) {
   return MAGPIE_OK;
 }
 
-int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
+// Checks, staging capacity, and uploads of the epochs' permutations, inverse
+// permutations and position records (k, row, col) in processing order.
+static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
   if (!c->has_probe || !c->has_pos || !c->has_data)
     return fail(MAGPIE_ERR_BAD_STATE, "set probe, positions and intensities first");
   if (n_epochs < 0 || batch < 1) return fail(MAGPIE_ERR_INVALID_ARG, "n_epochs >= 0 and batch >= 1 required");
-  if (n_epochs == 0) return MAGPIE_OK;
   int rc = set_dev(c);
   if (rc) return rc;
   const int N = c->n_pos, m = c->m;
   const int B = std::min(batch, N);
-  const int nbatch = (N + B - 1) / B;
   const size_t need_stage = (size_t)B * m * m;
   if (need_stage > c->stage_cap) {
     MG_HIP(hipStreamSynchronize(c->stream));
@@ -609,6 +631,18 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   MG_HIP(hipMemcpyAsync(c->posrec, hr, nperm * sizeof(int4), hipMemcpyHostToDevice, c->stream));
   MG_HIP(hipEventRecord(c->pin_done, c->stream));
   c->pin_pending = true;
+  return MAGPIE_OK;
+}
+
+int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (n_epochs == 0 && batch >= 1) return MAGPIE_OK;
+  int rc = prepare_epochs(c, n_epochs, batch, seed, order);
+  if (rc) return rc;
+  const int N = c->n_pos, m = c->m;
+  const int B = std::min(batch, N);
+  const int nbatch = (N + B - 1) / B;
+  const bool probe_step = (c->flags & MAGPIE_UPDATE_PROBE) != 0;
 
   mg::StepArgs sa{};
   sa.z = c->z;
@@ -628,7 +662,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
     sa.probe_den = c->pden;
     sa.probe_max = c->pmax;
   }
-  const int nw = mg::step_waves(m);
+  const int nw = mg::step_waves(m, c->rb);
   // probe step after a minibatch's accumulation: apply, then rebuild the hierarchy
   auto probe_tail = [&](int count) -> hipError_t {
     hipError_t e = mg::launch_probe_apply(m, count, nw, c->pnum, c->pden, c->pmax, c->beta, c->q64, c->stream);
@@ -653,6 +687,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   const bool use_graph = !c->timing && (c->flags & MAGPIE_GRAPH);
   if (use_graph) {
     const void* key[4] = {c->posrec, c->inv, c->stage, c->pnum};
+    if (c->g_rb != c->rb || c->g_th != c->th) drop_graph(c);
     if (!c->gexec || c->g_batch != B || std::memcmp(key, c->g_key, sizeof(key)) != 0) {
       drop_graph(c);
       hipGraph_t graph = nullptr;
@@ -666,9 +701,9 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
       for (int t = 0; t < nbatch && ce == hipSuccess; ++t) {
         sa.pos = c->posrec + (size_t)t * B;
         sa.count = std::min(B, N - t * B);
-        ce = mg::launch_step(m, mg::MODE_STEP, sa, c->stream);
+        ce = mg::launch_step(m, c->rb, mg::MODE_STEP, sa, c->stream);
         aa.batch_index = t;
-        if (ce == hipSuccess) ce = mg::launch_accumulate(aa, n_tiles, c->stream);
+        if (ce == hipSuccess) ce = mg::launch_accumulate(aa, c->th, n_tiles, c->stream);
         if (ce == hipSuccess && probe_step) ce = probe_tail(sa.count);
       }
       if (ce == hipSuccess) ce = mg::launch_advance_counter(c->epoch_ctr, c->stream);
@@ -685,6 +720,8 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
         return fail(MAGPIE_ERR_HIP, std::string("epoch graph instantiate failed: ") + hipGetErrorString(ie));
       }
       c->g_batch = B;
+      c->g_rb = c->rb;
+      c->g_th = c->th;
       std::memcpy(c->g_key, key, sizeof(key));
     }
     MG_HIP(mg::launch_set_counter(c->epoch_ctr, 0, c->stream));
@@ -697,12 +734,12 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
       sa.pos = c->posrec + (size_t)e * N + (size_t)t * B;
       sa.count = std::min(B, N - t * B);
       int ti = timed_slot(c, 0, sa.count);
-      MG_HIP(mg::launch_step(m, mg::MODE_STEP, sa, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
+      MG_HIP(mg::launch_step(m, c->rb, mg::MODE_STEP, sa, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
                              ti >= 0 ? c->timed[ti].b : nullptr));
       aa.inv = c->inv + (size_t)e * N;
       aa.batch_index = t;
       ti = timed_slot(c, 1, 0);
-      MG_HIP(mg::launch_accumulate(aa, n_tiles, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
+      MG_HIP(mg::launch_accumulate(aa, c->th, n_tiles, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
                                    ti >= 0 ? c->timed[ti].b : nullptr));
       if (probe_step) MG_HIP(probe_tail(sa.count));
     }
@@ -732,8 +769,8 @@ int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {
   sa.lvl_a_off = c->lvl_a_off;
   sa.phi_part = c->obj_part;
   sa.gn_part = c->gn_part;
-  const int nw = mg::step_waves(c->m);
-  MG_HIP(mg::launch_step(c->m, mg::MODE_OBJECTIVE, sa, c->stream));
+  const int nw = mg::step_waves(c->m, c->rb);
+  MG_HIP(mg::launch_step(c->m, c->rb, mg::MODE_OBJECTIVE, sa, c->stream));
   MG_HIP(mg::launch_reduce_parts(c->obj_part, c->n_pos, nw, 0, c->phi_obj, c->red, c->stream));
   MG_HIP(mg::launch_reduce_parts(c->gn_part, c->n_pos, nw, 1, c->gnorm, c->red + 1, c->stream));
   double h[2];
@@ -750,7 +787,7 @@ int magpie_get_step_phi(magpie_ctx* c, double* phi_k) {
   if (!c->has_pos) return fail(MAGPIE_ERR_BAD_STATE, "no positions");
   int rc = set_dev(c);
   if (rc) return rc;
-  MG_HIP(mg::launch_reduce_parts(c->step_part, c->n_pos, mg::step_waves(c->m), 0, c->phi_step, nullptr, c->stream));
+  MG_HIP(mg::launch_reduce_parts(c->step_part, c->n_pos, mg::step_waves(c->m, c->rb), 0, c->phi_step, nullptr, c->stream));
   MG_HIP(hipMemcpyAsync(phi_k, c->phi_step, (size_t)c->n_pos * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   MG_HIP(hipStreamSynchronize(c->stream));
   return MAGPIE_OK;
@@ -849,7 +886,7 @@ int magpie_forward_model(magpie_ctx* c, const void* z, int z_on_device, float* d
   sa.perm = nullptr;
   sa.count = c->n_pos;
   sa.d_out = dst;
-  hipError_t e = mg::launch_step(c->m, mg::MODE_FORWARD, sa, c->stream);
+  hipError_t e = mg::launch_step(c->m, c->rb, mg::MODE_FORWARD, sa, c->stream);
   if (e == hipSuccess && !out_on_device)
     e = hipMemcpyAsync(d_out, dt, nd * sizeof(float), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -889,6 +926,312 @@ int magpie_get_timing(magpie_ctx* c, double* step_ms, double* accum_ms, int64_t*
   *step_launches = nl[0];
   *accum_launches = nl[1];
   *positions = pos;
+  return MAGPIE_OK;
+}
+
+int magpie_list_plans(int m, int32_t* threads_per_transform, int cap) {
+  int tmp[8];
+  const int n = mg::plans_for(m, tmp, 8);
+  if (n == 0) return fail(MAGPIE_ERR_UNSUPPORTED, "no plan for this m");
+  if (threads_per_transform)
+    for (int i = 0; i < n && i < cap; ++i) threads_per_transform[i] = tmp[i];
+  return n;
+}
+
+int magpie_get_tuning(magpie_ctx* c, int* threads_per_transform, int* tile_rows) {
+  if (!c || !threads_per_transform || !tile_rows) return fail(MAGPIE_ERR_INVALID_ARG, "NULL argument");
+  *threads_per_transform = c->rb;
+  *tile_rows = c->th;
+  return MAGPIE_OK;
+}
+
+int magpie_set_tuning(magpie_ctx* c, int threads_per_transform, int tile_rows) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  const int rb = threads_per_transform ? threads_per_transform : c->rb;
+  const int th = tile_rows ? tile_rows : c->th;
+  if (!mg::plan_valid(c->m, rb)) return fail(MAGPIE_ERR_UNSUPPORTED, "no such FFT plan for this m");
+  if (!mg::tile_valid(th)) return fail(MAGPIE_ERR_UNSUPPORTED, "tile rows must be 8, 16 or 32");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  if (rb != c->rb) {
+    if (c->has_data) {
+      // move sqrt(d) from the old plan's order to the new one through natural order
+      const size_t cnt = (size_t)c->n_pos * c->m * c->m;
+      float* nat = nullptr;
+      rc = dev_alloc(&nat, cnt);
+      if (rc) return rc;
+      hipError_t e = mg::launch_unpermute_sqrt(c->m, c->rb, c->n_pos, c->sqrtd, nat, c->stream);
+      if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, sizeof(int), c->stream);
+      if (e == hipSuccess) e = mg::launch_permute_sqrt(c->m, rb, c->n_pos, nat, 1, c->sqrtd, c->flag, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      dev_free(nat);
+      if (e != hipSuccess) return fail(MAGPIE_ERR_HIP, std::string("re-layout of sqrt(d): ") + hipGetErrorString(e));
+    }
+    c->rb = rb;
+    if (c->has_pos) {
+      std::vector<double> nan((size_t)c->n_pos * mg::MAX_WAVES, std::nan(""));
+      MG_HIP(hipMemcpy(c->step_part, nan.data(), nan.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    drop_graph(c);
+  }
+  if (th != c->th) {
+    c->th = th;
+    if (c->has_pos) {
+      rc = build_tiles(c);
+      if (rc) return rc;
+    }
+    drop_graph(c);
+  }
+  return MAGPIE_OK;
+}
+
+int magpie_autotune(magpie_ctx* c, int batch, int trial_epochs, double* step_us, double* accum_us) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (!c->has_probe || !c->has_pos || !c->has_data)
+    return fail(MAGPIE_ERR_BAD_STATE, "set probe, positions and intensities first");
+  if (batch < 1 || trial_epochs < 1) return fail(MAGPIE_ERR_INVALID_ARG, "batch and trial_epochs must be >= 1");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  // the trials run real epochs: keep the object, epoch counter and flags, restore them after
+  const size_t nz = (size_t)c->nr * c->nc;
+  float2* zsave = nullptr;
+  rc = dev_alloc(&zsave, nz);
+  if (rc) return rc;
+  MG_HIP(hipMemcpyAsync(zsave, c->z, nz * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+  const uint64_t ep = c->epoch_index;
+  const uint32_t flags = c->flags;
+  const bool timing = c->timing;
+  c->flags = flags & ~MAGPIE_UPDATE_PROBE;
+  c->timing = true;
+  double* sm = nullptr;
+  double am = 0.0, best_step = 1e300, best_acc = 1e300;
+  int best_rb = c->rb, best_th = c->th;
+  auto trial = [&](double* s_us, double* a_us) -> int {
+    double s1, a1;
+    int64_t sl, al, np;
+    int r = magpie_get_timing(c, &s1, &a1, &sl, &al, &np);   // reset
+    if (!r) r = magpie_run_epochs(c, trial_epochs, batch, 0x5eedull, nullptr);
+    if (!r) r = magpie_get_timing(c, &s1, &a1, &sl, &al, &np);
+    if (!r) {
+      *s_us = s1 * 1e3 / std::max<int64_t>(1, sl);
+      *a_us = a1 * 1e3 / std::max<int64_t>(1, al);
+    }
+    return r;
+  };
+  (void)sm;
+  (void)am;
+  int rbs[8];
+  const int nplans = mg::plans_for(c->m, rbs, 8);
+  for (int i = 0; i < nplans && !rc; ++i) {
+    rc = magpie_set_tuning(c, rbs[i], 0);
+    double su = 0, au = 0;
+    if (!rc) rc = trial(&su, &au);
+    if (!rc && su < best_step) {
+      best_step = su;
+      best_rb = rbs[i];
+    }
+  }
+  const int ths[3] = {8, 16, 32};
+  for (int i = 0; i < 3 && !rc; ++i) {
+    rc = magpie_set_tuning(c, best_rb, ths[i]);
+    double su = 0, au = 0;
+    if (!rc) rc = trial(&su, &au);
+    if (!rc && au < best_acc) {
+      best_acc = au;
+      best_th = ths[i];
+    }
+  }
+  c->timing = timing;
+  c->flags = flags;
+  if (!rc) rc = magpie_set_tuning(c, best_rb, best_th);
+  hipError_t e = hipMemcpyAsync(c->z, zsave, nz * sizeof(float2), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(zsave);
+  c->epoch_index = ep;
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(MAGPIE_ERR_HIP, "autotune restore failed");
+  if (step_us) *step_us = best_step;
+  if (accum_us) *accum_us = best_acc;
+  return MAGPIE_OK;
+}
+
+int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, const int* batch, uint64_t seed) {
+  if (!ctxs || count < 1 || !batch) return fail(MAGPIE_ERR_INVALID_ARG, "contexts and batch sizes required");
+  if (n_epochs < 0) return fail(MAGPIE_ERR_INVALID_ARG, "n_epochs >= 0 required");
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context in list");
+    if (ctxs[i]->device != ctxs[0]->device) return fail(MAGPIE_ERR_INVALID_ARG, "contexts on different devices");
+    if (ctxs[i]->flags & MAGPIE_UPDATE_PROBE)
+      return fail(MAGPIE_ERR_UNSUPPORTED, "the probe step is not available in multi-context runs");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(MAGPIE_ERR_INVALID_ARG, "a context appears twice");
+  }
+  if (n_epochs == 0) return MAGPIE_OK;
+  magpie_ctx* c0 = ctxs[0];
+  int rc = set_dev(c0);
+  if (rc) return rc;
+  hipStream_t st = c0->stream;
+  // every context's earlier work precedes this run (its permutation uploads are
+  // enqueued on its own stream by prepare_epochs, so join afterwards)
+  for (int i = 0; i < count; ++i) {
+    rc = prepare_epochs(ctxs[i], n_epochs, batch[i], seed, nullptr);
+    if (rc) return rc;
+  }
+  std::vector<hipEvent_t> evs;
+  auto join = [&](hipStream_t from, hipStream_t to) -> int {
+    if (from == to) return MAGPIE_OK;
+    hipEvent_t e;
+    MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    evs.push_back(e);
+    MG_HIP(hipEventRecord(e, from));
+    MG_HIP(hipStreamWaitEvent(to, e, 0));
+    return MAGPIE_OK;
+  };
+  auto cleanup = [&]() {
+    for (auto e : evs) hipEventDestroy(e);
+  };
+  for (int i = 1; i < count && !rc; ++i) rc = join(ctxs[i]->stream, st);
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  // groups: step kernel by plan (m, rb), accumulation by tile height
+  struct Group {
+    int m, rb;
+    std::vector<int> members;
+  };
+  std::vector<Group> sgroups;
+  std::vector<Group> agroups;   // m field holds th
+  for (int i = 0; i < count; ++i) {
+    magpie_ctx* c = ctxs[i];
+    bool found = false;
+    for (auto& g : sgroups)
+      if (g.m == c->m && g.rb == c->rb) {
+        g.members.push_back(i);
+        found = true;
+      }
+    if (!found) sgroups.push_back({c->m, c->rb, {i}});
+    found = false;
+    for (auto& g : agroups)
+      if (g.m == c->th) {
+        g.members.push_back(i);
+        found = true;
+      }
+    if (!found) agroups.push_back({c->th, 0, {i}});
+  }
+  std::vector<int> B(count), nb(count), T(count);
+  int R = 0;
+  for (int i = 0; i < count; ++i) {
+    B[i] = std::min(batch[i], ctxs[i]->n_pos);
+    nb[i] = (ctxs[i]->n_pos + B[i] - 1) / B[i];
+    T[i] = n_epochs * nb[i];
+    R = std::max(R, T[i]);
+  }
+  // descriptors for every round: step args per plan group, accum args per tile group
+  std::vector<mg::StepArgs> hs((size_t)R * count);
+  std::vector<mg::AccumArgs> ha((size_t)R * count);
+  std::vector<int> s_max((size_t)R * sgroups.size(), 0), a_max((size_t)R * agroups.size(), 0);
+  for (int r = 0; r < R; ++r) {
+    size_t base = (size_t)r * count;
+    int gi = 0;
+    size_t off = 0;
+    for (auto& g : sgroups) {
+      for (size_t j = 0; j < g.members.size(); ++j) {
+        const int i = g.members[j];
+        magpie_ctx* c = ctxs[i];
+        mg::StepArgs a{};
+        a.z = c->z;
+        a.n_rows = c->nr;
+        a.n_cols = c->nc;
+        a.q = c->qf;
+        a.sqrtd = c->sqrtd;
+        a.offs = c->offs;
+        a.stage = c->stage;
+        a.u0f = c->u0f;
+        a.lvl = c->lvl;
+        a.levels = c->L;
+        a.lvl_a_off = c->lvl_a_off;
+        a.phi_part = c->step_part;
+        if (r < T[i]) {
+          const int e = r / nb[i], t = r % nb[i];
+          a.pos = c->posrec + (size_t)e * c->n_pos + (size_t)t * B[i];
+          a.count = std::min(B[i], c->n_pos - t * B[i]);
+        } else {
+          a.count = 0;
+        }
+        s_max[(size_t)r * sgroups.size() + gi] = std::max(s_max[(size_t)r * sgroups.size() + gi], a.count);
+        hs[base + off + j] = a;
+      }
+      off += g.members.size();
+      ++gi;
+    }
+    gi = 0;
+    off = 0;
+    for (auto& g : agroups) {
+      for (size_t j = 0; j < g.members.size(); ++j) {
+        const int i = g.members[j];
+        magpie_ctx* c = ctxs[i];
+        mg::AccumArgs a{};
+        a.z = c->z;
+        a.n_rows = c->nr;
+        a.n_cols = c->nc;
+        a.m = c->m;
+        a.tiles_x = c->tiles_x;
+        a.tile_ptr = c->tile_ptr;
+        a.tile_ent = c->tile_ent;
+        a.stage = c->stage;
+        a.offs = c->offs;
+        a.w0f = c->w0f;
+        a.batch = B[i];
+        if (r < T[i]) {
+          const int e = r / nb[i], t = r % nb[i];
+          a.inv = c->inv + (size_t)e * c->n_pos;
+          a.batch_index = t;
+          a.n_tiles = c->tiles_x * c->tiles_y;
+        } else {
+          a.inv = c->inv;
+          a.n_tiles = 0;
+        }
+        a_max[(size_t)r * agroups.size() + gi] = std::max(a_max[(size_t)r * agroups.size() + gi], a.n_tiles);
+        ha[base + off + j] = a;
+      }
+      off += g.members.size();
+      ++gi;
+    }
+  }
+  mg::StepArgs* ds = nullptr;
+  mg::AccumArgs* da = nullptr;
+  rc = dev_alloc(&ds, hs.size());
+  if (!rc) rc = dev_alloc(&da, ha.size());
+  hipError_t e = hipSuccess;
+  if (!rc) e = hipMemcpyAsync(ds, hs.data(), hs.size() * sizeof(mg::StepArgs), hipMemcpyHostToDevice, st);
+  if (!rc && e == hipSuccess)
+    e = hipMemcpyAsync(da, ha.data(), ha.size() * sizeof(mg::AccumArgs), hipMemcpyHostToDevice, st);
+  for (int r = 0; r < R && !rc && e == hipSuccess; ++r) {
+    size_t off = 0;
+    for (size_t gi = 0; gi < sgroups.size() && e == hipSuccess; ++gi) {
+      const auto& g = sgroups[gi];
+      e = mg::launch_step_multi(g.m, g.rb, ds + (size_t)r * count + off, (int)g.members.size(),
+                                s_max[(size_t)r * sgroups.size() + gi], st);
+      off += g.members.size();
+    }
+    off = 0;
+    for (size_t gi = 0; gi < agroups.size() && e == hipSuccess; ++gi) {
+      const auto& g = agroups[gi];
+      e = mg::launch_accumulate_multi(g.m, da + (size_t)r * count + off, (int)g.members.size(),
+                                      a_max[(size_t)r * agroups.size() + gi], st);
+      off += g.members.size();
+    }
+  }
+  // the descriptor buffers are freed once the launches that read them are done
+  if (e == hipSuccess && !rc) e = hipStreamSynchronize(st);
+  dev_free(ds);
+  dev_free(da);
+  if (!rc && e != hipSuccess) rc = fail(MAGPIE_ERR_HIP, std::string("multi-context run: ") + hipGetErrorString(e));
+  for (int i = 1; i < count && !rc; ++i) rc = join(st, ctxs[i]->stream);
+  cleanup();
+  if (rc) return rc;
+  for (int i = 0; i < count; ++i) ctxs[i]->epoch_index += (uint64_t)n_epochs;
   return MAGPIE_OK;
 }
 

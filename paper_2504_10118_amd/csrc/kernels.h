@@ -39,6 +39,7 @@ struct AccumArgs {
   float2* z;              // object, updated in place
   int n_rows, n_cols, m;
   int tiles_x;            // number of 64-wide tile columns
+  int n_tiles;
   const int* tile_ptr;    // CSR over tiles: positions overlapping each tile, ascending
   const int4* tile_ent;   // (k, row, col, 0) of each overlapping position
   const int* inv;         // position -> index in this epoch's permutation
@@ -51,29 +52,39 @@ struct AccumArgs {
 };
 
 constexpr int ACC_TILE_W = 64;
-constexpr int ACC_TILE_H = 16;
 constexpr int ACC_THREADS = 256;
 
-int step_threads(int m);                 // workgroup size of the per-position kernel
-size_t step_lds_bytes(int m);            // dynamic LDS of the per-position kernel
+// FFT plans (m, rb): rb threads per 1-D transform.  plans_for lists the
+// compiled plans of m, default first.
+bool plan_valid(int m, int rb);
+int default_plan(int m);
+int plans_for(int m, int* rbs, int cap);
+bool tile_valid(int th);                    // accumulate tile heights: 8, 16, 32
+int step_threads(int m, int rb);            // workgroup size of the per-position kernel
+int step_waves(int m, int rb);
+size_t step_lds_bytes(int m, int rb);       // dynamic LDS of the per-position kernel
 
 hipError_t init_twiddles(hipStream_t s);
 // ev0/ev1 (nullable): events the dispatch itself records at kernel start and end
-hipError_t launch_step(int m, int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0 = nullptr,
+hipError_t launch_step(int m, int rb, int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
-hipError_t launch_accumulate(const AccumArgs& a, int n_tiles, hipStream_t s, hipEvent_t ev0 = nullptr,
+hipError_t launch_accumulate(const AccumArgs& a, int th, int n_tiles, hipStream_t s, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);
+// one launch over several contexts: grid (max_count | max_tiles) x n_ctx,
+// descriptor y describes context y for this round (count / n_tiles 0 = idle)
+hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s);
+hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s);
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given,
                                   const double2* q64, double* u0, double* w0, float* w0f, float* u0f,
                                   float2* qf, double* lvl, double2* scr_q, double* scr_u,
                                   hipStream_t s);
-hipError_t launch_permute_sqrt(int m, int n_pos, const float* src, int is_sqrt, float* dst,
+hipError_t launch_permute_sqrt(int m, int rb, int n_pos, const float* src, int is_sqrt, float* dst,
                                int* bad_flag, hipStream_t s);
+hipError_t launch_unpermute_sqrt(int m, int rb, int n_pos, const float* src, float* dst, hipStream_t s);
 hipError_t launch_reduce_sum(const double* x, int n, double* out, hipStream_t s);
 // per position: sum of nw partials (optionally sqrt), then a fixed-order total
 hipError_t launch_reduce_parts(const double* parts, int n, int nw, int take_sqrt, double* per_pos,
                                double* total, hipStream_t s);
-int step_waves(int m);
 hipError_t launch_set_counter(int* counter, int value, hipStream_t s);
 hipError_t launch_advance_counter(int* counter, hipStream_t s);
 // Q += sum_s num_s / (sum_s den_s + beta sum_s max_s) where the denominator is

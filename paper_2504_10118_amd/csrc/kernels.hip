@@ -5,7 +5,7 @@
 //                       (Definition 2.1), inverse FFT, gradient
 //                       g0 = conj(Q)(Q z_k - R_k) (eq. 2.2), MAGPS V-cycle in
 //                       gradient form (Alg 3 / eq. 4.6), write c_k = w0 * dz_k.
-// accumulate_kernel     one workgroup per 64 x 16 object tile: fixed-order sum
+// accumulate_kernel     one workgroup per 64 x TH object tile: fixed-order sum
 //                       of the overlapping c_k and of w0 (FP64), z += N / D.
 // level_constants_kernel FP64 probe hierarchy (eq. 4.4) and per-level
 //                       coefficients of the gradient-form V-cycle.
@@ -47,14 +47,13 @@ hipError_t init_twiddles(hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int M> struct Plan;
-// RB: threads per 1-D transform; RA: points per thread; PAD: row padding of
-// the LDS transpose tile (float2 units).
-template <> struct Plan<8>   { static constexpr int RB = 2, RA = 4, PAD = 2; };
-template <> struct Plan<16>  { static constexpr int RB = 4, RA = 4, PAD = 2; };
-template <> struct Plan<32>  { static constexpr int RB = 4, RA = 8, PAD = 2; };
-template <> struct Plan<64>  { static constexpr int RB = 8, RA = 8, PAD = 2; };
-template <> struct Plan<128> { static constexpr int RB = 8, RA = 16, PAD = 2; };
+// FFT plan: RB threads per 1-D transform, RA = M / RB points per thread
+// (RA >= RB), PAD = row padding of the LDS transpose tile in float2.
+template <int M, int RB_>
+struct Plan {
+  static constexpr int RB = RB_, RA = M / RB_, PAD = 2;
+  static_assert(RA >= RB && RA % RB == 0, "stage B needs RA a multiple of RB");
+};
 
 template <int M>
 __device__ __forceinline__ float2 twiddle(int j) {
@@ -190,10 +189,10 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
 // or its own row slice (row passes) of the transpose tile T, so the register
 // stages exchange data through LDS without workgroup barriers; only the two
 // transposes (forward and back) synchronise the workgroup.
-template <int M, int MODE>
-__global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
-  constexpr int RB = Plan<M>::RB, RA = Plan<M>::RA;
-  constexpr int TPB = M * RB, CB = RA / RB, P = M + Plan<M>::PAD;
+template <int M, int RBv, int MODE>
+__device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
+  constexpr int RB = Plan<M, RBv>::RB, RA = Plan<M, RBv>::RA;
+  constexpr int TPB = M * RB, CB = RA / RB, P = M + Plan<M, RBv>::PAD;
   constexpr int LANES = TPB < 64 ? TPB : 64;
   constexpr int CPW = LANES / RB;
   constexpr int LRB = ilog2c(RB), LW = ilog2c(CPW);
@@ -211,11 +210,11 @@ __global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
   int k;
   int2 off;
   if (a.pos) {
-    const int4 pr = a.pos[eoff + blockIdx.x];
+    const int4 pr = a.pos[eoff + wg];
     k = pr.x;
     off = make_int2(pr.y, pr.z);
   } else {
-    k = a.perm ? a.perm[eoff + blockIdx.x] : (int)blockIdx.x;
+    k = a.perm ? a.perm[eoff + wg] : (int)wg;
     off = a.offs[k];
   }
 
@@ -432,7 +431,7 @@ __global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
           // probe step partials: conj(z_k)(R_k - Q z_k) and |z_k|^2
           const float2 pn = cmulc(zz, csub(rk, cmul(qq, zz)));
           const float pd = zz.x * zz.x + zz.y * zz.y;
-          const size_t e = (size_t)blockIdx.x * M * M + (size_t)(RB * n1 + g) * M + col;
+          const size_t e = (size_t)wg * M * M + (size_t)(RB * n1 + g) * M + col;
           a.probe_num[e] = pn;
           a.probe_den[e] = pd;
           pmx = fmaxf(pmx, pd);
@@ -443,7 +442,7 @@ __global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
     if constexpr (MODE == MODE_STEP) {
       if (a.probe_num) {
         const float wm = wave_max<LANES>(pmx);
-        if ((tid & 63) == 0) a.probe_max[(size_t)blockIdx.x * MAX_WAVES + wave] = wm;
+        if ((tid & 63) == 0) a.probe_max[(size_t)wg * MAX_WAVES + wave] = wm;
       }
     }
 
@@ -455,8 +454,8 @@ __global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
       if ((tid & 63) == 0) a.gn_part[(size_t)k * MAX_WAVES + wave] = tot;
       return;
     } else {
-      float2* outp = a.stage + (size_t)blockIdx.x * M * M + col;
-      const rsrc_t outr = make_rsrc(a.stage + (size_t)blockIdx.x * M * M, (unsigned)(M * M * sizeof(float2)));
+      float2* outp = a.stage + (size_t)wg * M * M + col;
+      const rsrc_t outr = make_rsrc(a.stage + (size_t)wg * M * M, (unsigned)(M * M * sizeof(float2)));
       const int ovo = (g * M + col) * (int)sizeof(float2);
       const int L = a.levels;
       if (L <= 1) {
@@ -472,7 +471,11 @@ __global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
         // coefficients: e_1 = sum_l A_l g^_l with A_l = -r_l prod_{j<l} rho_j.
         // Chunks of NC register rows: while every restriction pairs rows across
         // lanes (LW <= log2 RB) the rows n1 are independent.
-        constexpr int NC = (LW > LRB) ? RA : (M >= 128 ? 2 : (RA < 4 ? RA : 4));
+        // in-thread row pairs (levels above log2 RB) stay inside aligned chunks of NC
+        constexpr int NCB = (M >= 128) ? 2 : 4;
+        constexpr int NCP = (LW > LRB) ? (1 << (LW - LRB)) : 1;
+        constexpr int NC0 = NCP > NCB ? NCP : NCB;
+        constexpr int NC = NC0 < RA ? NC0 : RA;
         const double* Abase = a.lvl + a.lvl_a_off;
 #pragma unroll
         for (int n0 = 0; n0 < RA; n0 += NC) {
@@ -543,93 +546,121 @@ __global__ __launch_bounds__(M * Plan<M>::RB) void step_kernel(StepArgs a) {
   }
 }
 
-template <int M, int MODE>
-static void launch_step_mode(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  constexpr int TPB = M * Plan<M>::RB;
-  const size_t lds = step_lds_bytes(M);
-  hipFuncSetAttribute((const void*)step_kernel<M, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (ev0)
-    hipExtLaunchKernelGGL((step_kernel<M, MODE>), dim3(a.count), dim3(TPB), lds, s, ev0, ev1, 0, a);
-  else
-    hipLaunchKernelGGL((step_kernel<M, MODE>), dim3(a.count), dim3(TPB), lds, s, a);
+
+template <int M, int RBv, int MODE>
+__global__ __launch_bounds__(M * RBv) void step_kernel(StepArgs a) {
+  step_body<M, RBv, MODE>(a, (int)blockIdx.x);
 }
 
-template <int M>
-static hipError_t launch_step_m(int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (a.count <= 0) return hipSuccess;
-  switch (mode) {
-    case MODE_STEP: launch_step_mode<M, MODE_STEP>(a, s, ev0, ev1); break;
-    case MODE_OBJECTIVE: launch_step_mode<M, MODE_OBJECTIVE>(a, s, ev0, ev1); break;
-    case MODE_FORWARD: launch_step_mode<M, MODE_FORWARD>(a, s, ev0, ev1); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+// Many reconstructions in one launch: blockIdx.y selects a context's arguments
+// for this round (descs), blockIdx.x a position of its minibatch.
+template <int M, int RBv>
+__global__ __launch_bounds__(M * RBv) void step_multi_kernel(const StepArgs* descs) {
+  const StepArgs& a = descs[blockIdx.y];
+  if ((int)blockIdx.x >= a.count) return;
+  step_body<M, RBv, MODE_STEP>(a, (int)blockIdx.x);
 }
 
-int step_threads(int m) {
-  switch (m) {
-    case 8: return 8 * Plan<8>::RB;
-    case 16: return 16 * Plan<16>::RB;
-    case 32: return 32 * Plan<32>::RB;
-    case 64: return 64 * Plan<64>::RB;
-    case 128: return 128 * Plan<128>::RB;
-    default: return 0;
-  }
-}
-
-template <int M>
+template <int M, int RB>
 static size_t lds_bytes_m() {
-  constexpr int RB = Plan<M>::RB, TPB = M * RB, P = M + Plan<M>::PAD;
+  constexpr int TPB = M * RB, P = M + Plan<M, RB>::PAD;
   constexpr int LW = ilog2c((TPB < 64 ? TPB : 64) / RB);
   size_t b = (size_t)M * P * sizeof(float2);
   if (M <= 64) b += (size_t)cst_count_max(M, LW) * sizeof(double);
   return b;
 }
 
-size_t step_lds_bytes(int m) {
+template <int M, int RB, int MODE>
+static void launch_step_mode(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  constexpr int TPB = M * RB;
+  const size_t lds = lds_bytes_m<M, RB>();
+  hipFuncSetAttribute((const void*)step_kernel<M, RB, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (ev0)
+    hipExtLaunchKernelGGL((step_kernel<M, RB, MODE>), dim3(a.count), dim3(TPB), lds, s, ev0, ev1, 0, a);
+  else
+    hipLaunchKernelGGL((step_kernel<M, RB, MODE>), dim3(a.count), dim3(TPB), lds, s, a);
+}
+
+template <int M, int RB>
+static hipError_t launch_step_p(int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (a.count <= 0) return hipSuccess;
+  switch (mode) {
+    case MODE_STEP: launch_step_mode<M, RB, MODE_STEP>(a, s, ev0, ev1); break;
+    case MODE_OBJECTIVE: launch_step_mode<M, RB, MODE_OBJECTIVE>(a, s, ev0, ev1); break;
+    case MODE_FORWARD: launch_step_mode<M, RB, MODE_FORWARD>(a, s, ev0, ev1); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// The compiled plans: (M, RB).  The first plan listed for an M is its default.
+#define MG_FOR_EACH_PLAN(X) X(8, 2) X(16, 4) X(16, 2) X(32, 4) X(32, 2) X(64, 8) X(64, 4) X(128, 8)
+
+bool plan_valid(int m, int rb) {
+#define MG_PV(MM, RR) if (m == MM && rb == RR) return true;
+  MG_FOR_EACH_PLAN(MG_PV)
+#undef MG_PV
+  return false;
+}
+
+int default_plan(int m) {
   switch (m) {
-    case 8: return lds_bytes_m<8>();
-    case 16: return lds_bytes_m<16>();
-    case 32: return lds_bytes_m<32>();
-    case 64: return lds_bytes_m<64>();
-    case 128: return lds_bytes_m<128>();
+    case 8: return 2;
+    case 16: return 4;
+    case 32: return 4;
+    case 64: return 8;
+    case 128: return 8;
     default: return 0;
   }
 }
 
-hipError_t launch_step(int m, int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  switch (m) {
-    case 8: return launch_step_m<8>(mode, a, s, ev0, ev1);
-    case 16: return launch_step_m<16>(mode, a, s, ev0, ev1);
-    case 32: return launch_step_m<32>(mode, a, s, ev0, ev1);
-    case 64: return launch_step_m<64>(mode, a, s, ev0, ev1);
-    case 128: return launch_step_m<128>(mode, a, s, ev0, ev1);
-    default: return hipErrorInvalidValue;
-  }
+int plans_for(int m, int* rbs, int cap) {
+  int n = 0;
+#define MG_PL(MM, RR) if (m == MM && n < cap) rbs[n++] = RR;
+  MG_FOR_EACH_PLAN(MG_PL)
+#undef MG_PL
+  return n;
+}
+
+hipError_t launch_step(int m, int rb, int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+#define MG_LS(MM, RR) if (m == MM && rb == RR) return launch_step_p<MM, RR>(mode, a, s, ev0, ev1);
+  MG_FOR_EACH_PLAN(MG_LS)
+#undef MG_LS
+  return hipErrorInvalidValue;
+}
+
+int step_threads(int m, int rb) { return plan_valid(m, rb) ? m * rb : 0; }
+int step_waves(int m, int rb) { return (step_threads(m, rb) + 63) / 64; }
+
+size_t step_lds_bytes(int m, int rb) {
+#define MG_LB(MM, RR) if (m == MM && rb == RR) return lds_bytes_m<MM, RR>();
+  MG_FOR_EACH_PLAN(MG_LB)
+#undef MG_LB
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic segmented accumulation + apply.  One workgroup per 64 x 16
-// tile; lane = column, wave w owns rows w, w+4, w+8, w+12.  The positions
+// Deterministic segmented accumulation + apply.  One workgroup per 64 x TH
+// tile; lane = column, wave w owns rows w, w+4, w+8, ... .  The positions
 // overlapping the tile (ascending index, with their offsets) are screened 256
 // at a time in parallel: those in minibatch t are compacted, order preserved,
 // into LDS, then every thread sums their staged c_k and w0 over its pixels in
 // that order (FP64 sums of the staged FP32 c_k and an FP32 copy of w0).  Loads are predicated
 // rather than branched so that several positions' loads are in flight.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(ACC_THREADS) void accumulate_kernel(AccumArgs a) {
-  constexpr int RPT = ACC_TILE_H / (ACC_THREADS / 64);
+template <int TH>
+__device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int tile) {
+  constexpr int RPT = TH / (ACC_THREADS / 64);
   constexpr int NW = ACC_THREADS / 64;
   constexpr int U = 4;   // positions whose loads are in flight together
   __shared__ int s_slot[ACC_THREADS];
   __shared__ int2 s_off[ACC_THREADS];
   __shared__ int s_wcnt[NW];
-  const int tile = blockIdx.x;
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int X = tx * ACC_TILE_W + lane;
-  const int Y0 = ty * ACC_TILE_H + wave;
+  const int Y0 = ty * TH + wave;
   const int m = a.m;
   const size_t mm = (size_t)m * m;
   double nr[RPT], ni[RPT], dd[RPT];
@@ -713,12 +744,63 @@ __global__ __launch_bounds__(ACC_THREADS) void accumulate_kernel(AccumArgs a) {
   }
 }
 
-hipError_t launch_accumulate(const AccumArgs& a, int n_tiles, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (n_tiles <= 0) return hipSuccess;
+template <int TH>
+__global__ __launch_bounds__(ACC_THREADS) void accumulate_kernel(AccumArgs a) {
+  accumulate_body<TH>(a, (int)blockIdx.x);
+}
+
+template <int TH>
+__global__ __launch_bounds__(ACC_THREADS) void accumulate_multi_kernel(const AccumArgs* descs) {
+  const AccumArgs& a = descs[blockIdx.y];
+  if ((int)blockIdx.x >= a.n_tiles) return;
+  accumulate_body<TH>(a, (int)blockIdx.x);
+}
+
+template <int TH>
+static void launch_accumulate_t(const AccumArgs& a, int n_tiles, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0)
-    hipExtLaunchKernelGGL(accumulate_kernel, dim3(n_tiles), dim3(ACC_THREADS), 0, s, ev0, ev1, 0, a);
+    hipExtLaunchKernelGGL(accumulate_kernel<TH>, dim3(n_tiles), dim3(ACC_THREADS), 0, s, ev0, ev1, 0, a);
   else
-    hipLaunchKernelGGL(accumulate_kernel, dim3(n_tiles), dim3(ACC_THREADS), 0, s, a);
+    hipLaunchKernelGGL(accumulate_kernel<TH>, dim3(n_tiles), dim3(ACC_THREADS), 0, s, a);
+}
+
+bool tile_valid(int th) { return th == 8 || th == 16 || th == 32; }
+
+hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s) {
+  if (n_ctx <= 0 || max_count <= 0) return hipSuccess;
+#define MG_LM(MM, RR)                                                                                   \
+  if (m == MM && rb == RR) {                                                                            \
+    const size_t lds = lds_bytes_m<MM, RR>();                                                           \
+    hipFuncSetAttribute((const void*)step_multi_kernel<MM, RR>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                        (int)lds);                                                                      \
+    hipLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(max_count, n_ctx), dim3(MM * RR), lds, s, descs); \
+    return hipGetLastError();                                                                           \
+  }
+  MG_FOR_EACH_PLAN(MG_LM)
+#undef MG_LM
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s) {
+  if (n_ctx <= 0 || max_tiles <= 0) return hipSuccess;
+  switch (th) {
+    case 8: hipLaunchKernelGGL(accumulate_multi_kernel<8>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, descs); break;
+    case 16: hipLaunchKernelGGL(accumulate_multi_kernel<16>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, descs); break;
+    case 32: hipLaunchKernelGGL(accumulate_multi_kernel<32>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, descs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const AccumArgs& a, int th, int n_tiles, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (th) {
+    case 8: launch_accumulate_t<8>(a, n_tiles, s, ev0, ev1); break;
+    case 16: launch_accumulate_t<16>(a, n_tiles, s, ev0, ev1); break;
+    case 32: launch_accumulate_t<32>(a, n_tiles, s, ev0, ev1); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -848,44 +930,57 @@ hipError_t launch_level_constants(int m, int levels, double alpha, int u_given, 
 }
 
 // ---------------------------------------------------------------------------
-// sqrt(d) into kernel order: thread tid = g + RB*ky of position k reads
-// kx = g*CB + c + RA*k2 for j = c*RB + k2 and writes dst[k][tid*RA + j].
-// Flags negative or non-finite input.
+// sqrt(d) between natural order [k][ky][kx] and the kernel order of plan
+// (M, RB): thread tid = g + RB*ky of position k holds kx = g*CB + c + RA*k2 at
+// j = c*RB + k2, i.e. element [k][tid*RA + j].  Natural -> kernel flags
+// negative or non-finite input.
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, int RB, int TO_KERNEL>
 __global__ void permute_sqrt_kernel(int n_pos, const float* src, int is_sqrt, float* dst, int* bad) {
-  constexpr int RB = Plan<M>::RB, RA = Plan<M>::RA, CB = RA / RB;
+  constexpr int RA = M / RB, CB = RA / RB;
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
   const int g = tid & (RB - 1), ky = tid / RB;
-  const float* sp = src + (size_t)k * M * M + (size_t)ky * M;
-  float* dp = dst + (size_t)k * M * M + (size_t)tid * RA;
+  const size_t nat = (size_t)k * M * M + (size_t)ky * M;     // natural row ky
+  const size_t ker = (size_t)k * M * M + (size_t)tid * RA;   // this thread's kernel-order run
   int badl = 0;
 #pragma unroll
   for (int c = 0; c < CB; ++c)
 #pragma unroll
     for (int k2 = 0; k2 < RB; ++k2) {
-      const float x = sp[g * CB + c + RA * k2];
-      if (!(x >= 0.0f) || !isfinite(x)) badl = 1;
-      dp[c * RB + k2] = is_sqrt ? x : sqrtf(x);
+      const int kx = g * CB + c + RA * k2;
+      if (TO_KERNEL) {
+        const float x = src[nat + kx];
+        if (!(x >= 0.0f) || !isfinite(x)) badl = 1;
+        dst[ker + c * RB + k2] = is_sqrt ? x : sqrtf(x);
+      } else {
+        dst[nat + kx] = src[ker + c * RB + k2];
+      }
     }
   if (badl) atomicOr(bad, 1);
 }
 
-hipError_t launch_permute_sqrt(int m, int n_pos, const float* src, int is_sqrt, float* dst, int* bad,
+hipError_t launch_permute_sqrt(int m, int rb, int n_pos, const float* src, int is_sqrt, float* dst, int* bad,
                                hipStream_t s) {
-  switch (m) {
-#define MG_CASE(MM)                                                                                  \
-  case MM:                                                                                           \
-    hipLaunchKernelGGL(permute_sqrt_kernel<MM>, dim3(n_pos), dim3(MM * Plan<MM>::RB), 0, s, n_pos, src, \
-                       is_sqrt, dst, bad);                                                           \
-    break;
-    MG_CASE(8) MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128)
-#undef MG_CASE
-    default:
-      return hipErrorInvalidValue;
+#define MG_PS(MM, RR) \
+  if (m == MM && rb == RR) { \
+    hipLaunchKernelGGL((permute_sqrt_kernel<MM, RR, 1>), dim3(n_pos), dim3(MM * RR), 0, s, n_pos, src, is_sqrt, dst, bad); \
+    return hipGetLastError(); \
   }
-  return hipGetLastError();
+  MG_FOR_EACH_PLAN(MG_PS)
+#undef MG_PS
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_unpermute_sqrt(int m, int rb, int n_pos, const float* src, float* dst, hipStream_t s) {
+#define MG_US(MM, RR) \
+  if (m == MM && rb == RR) { \
+    hipLaunchKernelGGL((permute_sqrt_kernel<MM, RR, 0>), dim3(n_pos), dim3(MM * RR), 0, s, n_pos, src, 1, dst, nullptr); \
+    return hipGetLastError(); \
+  }
+  MG_FOR_EACH_PLAN(MG_US)
+#undef MG_US
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -931,7 +1026,6 @@ hipError_t launch_reduce_parts(const double* parts, int n, int nw, int take_sqrt
   return hipGetLastError();
 }
 
-int step_waves(int m) { return (step_threads(m) + 63) / 64; }
 
 // Epoch counter for graph replays (kernels, so that a captured graph holds no memset node).
 __global__ void set_counter_kernel(int* c, int v) { *c = v; }

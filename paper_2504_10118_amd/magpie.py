@@ -57,6 +57,11 @@ def _bind(lib):
         "magpie_get_epoch_index": (i, [vp, ctypes.POINTER(u64)]),
         "magpie_set_epoch_index": (i, [vp, u64]),
         "magpie_set_timing": (i, [vp, i]),
+        "magpie_list_plans": (i, [i, vp, i]),
+        "magpie_set_tuning": (i, [vp, i, i]),
+        "magpie_get_tuning": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "magpie_autotune": (i, [vp, i, i, ctypes.POINTER(d), ctypes.POINTER(d)]),
+        "magpie_run_epochs_multi": (i, [ctypes.POINTER(vp), i, i, ctypes.POINTER(i), u64]),
         "magpie_get_timing": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     }
@@ -115,6 +120,27 @@ def permutation(seed: int, epoch: int, n: int) -> np.ndarray:
     out = np.empty(n, dtype=np.int32)
     _check(lib.magpie_permutation(seed, epoch, n, out.ctypes.data_as(ctypes.c_void_p)))
     return out
+
+
+def list_plans(m: int) -> list[int]:
+    """Compiled FFT plans of the step kernel for probe side m (threads per 1-D transform), default first."""
+    lib = load_library()
+    buf = (ctypes.c_int32 * 8)()
+    n = lib.magpie_list_plans(m, ctypes.cast(buf, ctypes.c_void_p), 8)
+    if n < 0:
+        _check(n)
+    return [buf[i] for i in range(n)]
+
+
+def run_epochs_multi(contexts, n_epochs: int, batch, seed: int = 0):
+    """Advance several independent reconstructions together (one launch per plan / tile group per round)."""
+    lib = load_library()
+    cs = list(contexts)
+    if isinstance(batch, int):
+        batch = [batch] * len(cs)
+    hs = (ctypes.c_void_p * len(cs))(*[c._h.value for c in cs])
+    bs = (ctypes.c_int * len(cs))(*[int(b) for b in batch])
+    _check(lib.magpie_run_epochs_multi(hs, len(cs), n_epochs, bs, seed))
 
 
 class Magpie:
@@ -225,6 +251,21 @@ class Magpie:
                                           ctypes.byref(al), ctypes.byref(pos)))
         return {"step_ms": sm.value, "accum_ms": am.value, "step_launches": sl.value,
                 "accum_launches": al.value, "positions": pos.value}
+
+    def set_tuning(self, threads_per_transform: int = 0, tile_rows: int = 0):
+        _check(self.lib.magpie_set_tuning(self._h, threads_per_transform, tile_rows))
+
+    def get_tuning(self):
+        rb, th = ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.magpie_get_tuning(self._h, ctypes.byref(rb), ctypes.byref(th)))
+        return rb.value, th.value
+
+    def autotune(self, batch: int, trial_epochs: int = 3):
+        """Pick the fastest FFT plan and tile height on this context's data; returns (plan, tile, step_us, acc_us)."""
+        su, au = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.magpie_autotune(self._h, batch, trial_epochs, ctypes.byref(su), ctypes.byref(au)))
+        rb, th = self.get_tuning()
+        return rb, th, su.value, au.value
 
     # -- outputs
     def get_object(self, out=None, dtype=np.complex64):

@@ -289,3 +289,93 @@ def test_probe_update_parity(m, levels, batch):
     _print("probe update m", m, "object rel", rz, "probe rel", rq)
     assert rz <= 1e-5
     assert rq <= 1e-5
+
+
+@pytest.mark.parametrize("m,rb,levels", [(16, 2, 3), (32, 2, 3), (64, 4, 3), (64, 4, 5), (32, 2, 6)])
+def test_fft_plan_variants(m, rb, levels):
+    """Every compiled FFT plan matches the oracle (one epoch from the same z)."""
+    from paper_2504_10118_amd import list_plans
+    assert rb in list_plans(m)
+    rng = np.random.default_rng(16 + m + rb)
+    c = Case(rng, 2 * m + 7, 2 * m + 9, m, max(2, m // 3), noise=0.05)
+    order = rng.permutation(c.n_pos).astype(np.int32)
+    g = c.gpu(levels, 0.5)
+    g.set_tuning(rb, 0)
+    assert g.get_tuning()[0] == rb
+    g.run_epochs(1, 5, order=order[None])
+    zg = g.get_object().astype(np.complex128)
+    g.close()
+    zo = c.oracle_run(levels, 0.5, [order], 5)
+    rel = c.rel(zg, zo)
+    _print("plan", m, rb, levels, "rel", rel)
+    assert rel <= 1e-5
+
+
+def test_tile_heights_bitwise_equal_and_plan_switch_after_load():
+    rng = np.random.default_rng(17)
+    c = Case(rng, 200, 170, 32, 7, noise=0.05)
+    outs = []
+    for th in (8, 16, 32):
+        g = c.gpu(3, 0.5)
+        g.set_tuning(0, th)
+        g.run_epochs(2, 12, seed=4)
+        outs.append(g.get_object())
+        g.close()
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    assert np.array_equal(outs[0].view(np.uint64), outs[2].view(np.uint64))
+    # switching the plan after the data are loaded re-lays sqrt(d): equal to setting it first
+    from paper_2504_10118_amd import Magpie
+    res = []
+    for before in (True, False):
+        g = Magpie(c.n_rows, c.n_cols, c.m, 3, 0.5)
+        if before:
+            g.set_tuning(2, 0)
+        g.set_probe(c.Q32)
+        g.set_positions(c.offs)
+        g.load_intensities(c.sd32, is_sqrt=True)
+        if not before:
+            g.set_tuning(2, 0)
+        g.set_object(c.z0_32)
+        g.run_epochs(1, 12, seed=4)
+        res.append(g.get_object())
+        g.close()
+    assert np.array_equal(res[0].view(np.uint64), res[1].view(np.uint64))
+
+
+def test_autotune_keeps_state():
+    rng = np.random.default_rng(18)
+    c = Case(rng, 160, 160, 32, 8, noise=0.05)
+    g = c.gpu(3, 0.5)
+    g.run_epochs(1, 10, seed=1)
+    z_before = g.get_object()
+    ep = g.epoch_index
+    rb, th, su, au = g.autotune(10, 2)
+    _print("autotune plan", rb, "tile", th, "step us", su, "acc us", au)
+    from paper_2504_10118_amd import list_plans
+    assert rb in list_plans(32) and th in (8, 16, 32) and su > 0 and au > 0
+    assert np.array_equal(g.get_object().view(np.uint64), z_before.view(np.uint64))
+    assert g.epoch_index == ep
+    g.close()
+
+
+def test_multi_context_equals_separate_runs():
+    """Reconstructions of different sizes advanced together equal their separate runs bit for bit."""
+    from paper_2504_10118_amd import run_epochs_multi
+    rng = np.random.default_rng(19)
+    cases = [Case(rng, 120, 100, 16, 6, noise=0.05), Case(rng, 150, 170, 32, 9, noise=0.05),
+             Case(rng, 96, 96, 32, 11, noise=0.05)]
+    levels = [3, 2, 4]
+    batches = [7, 25, 3]
+    single = []
+    for c, L, B in zip(cases, levels, batches):
+        g = c.gpu(L, 0.5)
+        g.run_epochs(3, B, seed=77)
+        single.append(g.get_object())
+        g.close()
+    gs = [c.gpu(L, 0.5) for c, L in zip(cases, levels)]
+    gs[1].set_tuning(0, 8)              # a second tile-height group
+    run_epochs_multi(gs, 3, batches, seed=77)
+    for g, ref in zip(gs, single):
+        assert g.epoch_index == 3
+        assert np.array_equal(g.get_object().view(np.uint64), ref.view(np.uint64))
+        g.close()
