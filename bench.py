@@ -83,38 +83,161 @@ def describe(cfg, batch, levels, alpha):
             f"{levels} levels, minibatch {batch}, alpha {alpha}")
 
 
-def cpu_baseline(cfg, Q32, offs, sqrt_d32, levels, batch, alpha, seed, seconds):
-    """The oracle (literal Alg 3, minibatch combination) on whole minibatches of epoch 0 until `seconds` pass."""
-    import oracle
-    Q = Q32.astype(np.complex128)
-    u = oracle.u_rpie(Q, alpha)
-    z = np.ones((cfg.n, cfg.n), dtype=np.complex128)
-    order = oracle.library_permutation(seed, 0, cfg.n_pos)
-    done = 0
-    nb = 0
-    t0 = time.perf_counter()
-    while True:
-        for chunk in oracle.batches(order, batch):
-            z = oracle.minibatch_step(z, Q, offs, sqrt_d32, u, levels, chunk)
-            done += len(chunk)
-            nb += 1
-            if time.perf_counter() - t0 >= seconds:
-                break
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
+def host_cpu_name() -> str:
     cpu = platform.processor() or platform.machine()
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 if line.startswith("model name"):
-                    cpu = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": done / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nb} minibatches ({done} patterns; repeated passes over the minibatches of epoch 0), FP64 NumPy single thread, "
-                      f"{dt:.1f} s on {cpu} ({os.cpu_count()} host cores visible)"}
+    return cpu
+
+
+def oracle_intensities(z_true, Q, offs, peak, rng):
+    """sqrt of Poisson counts of the oracle's own forward model (inputs of the CPU baseline)."""
+    import oracle
+    from synth import poisson_counts
+    dt = oracle.forward_model(np.asarray(z_true, dtype=np.complex128), np.asarray(Q, dtype=np.complex128), offs)
+    return np.sqrt(poisson_counts(dt, peak, rng))
+
+
+def cpu_baseline(n, Q, offs, sqrt_d, levels, batch, alpha, seed, seconds):
+    """The oracle (literal Alg 3, minibatch combination) on whole minibatches of epoch 0 until `seconds` pass.
+
+    Returns (patterns, seconds, minibatches)."""
+    import oracle
+    Q = np.asarray(Q, dtype=np.complex128)
+    u = oracle.u_rpie(Q, alpha)
+    z = np.ones((n, n), dtype=np.complex128)
+    order = oracle.library_permutation(seed, 0, len(offs))
+    done = 0
+    nb = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for chunk in oracle.batches(order, batch):
+            z = oracle.minibatch_step(z, Q, offs, sqrt_d, u, levels, chunk)
+            done += len(chunk)
+            nb += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+    return done, time.perf_counter() - t0, nb
+
+
+def bench_batched(args):
+    """64 independent reconstructions of uneven size advanced together by the
+    multi-context entry point (one launch per FFT plan / tile group per round)."""
+    import torch
+    from paper_2504_10118_amd import Magpie, run_epochs_multi
+    from synth import batched_workload, make_batched_inputs, poisson_counts_device
+
+    alpha = 0.5 if args.alpha is None else args.alpha
+    specs = batched_workload()
+    ctxs, batches, first = [], [], None
+    for sp in specs:
+        z_true, Q, offs, _ = make_batched_inputs(sp)
+        ctx = Magpie(sp.n, sp.n, sp.m, sp.levels, alpha, device=0)
+        ctx.set_probe(Q.astype(np.complex64))
+        ctx.set_positions(offs)
+        dt = torch.empty((sp.n_pos, sp.m, sp.m), dtype=torch.float32, device="cuda")
+        ctx.forward_model(z_true.astype(np.complex64), out=dt)                  # GPU forward model
+        ctx.load_intensities(poisson_counts_device(dt, sp.peak, sp.seed), is_sqrt=False)
+        ctx.sync()
+        ctx._keep_d = None
+        del dt
+        ctx.set_object(np.ones((sp.n, sp.n), dtype=np.complex64))
+        ctxs.append(ctx)
+        batches.append(args.batch or sp.batch)
+        if first is None:
+            first = (sp, z_true, Q, offs)
+    torch.cuda.synchronize()
+    total_pos = sum(sp.n_pos for sp in specs)
+    bytes_per_epoch = sum(20 * sp.m * sp.m * sp.n_pos for sp in specs)
+
+    def reset():
+        for sp, c in zip(specs, ctxs):
+            c.set_object(np.ones((sp.n, sp.n), dtype=np.complex64))
+            c.epoch_index = 0
+        torch.cuda.synchronize()
+
+    if args.warmup:
+        run_epochs_multi(ctxs, args.warmup, batches, seed=args.seed + 1)
+    reset()
+    t0 = time.perf_counter()
+    run_epochs_multi(ctxs, args.steps, batches, seed=args.seed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # kernel timing pass: dispatch-recorded events on every multi launch
+    reset()
+    ctxs[0].set_timing(True)
+    ctxs[0].get_timing()
+    t2 = time.perf_counter()
+    run_epochs_multi(ctxs, args.steps, batches, seed=args.seed)
+    tm = ctxs[0].get_timing()
+    t3 = time.perf_counter()
+    ctxs[0].set_timing(False)
+    phis = [c.objective()[0] for c in ctxs]
+    for c in ctxs:
+        c.close()
+
+    wall = t1 - t0
+    step_s = tm["step_ms"] * 1e-3
+    achieved = args.steps * bytes_per_epoch / step_s / 1e9 if step_s > 0 else None
+    ms = [sp.m for sp in specs]
+    out = {
+        "metric": "diffraction patterns/s (fused step)",
+        "value": args.steps * total_pos / wall,
+        "unit": "patterns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"cfg4: {len(specs)} independent reconstructions, objects "
+                         f"{min(sp.n for sp in specs)}..{max(sp.n for sp in specs)} px, probes 64 ({ms.count(64)}) "
+                         f"and 128 ({ms.count(128)}), {min(sp.n_pos for sp in specs)}..{max(sp.n_pos for sp in specs)} "
+                         f"positions each ({total_pos} total), Poisson 1e4..1e5 peak photons, L = 3 (m 64) / 4 (m 128), "
+                         f"minibatch min(256, N), alpha {alpha}"),
+            "reconstructions": len(specs), "positions": total_pos,
+            "step": f"one epoch of every reconstruction = {total_pos} patterns",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "step_multi_kernel<64|128, MODE_STEP>",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": None,
+            "bytes_per_pattern": "20 m^2",
+            "avg_launch_us": tm["step_ms"] * 1e3 / max(1, tm["step_launches"]),
+            "launches": tm["step_launches"],
+        },
+        "accumulate_kernel": {
+            "avg_launch_us": tm["accum_ms"] * 1e3 / max(1, tm["accum_launches"]),
+            "launches": tm["accum_launches"],
+        },
+        "event_pass": {"ms_per_step": (t3 - t2) * 1e3 / args.steps,
+                       "step_share": step_s / (t3 - t2), "accumulate_share": tm["accum_ms"] * 1e-3 / (t3 - t2)},
+        "objective_after_median": float(np.median(phis)),
+    }
+    if not args.no_cpu_baseline:
+        sp, z_true, Q, offs = first
+        sqrt_d = oracle_intensities(z_true, Q, offs, sp.peak, np.random.default_rng(sp.seed))
+        done, dt, nb = cpu_baseline(sp.n, Q, offs, sqrt_d, sp.levels, args.batch or sp.batch, alpha, args.seed,
+                                    args.cpu_seconds)
+        out["cpu_baseline"] = {
+            "value": done / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
+            "sample": f"reconstruction 0 (object {sp.n}, probe {sp.m}, {sp.n_pos} positions): {nb} minibatches "
+                      f"({done} patterns) of epoch 0, FP64 NumPy single thread, {dt:.1f} s on {host_cpu_name()} "
+                      f"({os.cpu_count()} host cores visible)"}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -122,7 +245,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed epochs")
     ap.add_argument("--warmup", type=int, default=20, help="untimed epochs")
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
+                    help="1-3: one reconstruction; 4: 64 independent reconstructions of uneven size")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--alpha", type=float, default=None)
@@ -154,6 +278,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.config == 4:
+        return bench_batched(args)
 
     cfg, z_true, Q32, offs, r_noise = workload_inputs(args.config)
     batch = args.batch or cfg.batch
@@ -249,9 +376,13 @@ def main():
         "stopping_statistic_after": stat,
     }
     if not args.no_cpu_baseline:
-        sqrt_d = np.sqrt(d.astype(np.float64))
-        out["cpu_baseline"] = cpu_baseline(cfg, Q32, offs, sqrt_d, levels, batch, alpha, args.seed,
-                                           args.cpu_seconds)
+        sqrt_d = oracle_intensities(z_true, Q32, offs, cfg.peak, np.random.default_rng(args.seed))
+        done, dt, nb = cpu_baseline(cfg.n, Q32, offs, sqrt_d, levels, batch, alpha, args.seed, args.cpu_seconds)
+        out["cpu_baseline"] = {
+            "value": done / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nb} minibatches of {batch} ({done} patterns; passes over the minibatches of epoch 0) of "
+                      f"the same workload, FP64 NumPy single thread, {dt:.1f} s on {host_cpu_name()} "
+                      f"({os.cpu_count()} host cores visible)"}
     print(json.dumps(out), flush=True)
 
 

@@ -1211,15 +1211,21 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     size_t off = 0;
     for (size_t gi = 0; gi < sgroups.size() && e == hipSuccess; ++gi) {
       const auto& g = sgroups[gi];
+      int npat = 0;
+      for (size_t j = 0; j < g.members.size(); ++j) npat += hs[(size_t)r * count + off + j].count;
+      const int ti = (npat > 0) ? timed_slot(c0, 0, npat) : -1;
       e = mg::launch_step_multi(g.m, g.rb, ds + (size_t)r * count + off, (int)g.members.size(),
-                                s_max[(size_t)r * sgroups.size() + gi], st);
+                                s_max[(size_t)r * sgroups.size() + gi], st, ti >= 0 ? c0->timed[ti].a : nullptr,
+                                ti >= 0 ? c0->timed[ti].b : nullptr);
       off += g.members.size();
     }
     off = 0;
     for (size_t gi = 0; gi < agroups.size() && e == hipSuccess; ++gi) {
       const auto& g = agroups[gi];
+      const int ti = (a_max[(size_t)r * agroups.size() + gi] > 0) ? timed_slot(c0, 1, 0) : -1;
       e = mg::launch_accumulate_multi(g.m, da + (size_t)r * count + off, (int)g.members.size(),
-                                      a_max[(size_t)r * agroups.size() + gi], st);
+                                      a_max[(size_t)r * agroups.size() + gi], st, ti >= 0 ? c0->timed[ti].a : nullptr,
+                                      ti >= 0 ? c0->timed[ti].b : nullptr);
       off += g.members.size();
     }
   }

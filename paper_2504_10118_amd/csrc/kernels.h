@@ -72,8 +72,10 @@ hipError_t launch_accumulate(const AccumArgs& a, int th, int n_tiles, hipStream_
                              hipEvent_t ev1 = nullptr);
 // one launch over several contexts: grid (max_count | max_tiles) x n_ctx,
 // descriptor y describes context y for this round (count / n_tiles 0 = idle)
-hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s);
-hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s);
+hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s,
+                                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given,
                                   const double2* q64, double* u0, double* w0, float* w0f, float* u0f,
                                   float2* qf, double* lvl, double2* scr_q, double* scr_u,

@@ -766,14 +766,19 @@ static void launch_accumulate_t(const AccumArgs& a, int n_tiles, hipStream_t s, 
 
 bool tile_valid(int th) { return th == 8 || th == 16 || th == 32; }
 
-hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s) {
+hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1) {
   if (n_ctx <= 0 || max_count <= 0) return hipSuccess;
 #define MG_LM(MM, RR)                                                                                   \
   if (m == MM && rb == RR) {                                                                            \
     const size_t lds = lds_bytes_m<MM, RR>();                                                           \
     hipFuncSetAttribute((const void*)step_multi_kernel<MM, RR>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                         (int)lds);                                                                      \
-    hipLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(max_count, n_ctx), dim3(MM * RR), lds, s, descs); \
+    if (ev0)                                                                                            \
+      hipExtLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(max_count, n_ctx), dim3(MM * RR), lds, s, \
+                            ev0, ev1, 0, descs);                                                        \
+    else                                                                                                \
+      hipLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(max_count, n_ctx), dim3(MM * RR), lds, s, descs); \
     return hipGetLastError();                                                                           \
   }
   MG_FOR_EACH_PLAN(MG_LM)
@@ -781,12 +786,23 @@ hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, in
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s) {
+template <int TH>
+static void launch_acc_multi_t(const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s, hipEvent_t ev0,
+                               hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, ev0, ev1,
+                          0, descs);
+  else
+    hipLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, descs);
+}
+
+hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s,
+                                   hipEvent_t ev0, hipEvent_t ev1) {
   if (n_ctx <= 0 || max_tiles <= 0) return hipSuccess;
   switch (th) {
-    case 8: hipLaunchKernelGGL(accumulate_multi_kernel<8>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, descs); break;
-    case 16: hipLaunchKernelGGL(accumulate_multi_kernel<16>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, descs); break;
-    case 32: hipLaunchKernelGGL(accumulate_multi_kernel<32>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, descs); break;
+    case 8: launch_acc_multi_t<8>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
+    case 16: launch_acc_multi_t<16>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
+    case 32: launch_acc_multi_t<32>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

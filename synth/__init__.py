@@ -22,6 +22,10 @@ from .generators import (  # noqa: F401
     make_probe,
     make_scan,
     poisson_counts,
+    poisson_counts_device,
     epoch_orders,
     make_problem_inputs,
+    BatchedRecon,
+    batched_workload,
+    make_batched_inputs,
 )

@@ -150,3 +150,66 @@ def make_problem_inputs(cfg: ScanConfig):
     q = make_probe(cfg.m)
     offs = make_scan(cfg.n, cfg.m, cfg.P, cfg.step, r_scan)
     return z, q, offs, r_noise, r_perm
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchedRecon:
+    """One reconstruction of the batched workload (cfg 4)."""
+
+    index: int
+    n: int
+    m: int
+    P: int
+    step: int
+    peak: float
+    levels: int
+    batch: int
+    seed: int
+
+    @property
+    def n_pos(self) -> int:
+        return self.P * self.P
+
+
+def batched_workload(count: int = 64, cfg_id: int = 4):
+    """cfg 4: `count` independent reconstructions of uneven size.
+
+    Per reconstruction: n ~ U{256, 384, 512, 768, 1024}, m ~ U{64, 128},
+    P ~ U{20..80} (capped so the raster fits), step = min(10, (n-m-2)//(P-1)),
+    peak photons log-uniform in [1e4, 1e5], L = 3 (m = 64) or 4 (m = 128),
+    minibatch min(256, P*P).
+    """
+    rng = config_rngs(cfg_id)[0]
+    out = []
+    for i in range(count):
+        n = int(rng.choice([256, 384, 512, 768, 1024]))
+        m = int(rng.choice([64, 128]))
+        P = int(rng.integers(20, 81))
+        P = min(P, (n - m - 2) // 2 + 1)
+        step = min(10, (n - m - 2) // (P - 1))
+        peak = float(10 ** rng.uniform(4.0, 5.0))
+        levels = 3 if m == 64 else 4
+        out.append(BatchedRecon(i, n, m, P, step, peak, levels, min(256, P * P),
+                                int(rng.integers(0, 2**31 - 1))))
+    return out
+
+
+def make_batched_inputs(spec: BatchedRecon):
+    """Object, probe and scan of one reconstruction of the batched workload."""
+    ss = np.random.SeedSequence(spec.seed)
+    r_obj, r_scan, r_noise = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
+    z = make_object(spec.n, r_obj, rectangles=True)
+    q = make_probe(spec.m)
+    offs = make_scan(spec.n, spec.m, spec.P, spec.step, r_scan)
+    return z, q, offs, r_noise
+
+
+def poisson_counts_device(dtilde, peak: float, seed: int):
+    """Device-side Poisson counts for a torch tensor of noiseless intensities
+    (same model as :func:`poisson_counts`; used where the data are too large to
+    draw on the host)."""
+    import torch
+    gen = torch.Generator(device=dtilde.device)
+    gen.manual_seed(int(seed))
+    sigma = float(peak) / float(dtilde.max())
+    return torch.poisson(dtilde * sigma, generator=gen) / sigma

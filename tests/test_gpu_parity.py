@@ -374,7 +374,12 @@ def test_multi_context_equals_separate_runs():
         g.close()
     gs = [c.gpu(L, 0.5) for c, L in zip(cases, levels)]
     gs[1].set_tuning(0, 8)              # a second tile-height group
+    gs[0].set_timing(True)              # per-launch events on the multi launches
     run_epochs_multi(gs, 3, batches, seed=77)
+    tm = gs[0].get_timing()
+    assert tm["positions"] == 3 * sum(len(c.offs) for c in cases)
+    assert tm["step_ms"] > 0 and tm["accum_ms"] > 0 and tm["step_launches"] > 0 and tm["accum_launches"] > 0
+    gs[0].set_timing(False)
     for g, ref in zip(gs, single):
         assert g.epoch_index == 3
         assert np.array_equal(g.get_object().view(np.uint64), ref.view(np.uint64))
