@@ -15,3 +15,4 @@ Parity status of each part is in the module docstring of ``oracle.core``.
 """
 
 from .core import *  # noqa: F401,F403
+from . import learned  # noqa: F401
