@@ -16,7 +16,8 @@ the paper's own pieces where they apply:
   W -> W, ReLU, nearest 2x upsampling, W -> W, ReLU, W -> W, ReLU, W -> 2.
   The two output channels are log-amplitude and phase of the coarse object;
 * the loss is the masked complex mean squared error between exp(y0 + i y1)
-  and the target coarse object; Adam (Kingma and Ba, 2015) with bias
+  and the target coarse object, optionally after removing each sample's
+  global phase (the objective of eq. 2.1 does not see it); Adam (Kingma and Ba, 2015) with bias
   correction updates the parameters.
 
 Parity pins (tests/test_oracle_learned.py): the convolution against SciPy's
@@ -38,7 +39,8 @@ from .core import prolong, restrict
 
 __all__ = [
     "layer_shapes", "n_params", "unpack", "conv3x3", "conv3x3_backward", "relu", "upsample2",
-    "upsample2_backward", "net_forward", "net_backward", "complex_mse", "adam_step", "bf16_round",
+    "upsample2_backward", "net_forward", "net_backward", "complex_mse", "complex_mse_aligned", "adam_step",
+    "bf16_round",
     "position_stats", "input_map", "restrict_object", "prolong_object",
 ]
 
@@ -168,6 +170,30 @@ def complex_mse(y, target, mask):
     dy = np.empty_like(y)
     dy[:, 0] = 2.0 * msk * np.real(g) / norm             # dpred / dy0 = pred
     dy[:, 1] = -2.0 * msk * np.imag(g) / norm            # dpred / dy1 = i pred
+    return loss, dy
+
+
+def complex_mse_aligned(y, target, mask):
+    """complex_mse after removing each sample's global phase: pred is rotated by
+    exp(i phi_n), phi_n = arg sum_p mask conj(pred) t (the minimiser over phi), so
+    loss = sum_n min_phi sum_p mask |exp(i phi) pred - t|^2 / (N sum_p mask).
+    By the envelope theorem the gradient is that of the rotated residual with
+    phi_n held fixed.  Returns (loss, dL/dy)."""
+    y = np.asarray(y, dtype=np.float64)
+    N = y.shape[0]
+    pred = np.exp(y[:, 0] + 1j * y[:, 1])
+    t = np.asarray(target, dtype=np.complex128)
+    msk = np.asarray(mask, dtype=np.float64)[None]
+    ip = (msk * np.conj(pred) * t).sum(axis=(1, 2))
+    rot = np.where(np.abs(ip) > 0, ip / np.where(np.abs(ip) > 0, np.abs(ip), 1.0), 1.0)
+    pr = pred * rot[:, None, None]
+    r = pr - t
+    norm = N * msk.sum()
+    loss = float((msk * np.abs(r) ** 2).sum() / norm)
+    g = np.conj(r) * pr
+    dy = np.empty_like(y)
+    dy[:, 0] = 2.0 * msk * np.real(g) / norm
+    dy[:, 1] = -2.0 * msk * np.imag(g) / norm
     return loss, dy
 
 

@@ -8,6 +8,12 @@ paper_2504_10118_amd.build``.  This package only marshals arguments.
 from .magpie import (  # noqa: F401
     C64,
     C128,
+    CNN,
+    COARSE_C64,
+    COARSE_C128,
+    COARSE_LOGPOLAR,
+    W_BF16,
+    W_F32,
     UPDATE_PROBE,
     GRAPH,
     LIB_PATH,
@@ -16,5 +22,6 @@ from .magpie import (  # noqa: F401
     list_plans,
     load_library,
     permutation,
+    restrict_object,
     run_epochs_multi,
 )

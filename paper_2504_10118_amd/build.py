@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libmagpie.so")
-SOURCES = ["kernels.hip", "capi.cpp"]
+SOURCES = ["kernels.hip", "cnn.hip", "capi.cpp", "learned.cpp"]
 ARCH = os.environ.get("MAGPIE_OFFLOAD_ARCH", "gfx950")
 
 

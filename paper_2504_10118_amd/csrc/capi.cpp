@@ -1,161 +1,10 @@
 // Host runtime of the MAGPIE C ABI (include/magpie.h): context, device
 // buffers, input validation, epoch scheduling and kernel launches.
-#include <hip/hip_runtime.h>
+#include "context.h"
 
-#include <algorithm>
-#include <cmath>
-#include <cstdint>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "../../include/magpie.h"
-#include "kernels.h"
+using namespace mgrt;
 
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
-
-#define MG_HIP(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(MAGPIE_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
-  } while (0)
-
-bool valid_m(int m) { return m == 8 || m == 16 || m == 32 || m == 64 || m == 128; }
-
-int ilog2(int m) {
-  int l = 0;
-  while ((1 << l) < m) ++l;
-  return l;
-}
-
-template <typename T>
-int dev_alloc(T** p, size_t count) {
-  *p = nullptr;
-  if (count == 0) return MAGPIE_OK;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    return fail(MAGPIE_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
-  }
-  return MAGPIE_OK;
-}
-
-template <typename T>
-void dev_free(T*& p) {
-  if (p) hipFree((void*)p);
-  p = nullptr;
-}
-
-uint64_t splitmix64_next(uint64_t& state) {
-  state += 0x9E3779B97F4A7C15ull;
-  uint64_t z = state;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-void fisher_yates(uint64_t seed, uint64_t epoch, int n, int32_t* out) {
-  for (int i = 0; i < n; ++i) out[i] = i;
-  uint64_t st = seed ^ epoch;
-  for (int i = n - 1; i > 0; --i) {
-    const uint64_t j = splitmix64_next(st) % (uint64_t)(i + 1);
-    std::swap(out[i], out[(size_t)j]);
-  }
-}
-
-}  // namespace
-
-struct magpie_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int nr = 0, nc = 0, m = 0, L = 1;
-  int rb = 0;    // FFT plan of the step kernel (threads per 1-D transform)
-  int th = 16;   // accumulate tile height
-  double alpha = 0.0;
-  uint32_t flags = 0;
-  double beta = 0.0;
-  bool u_given = false;
-  int n_pos = 0;
-  bool has_probe = false, has_pos = false, has_data = false;
-  uint64_t epoch_index = 0;
-
-  // device buffers
-  float2* z = nullptr;
-  float2* qf = nullptr;
-  double2* q64 = nullptr;
-  double* u0 = nullptr;
-  double* w0 = nullptr;
-  float* w0f = nullptr;
-  float* u0f = nullptr;
-  double* lvl = nullptr;
-  double2* scr_q = nullptr;
-  double* scr_u = nullptr;
-  int* flag = nullptr;
-  double* red = nullptr;
-
-  int2* offs = nullptr;
-  float* sqrtd = nullptr;
-  double* phi_step = nullptr;   // per position, reduced on demand
-  double* phi_obj = nullptr;
-  double* gnorm = nullptr;
-  double* step_part = nullptr;  // per-wave partials [N][MAX_WAVES]
-  double* obj_part = nullptr;
-  double* gn_part = nullptr;
-  int lvl_a_off = 0;
-  int* tile_ptr = nullptr;
-  int4* tile_ent = nullptr;
-  int tiles_x = 0, tiles_y = 0;
-  std::vector<int32_t> h_offs;
-
-  float2* stage = nullptr;
-  size_t stage_cap = 0;  // in float2
-  float2* pnum = nullptr;   // probe step partials (allocated with the staging when the flag is on)
-  float* pden = nullptr;
-  float* pmax = nullptr;
-  size_t pcap = 0;
-  int* perm = nullptr;   // [E][N]
-  int4* posrec = nullptr;  // [E][N] (k, row, col, 0) in processing order
-  int* inv = nullptr;    // [E][N]
-  size_t perm_cap = 0;   // ints per array
-  int32_t* h_pin = nullptr;
-  size_t h_pin_cap = 0;  // ints
-  hipEvent_t pin_done = nullptr;
-  bool pin_pending = false;
-
-  // optional per-launch timing
-  bool timing = false;
-  struct Timed {
-    hipEvent_t a, b;
-    int kind;   // 0 = step kernel, 1 = accumulate kernel
-    int count;  // positions (step kernel)
-  };
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<Timed> timed;
-
-  // captured epoch graph (replayed once per epoch); the epoch index is read
-  // by the kernels from epoch_ctr, which the graph's last node advances
-  hipGraphExec_t gexec = nullptr;
-  int g_batch = 0;
-  const void* g_key[4] = {nullptr, nullptr, nullptr, nullptr};  // buffers it was built on
-  int* epoch_ctr = nullptr;
-  int g_rb = 0, g_th = 0;
-};
-
-namespace {
-
-int set_dev(magpie_ctx* c) {
-  MG_HIP(hipSetDevice(c->device));
-  return MAGPIE_OK;
-}
 
 void drop_graph(magpie_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
@@ -239,14 +88,6 @@ int build_tiles(magpie_ctx* c) {
     MG_HIP(hipMemcpyAsync(c->tile_ent, pos.data(), pos.size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
   MG_HIP(hipStreamSynchronize(c->stream));
   drop_graph(c);
-  return MAGPIE_OK;
-}
-
-int read_flag(magpie_ctx* c, int* out) {
-  int h = 0;
-  MG_HIP(hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  MG_HIP(hipStreamSynchronize(c->stream));
-  *out = h;
   return MAGPIE_OK;
 }
 
@@ -355,6 +196,12 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->perm);
   dev_free(c->posrec);
   dev_free(c->inv);
+  dev_free(c->lrn_sd);
+  dev_free(c->lrn_stats);
+  dev_free(c->lrn_fine);
+  dev_free(c->lrn_map);
+  dev_free(c->lrn_q);
+  dev_free(c->lrn_one);
   if (c->h_pin) hipHostFree(c->h_pin);
   if (c->pin_done) hipEventDestroy(c->pin_done);
   for (auto& t : c->timed) {

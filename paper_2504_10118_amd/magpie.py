@@ -23,6 +23,8 @@ ERRORS = {
 C64, C128 = 0, 1
 UPDATE_PROBE = 0x1
 GRAPH = 0x2
+W_F32, W_BF16 = 0, 1
+COARSE_C64, COARSE_C128, COARSE_LOGPOLAR = 0, 1, 2
 
 _lib = None
 
@@ -64,6 +66,22 @@ def _bind(lib):
         "magpie_run_epochs_multi": (i, [ctypes.POINTER(vp), i, i, ctypes.POINTER(i), u64]),
         "magpie_get_timing": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        # learned start (include/magpie_learned.h)
+        "magpie_cnn_create": (i, [ctypes.POINTER(vp), i, i, i, i, i, i, vp]),
+        "magpie_cnn_destroy": (i, [vp]),
+        "magpie_cnn_num_params": (i, [vp, ctypes.POINTER(ctypes.c_int64)]),
+        "magpie_cnn_set_params": (i, [vp, vp, i]),
+        "magpie_cnn_get_params": (i, [vp, vp, i]),
+        "magpie_cnn_get_grads": (i, [vp, vp, i]),
+        "magpie_cnn_forward": (i, [vp, vp, vp, i, i]),
+        "magpie_cnn_loss": (i, [vp, vp, vp, i, i, i, ctypes.POINTER(d)]),
+        "magpie_cnn_backward": (i, [vp, vp, i, i]),
+        "magpie_cnn_adam_step": (i, [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+        "magpie_cnn_sync": (i, [vp]),
+        "magpie_input_map": (i, [vp, i, vp, i]),
+        "magpie_set_object_from_coarse": (i, [vp, vp, i, i, i]),
+        "magpie_restrict_object": (i, [vp, i, i, i, vp, vp]),
+        "magpie_learned_start": (i, [vp, vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -80,6 +98,14 @@ def load_library(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"libmagpie.so not built at {p}; run `python -m paper_2504_10118_amd.build`")
+    # One HIP runtime per process: torch ships its own libamdhip64 under the same
+    # soname, so loading torch's libraries first lets the library bind to that copy
+    # (loading ours first would make torch load a second runtime that cannot
+    # initialise the GPU).  Importing torch does not touch the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = _bind(ctypes.CDLL(p))
     if path is None:
         _lib = lib
@@ -286,6 +312,32 @@ class Magpie:
                                          C128 if dtype is np.complex128 else C64, 0))
         return out
 
+    # -- learned start
+    def input_map(self, side: int, out=None):
+        """Network input map [3, side, side] (float32) from this context's intensities."""
+        if out is not None and _is_torch(out) and out.is_cuda:
+            _check(self.lib.magpie_input_map(self._h, side, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        res = np.empty((3, side, side), dtype=np.float32)
+        _check(self.lib.magpie_input_map(self._h, side, res.ctypes.data_as(ctypes.c_void_p), 0))
+        return res
+
+    def set_object_from_coarse(self, coarse, fmt: int = COARSE_C64):
+        """Object <- coarse object copied into f x f blocks (f = object side / coarse side)."""
+        if fmt == COARSE_LOGPOLAR:
+            p, dev, keep = _ptr(coarse, np.float32)
+            side = int(coarse.shape[-1])
+        else:
+            p, dev, keep = _ptr(coarse, np.complex128 if fmt == COARSE_C128 else np.complex64)
+            side = int(coarse.shape[-1])
+        _check(self.lib.magpie_set_object_from_coarse(self._h, p, side, fmt, dev))
+
+    def learned_start(self, net: "CNN"):
+        """Learned start with the flat-start fallback; returns (used, phi_learned, phi_flat)."""
+        pl, pf, used = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(self.lib.magpie_learned_start(self._h, net._h, ctypes.byref(pl), ctypes.byref(pf), ctypes.byref(used)))
+        return bool(used.value), pl.value, pf.value
+
     def forward_model(self, z, out=None):
         p, dev, keep = _ptr(z, np.complex64, (self.n_rows, self.n_cols))
         if out is not None and _is_torch(out) and out.is_cuda:
@@ -294,3 +346,105 @@ class Magpie:
         res = np.empty((self.n_pos, self.m, self.m), dtype=np.float32)
         _check(self.lib.magpie_forward_model(self._h, p, dev, res.ctypes.data_as(ctypes.c_void_p), 0))
         return res
+
+
+def restrict_object(z, times: int, out=None, stream=None):
+    """Whole-object restriction (f x f block means, f = 2**times) of a complex64 device tensor."""
+    import torch
+    if not (_is_torch(z) and z.is_cuda and z.dtype == torch.complex64 and z.is_contiguous()):
+        raise ValueError("z must be a contiguous complex64 device tensor")
+    lib = load_library()
+    nr, nc = int(z.shape[-2]), int(z.shape[-1])
+    f = 1 << times
+    lead = tuple(z.shape[:-2])
+    if out is None:
+        out = torch.empty(lead + (nr // f, nc // f), dtype=torch.complex64, device=z.device)
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(z.device).cuda_stream)
+    zz = z.reshape(-1, nr, nc)
+    oo = out.reshape(-1, nr // f, nc // f)
+    for b in range(zz.shape[0]):
+        _check(lib.magpie_restrict_object(ctypes.c_void_p(zz[b].data_ptr()), nr, nc, times,
+                                          ctypes.c_void_p(oo[b].data_ptr()), st))
+    return out
+
+
+class CNN:
+    """Coarse-object network of the learned start (5 conv layers, width 32, FP32 or BF16 weights)."""
+
+    def __init__(self, in_ch: int = 3, side: int = 64, max_batch: int = 32, weight_dtype: int = W_F32,
+                 device: int = 0, stream=None):
+        self.lib = load_library()
+        self.in_ch, self.side, self.max_batch = in_ch, side, max_batch
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        _check(self.lib.magpie_cnn_create(ctypes.byref(h), in_ch, 32, side, max_batch, weight_dtype, device, st))
+        self._h = h
+        n = ctypes.c_int64()
+        _check(self.lib.magpie_cnn_num_params(self._h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.magpie_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p, dev, keep = _ptr(params, np.float32, (self.n_params,))
+        _check(self.lib.magpie_cnn_set_params(self._h, p, dev))
+        self._keep_p = keep if dev else None
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(self.lib.magpie_cnn_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def get_grads(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(self.lib.magpie_cnn_get_grads(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def forward(self, x, out=None):
+        nb = int(x.shape[0])
+        s2 = 2 * self.side
+        p, dev, keep = _ptr(x, np.float32, (nb, self.in_ch, self.side, self.side))
+        if dev:
+            if out is None:
+                _check(self.lib.magpie_cnn_forward(self._h, p, None, nb, 1))
+                return None
+            _check(self.lib.magpie_cnn_forward(self._h, p, ctypes.c_void_p(out.data_ptr()), nb, 1))
+            return out
+        res = np.empty((nb, 2, s2, s2), dtype=np.float32)
+        _check(self.lib.magpie_cnn_forward(self._h, p, res.ctypes.data_as(ctypes.c_void_p), nb, 0))
+        return res
+
+    def loss(self, target, mask, align_phase: bool = False) -> float:
+        nb = int(target.shape[0])
+        s2 = 2 * self.side
+        pt, dev, kt = _ptr(target, np.complex64, (nb, s2, s2))
+        pm, devm, km = _ptr(mask, np.float32, (s2, s2))
+        if dev != devm:
+            raise ValueError("target and mask must both be host arrays or both device tensors")
+        out = ctypes.c_double()
+        _check(self.lib.magpie_cnn_loss(self._h, pt, pm, nb, int(bool(align_phase)), dev, ctypes.byref(out)))
+        return out.value
+
+    def backward(self, dy=None, nbatch=None):
+        if dy is None:
+            _check(self.lib.magpie_cnn_backward(self._h, None, int(nbatch), 0))
+            return
+        nb = int(dy.shape[0])
+        s2 = 2 * self.side
+        p, dev, keep = _ptr(dy, np.float32, (nb, 2, s2, s2))
+        _check(self.lib.magpie_cnn_backward(self._h, p, nb, dev))
+
+    def adam_step(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(self.lib.magpie_cnn_adam_step(self._h, lr, beta1, beta2, eps))
+
+    def sync(self):
+        _check(self.lib.magpie_cnn_sync(self._h))

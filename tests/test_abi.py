@@ -62,3 +62,22 @@ def test_permutation_matches_oracle(seed, epoch, n):
     got = pkg.permutation(seed, epoch, n)
     want = oracle.library_permutation(seed, epoch, n)
     np.testing.assert_array_equal(got, want)
+
+
+def test_learned_entry_points_reject_bad_arguments_before_touching_a_device():
+    lib = pkg.load_library()
+    h = ctypes.c_void_p()
+    assert lib.magpie_cnn_create(ctypes.byref(h), 2, 32, 64, 8, 0, 0, None) == -6    # in_ch
+    assert lib.magpie_cnn_create(ctypes.byref(h), 3, 16, 64, 8, 0, 0, None) == -6    # width
+    assert lib.magpie_cnn_create(ctypes.byref(h), 3, 32, 63, 8, 0, 0, None) == -1    # odd side
+    assert lib.magpie_cnn_create(ctypes.byref(h), 3, 32, 64, 0, 0, 0, None) == -1    # max_batch
+    assert lib.magpie_cnn_create(ctypes.byref(h), 3, 32, 64, 8, 5, 0, None) == -1    # weight dtype
+    assert lib.magpie_cnn_create(None, 3, 32, 64, 8, 0, 0, None) == -1
+    assert lib.magpie_cnn_forward(None, None, None, 1, 0) == -1
+    assert lib.magpie_cnn_backward(None, None, 1, 0) == -1
+    assert lib.magpie_cnn_adam_step(None, 1e-3, 0.9, 0.999, 1e-8) == -1
+    assert lib.magpie_input_map(None, 64, None, 0) == -1
+    assert lib.magpie_set_object_from_coarse(None, None, 64, 0, 0) == -1
+    assert lib.magpie_learned_start(None, None, None, None, None) == -1
+    assert lib.magpie_restrict_object(None, 64, 64, 1, None, None) == -1
+    assert lib.magpie_cnn_destroy(None) == 0

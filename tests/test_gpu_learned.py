@@ -1,0 +1,320 @@
+"""GPU parity of the learned-start kernels against the FP64 oracle (oracle.learned).
+
+Network: forward, masked complex MSE (plain and phase-aligned), all
+parameter gradients, Adam, the BF16-weight variant, determinism.  Input map,
+whole-object prolongation / restriction, and the learned start's fallback.
+Sizes are small but span several 16 x 16 convolution tiles with ragged
+edges at both resolutions.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import learned as ol
+from gpu_cases import Case
+
+pytestmark = pytest.mark.gpu
+
+CIN, W, SIDE = 3, 32, 20          # 20 x 20 input, 40 x 40 output: ragged 16 x 16 tiles at both sizes
+
+
+def _params(rng, cin=CIN, scale=1.0):
+    """He-scaled random parameters (FP32) with small biases."""
+    out = []
+    for co, ci in ol.layer_shapes(cin, W):
+        out.append(rng.normal(0.0, scale * np.sqrt(2.0 / (9 * ci)), co * ci * 9))
+        out.append(rng.normal(0.0, 0.05, co))
+    p = np.concatenate(out).astype(np.float32)
+    return p
+
+
+def _inputs(rng, nb, cin=CIN, side=SIDE):
+    x = rng.normal(0.0, 1.0, (nb, cin, side, side)).astype(np.float32)
+    s2 = 2 * side
+    t = (rng.uniform(0.7, 1.0, (nb, s2, s2)) * np.exp(1j * rng.uniform(-1, 1, (nb, s2, s2)))).astype(np.complex64)
+    mask = (rng.uniform(size=(s2, s2)) > 0.25).astype(np.float32) * rng.uniform(0.5, 1.0, (s2, s2)).astype(np.float32)
+    return x, t, mask
+
+
+def _net(cin=CIN, side=SIDE, max_batch=4, wdt=0):
+    from paper_2504_10118_amd import CNN
+    return CNN(in_ch=cin, side=side, max_batch=max_batch, weight_dtype=wdt)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_forward_matches_oracle():
+    rng = np.random.default_rng(100)
+    p = _params(rng)
+    x, _, _ = _inputs(rng, 3)
+    net = _net()
+    net.set_params(p)
+    y = net.forward(x)
+    yo, _ = ol.net_forward(p.astype(np.float64), x.astype(np.float64), CIN, W)
+    assert y.shape == yo.shape
+    assert _rel(y, yo) <= 1e-5
+    assert np.max(np.abs(y - yo)) <= 1e-5 * np.max(np.abs(yo))
+    net.close()
+
+
+@pytest.mark.parametrize("align", [False, True])
+def test_loss_and_all_gradients_match_oracle(align):
+    rng = np.random.default_rng(101 + int(align))
+    p = _params(rng)
+    x, t, mask = _inputs(rng, 3)
+    net = _net()
+    net.set_params(p)
+    net.forward(x)
+    loss = net.loss(t, mask, align_phase=align)
+    net.backward(nbatch=3)
+    g = net.get_grads()
+    yo, cache = ol.net_forward(p.astype(np.float64), x.astype(np.float64), CIN, W)
+    fn = ol.complex_mse_aligned if align else ol.complex_mse
+    lo, dyo = fn(yo, t.astype(np.complex128), mask.astype(np.float64))
+    go, _ = ol.net_backward(p.astype(np.float64), cache, dyo, CIN, W)
+    assert abs(loss - lo) <= 1e-5 * lo
+    # per layer: weights and biases
+    off = 0
+    for co, ci in ol.layer_shapes(CIN, W):
+        for cnt in (co * ci * 9, co):
+            a, b = g[off:off + cnt], go[off:off + cnt]
+            assert _rel(a, b) <= 2e-5, (co, ci, cnt, _rel(a, b))
+            off += cnt
+    assert off == g.size
+    net.close()
+
+
+def test_gradient_with_explicit_dy_and_determinism():
+    rng = np.random.default_rng(103)
+    p = _params(rng)
+    x, _, _ = _inputs(rng, 2)
+    dy = rng.normal(size=(2, 2, 2 * SIDE, 2 * SIDE)).astype(np.float32)
+    net = _net()
+    net.set_params(p)
+    net.forward(x)
+    net.backward(dy)
+    g1 = net.get_grads()
+    net.forward(x)
+    net.backward(dy)
+    g2 = net.get_grads()
+    assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+    yo, cache = ol.net_forward(p.astype(np.float64), x.astype(np.float64), CIN, W)
+    go, _ = ol.net_backward(p.astype(np.float64), cache, dy.astype(np.float64), CIN, W)
+    assert _rel(g1, go) <= 2e-5
+    net.close()
+
+
+def test_adam_steps_match_oracle():
+    rng = np.random.default_rng(104)
+    p = _params(rng)
+    x, t, mask = _inputs(rng, 2)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    net = _net()
+    net.set_params(p)
+    po = p.astype(np.float64)
+    mo = np.zeros_like(po)
+    vo = np.zeros_like(po)
+    big = np.ones(po.size, bool)
+    for step in (1, 2, 3):
+        net.forward(x)
+        net.loss(t, mask)
+        net.backward(nbatch=2)
+        net.adam_step(lr, b1, b2, eps)
+        yo, cache = ol.net_forward(po, x.astype(np.float64), CIN, W)
+        _, dyo = ol.complex_mse(yo, t.astype(np.complex128), mask.astype(np.float64))
+        go, _ = ol.net_backward(po, cache, dyo, CIN, W)
+        big &= np.abs(go) > 3e-2 * np.max(np.abs(go))
+        po, mo, vo = ol.adam_step(po, go, mo, vo, step, lr, b1, b2, eps)
+    pg = net.get_params()
+    # Adam's step is about lr * g_t / rms(g): it turns the relative error of a gradient
+    # component into the same relative error of the step.  FP32 gradients agree with
+    # the oracle to ~1e-5 of their norm, so small components may differ by percents
+    # (or flip sign): those get the lr-sized bound, the components whose gradient was
+    # at least 3 % of the largest at every step a bound of 1 % of lr
+    assert np.max(np.abs(pg - po)) <= 6 * lr
+    assert np.max(np.abs(pg - po)[big]) <= 1e-2 * lr
+    assert np.mean(big) > 0.02
+    net.close()
+
+
+def test_bf16_weight_variant_matches_oracle_with_rounded_weights():
+    from paper_2504_10118_amd import W_BF16
+    rng = np.random.default_rng(105)
+    p = _params(rng)
+    x, t, mask = _inputs(rng, 2)
+    net = _net(wdt=W_BF16)
+    net.set_params(p)
+    y = net.forward(x)
+    pr = p.astype(np.float64).copy()
+    off = 0
+    for co, ci in ol.layer_shapes(CIN, W):
+        n = co * ci * 9
+        pr[off:off + n] = ol.bf16_round(p[off:off + n])
+        off += n + co
+    yo, cache = ol.net_forward(pr, x.astype(np.float64), CIN, W)
+    assert _rel(y, yo) <= 1e-5
+    # and it differs from the FP32-weight network by about bf16 precision
+    y32, _ = ol.net_forward(p.astype(np.float64), x.astype(np.float64), CIN, W)
+    assert 1e-5 < _rel(y, y32) < 3e-2
+    net.forward(x)
+    net.loss(t, mask)
+    net.backward(nbatch=2)
+    _, dyo = ol.complex_mse(yo, t.astype(np.complex128), mask.astype(np.float64))
+    go, _ = ol.net_backward(pr, cache, dyo, CIN, W)
+    assert _rel(net.get_grads(), go) <= 2e-5
+    net.close()
+
+
+def test_one_input_channel_network():
+    rng = np.random.default_rng(106)
+    p = _params(rng, cin=1)
+    x, t, mask = _inputs(rng, 2, cin=1)
+    net = _net(cin=1)
+    assert net.n_params == ol.n_params(1, W)
+    net.set_params(p)
+    y = net.forward(x)
+    yo, cache = ol.net_forward(p.astype(np.float64), x.astype(np.float64), 1, W)
+    assert _rel(y, yo) <= 1e-5
+    net.loss(t, mask)
+    net.backward(nbatch=2)
+    _, dyo = ol.complex_mse(yo, t.astype(np.complex128), mask.astype(np.float64))
+    go, _ = ol.net_backward(p.astype(np.float64), cache, dyo, 1, W)
+    assert _rel(net.get_grads(), go) <= 2e-5
+    net.close()
+
+
+def test_training_steps_lower_the_loss():
+    rng = np.random.default_rng(107)
+    p = _params(rng, scale=0.5)
+    x, t, mask = _inputs(rng, 4)
+    net = _net()
+    net.set_params(p)
+    losses = []
+    for _ in range(30):
+        net.forward(x)
+        losses.append(net.loss(t, mask, align_phase=True))
+        net.backward(nbatch=4)
+        net.adam_step(3e-3)
+    assert losses[-1] < 0.7 * losses[0]
+    net.close()
+
+
+def test_network_argument_errors():
+    from paper_2504_10118_amd import MagpieError
+    net = _net()
+    with pytest.raises(MagpieError):
+        net.backward(nbatch=1)                    # no forward yet
+    rng = np.random.default_rng(108)
+    x, t, mask = _inputs(rng, 2)
+    net.forward(x)
+    with pytest.raises(MagpieError):
+        net.loss(t, np.zeros_like(mask))          # all-zero mask
+    with pytest.raises(MagpieError):
+        net.backward(nbatch=3)                    # batch differs from the forward
+    with pytest.raises(MagpieError):
+        net.forward(np.zeros((5, CIN, SIDE, SIDE), np.float32))   # above max_batch
+    bad = np.zeros(net.n_params, np.float32)
+    bad[7] = np.nan
+    with pytest.raises(MagpieError):
+        net.set_params(bad)
+    net.close()
+
+
+# ---------------------------------------------------------------------------
+# Input map, pyramid, learned start
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m,step,side", [(96, 32, 9, 24), (128, 16, 7, 32), (80, 32, 11, 16)])
+def test_input_map_matches_oracle(n, m, step, side):
+    rng = np.random.default_rng(200 + n + m)
+    c = Case(rng, n, n, m, step, noise=0.05)
+    g = c.gpu(2, 0.5)
+    mp = g.input_map(side)
+    mo = ol.input_map(c.sd32.astype(np.float64), c.Q, c.offs, n, n, side)
+    for ch in range(3):
+        scale = max(np.max(np.abs(mo[ch])), 1e-12)
+        assert np.max(np.abs(mp[ch] - mo[ch])) <= 1e-6 * scale, ch
+    # the map does not depend on the FFT plan that stores sqrt(d) in kernel order
+    from paper_2504_10118_amd import list_plans
+    for rb in list_plans(m):
+        g.set_tuning(rb, 0)
+        assert np.array_equal(g.input_map(side), mp)
+    g.close()
+
+
+@pytest.mark.parametrize("fmt", ["c64", "c128", "logpolar"])
+def test_set_object_from_coarse_matches_prolongation(fmt):
+    from paper_2504_10118_amd import COARSE_C64, COARSE_C128, COARSE_LOGPOLAR
+    rng = np.random.default_rng(300)
+    c = Case(rng, 96, 96, 32, 12)
+    g = c.gpu(2, 0.5)
+    side = 24
+    zc = (rng.uniform(0.5, 1.2, (side, side)) * np.exp(1j * rng.uniform(-2, 2, (side, side))))
+    if fmt == "c64":
+        g.set_object_from_coarse(zc.astype(np.complex64), COARSE_C64)
+        want = ol.prolong_object(zc.astype(np.complex64), 2)
+        assert np.array_equal(g.get_object(), want)
+    elif fmt == "c128":
+        g.set_object_from_coarse(zc, COARSE_C128)
+        assert np.array_equal(g.get_object(), ol.prolong_object(zc, 2).astype(np.complex64))
+    else:
+        planes = np.stack([np.log(np.abs(zc)), np.angle(zc)]).astype(np.float32)
+        g.set_object_from_coarse(planes, COARSE_LOGPOLAR)
+        want = ol.prolong_object(np.exp(planes[0].astype(np.float64) + 1j * planes[1].astype(np.float64)), 2)
+        assert np.max(np.abs(g.get_object() - want)) <= 1e-6 * np.max(np.abs(want))
+    g.close()
+
+
+def test_set_object_from_coarse_rejects_non_power_of_two_ratio():
+    from paper_2504_10118_amd import MagpieError
+    rng = np.random.default_rng(301)
+    c = Case(rng, 96, 96, 32, 12)
+    g = c.gpu(2, 0.5)
+    with pytest.raises(MagpieError):
+        g.set_object_from_coarse(np.ones((32, 32), np.complex64))      # 96 / 32 = 3
+    g.close()
+
+
+def test_restrict_object_matches_oracle():
+    import torch
+    from paper_2504_10118_amd import restrict_object
+    rng = np.random.default_rng(302)
+    z = (rng.normal(size=(3, 64, 96)) + 1j * rng.normal(size=(3, 64, 96))).astype(np.complex64)
+    out = restrict_object(torch.from_numpy(z).cuda(), 2)
+    torch.cuda.synchronize()
+    want = np.stack([ol.restrict_object(z[i].astype(np.complex128), 2) for i in range(3)])
+    assert np.max(np.abs(out.cpu().numpy() - want)) <= 1e-6 * np.max(np.abs(want))
+
+
+def test_learned_start_falls_back_to_the_flat_start():
+    """A zero network predicts exactly the flat start (tie -> flat); a network that predicts a
+    far too bright object loses on the objective and the flat start is kept."""
+    rng = np.random.default_rng(400)
+    c = Case(rng, 128, 128, 32, 10, noise=0.0)
+    g = c.gpu(3, 0.5)
+    net = _net(side=32, max_batch=1)
+    used, pl, pf = g.learned_start(net)
+    assert not used and pl == pf
+    assert np.array_equal(g.get_object(), np.ones((128, 128), np.complex64))
+    p = np.zeros(net.n_params, np.float32)
+    p[-2] = 3.0                                   # log-amplitude bias of the head: |z| = e^3
+    net.set_params(p)
+    g.set_object(c.z0_32)
+    used, pl, pf = g.learned_start(net)
+    assert not used and pl > pf
+    assert np.array_equal(g.get_object(), np.ones((128, 128), np.complex64))
+    # a constant object a* z with a* = argmin_a sum_k || a |F Q| - sqrt(d_k) ||^2 beats the flat
+    # start (a = 1) and is kept
+    import oracle
+    fq = np.abs(oracle.fft2(c.Q))
+    a_star = float(sum((fq * c.sd[k]).sum() for k in range(c.n_pos)) / (c.n_pos * (fq ** 2).sum()))
+    assert abs(a_star - 1.0) > 0.02
+    p[-2] = np.log(a_star)
+    net.set_params(p)
+    used, pl, pf = g.learned_start(net)
+    assert used and pl < pf
+    zc = np.full((64, 64), np.exp(p[-2]), dtype=np.complex128)
+    assert np.max(np.abs(g.get_object() - ol.prolong_object(zc, 1))) <= 1e-6
+    net.close()
+    g.close()

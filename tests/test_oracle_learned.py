@@ -119,6 +119,32 @@ def test_complex_mse_value_and_gradient():
         assert np.isclose(fd, dy[j], rtol=1e-6, atol=1e-12)
 
 
+def test_aligned_mse_is_phase_invariant_and_its_gradient_matches_finite_differences():
+    rng = np.random.default_rng(10)
+    y = rng.normal(0, 0.3, size=(2, 2, 5, 5))
+    t = np.exp(1j * rng.uniform(-1, 1, (5, 5))) * rng.uniform(0.6, 1.0, (5, 5))
+    mask = (rng.uniform(size=(5, 5)) > 0.3).astype(float)
+    loss, dy = ol.complex_mse_aligned(y, t, mask)
+    # a global phase added to the prediction changes nothing
+    y2 = y.copy()
+    y2[:, 1] += 1.234
+    assert np.isclose(ol.complex_mse_aligned(y2, t, mask)[0], loss, rtol=1e-12)
+    # the aligned loss is the minimum over a fine grid of global phases
+    for n in range(2):
+        one = y[n:n + 1]
+        best = min(ol.complex_mse(one + np.array([0, ph])[None, :, None, None], t, mask)[0]
+                   for ph in np.linspace(-np.pi, np.pi, 4001))
+        got = ol.complex_mse_aligned(one, t, mask)[0]
+        assert got <= best + 1e-12 and best - got < 1e-5
+    h = 1e-6
+    for j in [(0, 0, 1, 2), (1, 1, 3, 3), (1, 0, 0, 4), (0, 1, 2, 2)]:
+        yp, ym = y.copy(), y.copy()
+        yp[j] += h
+        ym[j] -= h
+        fd = (ol.complex_mse_aligned(yp, t, mask)[0] - ol.complex_mse_aligned(ym, t, mask)[0]) / (2 * h)
+        assert np.isclose(fd, dy[j], rtol=1e-6, atol=1e-11)
+
+
 def test_adam_first_steps_closed_form():
     rng = np.random.default_rng(6)
     p0 = rng.normal(size=50)
