@@ -125,6 +125,46 @@ def cpu_baseline(n, Q, offs, sqrt_d, levels, batch, alpha, seed, seconds):
     return done, time.perf_counter() - t0, nb
 
 
+def learned_race(n_objects: int):
+    """Wall time to 1e-3 relative object error, flat vs learned start (noiseless data)."""
+    import torch
+    from paper_2504_10118_amd import learned as L
+    params, meta = L.load_weights()
+    with torch.cuda.stream(torch.cuda.Stream()):
+        net = L.load_network(stream=L._current_stream())
+        res = L.race(net, L.held_out_objects(n_objects), target=1e-3, log=lambda s: None)
+        net.close()
+    plain = [r["plain"] for r in res]
+    learned = [r["learned"] for r in res]
+    ok = all(p["reached"] for p in plain) and all(q["reached"] for q in learned)
+    sp = [p["seconds"] / q["seconds"] for p, q in zip(plain, learned)]
+    return {
+        "metric": "wall time to 1e-3 relative object error, learned vs plain start",
+        "unit": "ms",
+        "higher_is_better": False,
+        "data": (f"noiseless intensities of {n_objects} held-out objects (the 512x512 workload's own object, "
+                 f"then objects of the same model from a seed outside the training set), same scan geometry, "
+                 f"3 levels, minibatch 256, error checked every 10 epochs off the clock"),
+        "plain_ms": [p["seconds"] * 1e3 for p in plain],
+        "learned_ms": [q["seconds"] * 1e3 for q in learned],
+        "plain_epochs": [p["epochs"] for p in plain],
+        "learned_epochs": [q["epochs"] for q in learned],
+        "learned_start_ms": [q["start_seconds"] * 1e3 for q in learned],
+        "start_error_plain": [p["error_start"] for p in plain],
+        "start_error_learned": [q["error_start"] for q in learned],
+        "learned_kept": [q["learned_used"] for q in learned],
+        "all_reached": ok,
+        "speedup_median": float(np.median(sp)),
+        "speedup_min": float(np.min(sp)),
+        "value_plain_median_ms": float(np.median([p["seconds"] * 1e3 for p in plain])),
+        "value_learned_median_ms": float(np.median([q["seconds"] * 1e3 for q in learned])),
+        "learned_includes": "input map + network inference + prolongation + the two objective evaluations of the fallback",
+        "training": {"samples": meta["train"], "epochs": meta["epochs"], "gpu_seconds": meta["train_seconds"],
+                     "data_seconds": meta["data_seconds"], "val_loss": meta["history"][-1]["val_loss"],
+                     "weights": "paper_2504_10118_amd/weights/" + os.path.basename(L.DEFAULT_WEIGHTS)},
+    }
+
+
 def bench_batched(args):
     """64 independent reconstructions of uneven size advanced together by the
     multi-context entry point (one launch per FFT plan / tile group per round)."""
@@ -135,9 +175,12 @@ def bench_batched(args):
     alpha = 0.5 if args.alpha is None else args.alpha
     specs = batched_workload()
     ctxs, batches, first = [], [], None
+    # torch (noise) and the contexts (forward model, loads) share one stream
+    st = torch.cuda.Stream()
+    torch.cuda.set_stream(st)
     for sp in specs:
         z_true, Q, offs, _ = make_batched_inputs(sp)
-        ctx = Magpie(sp.n, sp.n, sp.m, sp.levels, alpha, device=0)
+        ctx = Magpie(sp.n, sp.n, sp.m, sp.levels, alpha, device=0, stream=st.cuda_stream)
         ctx.set_probe(Q.astype(np.complex64))
         ctx.set_positions(offs)
         dt = torch.empty((sp.n_pos, sp.m, sp.m), dtype=torch.float32, device="cuda")
@@ -253,6 +296,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2504)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--race-objects", type=int, default=4,
+                    help="held-out objects of the learned-vs-plain time-to-1e-3 race (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -375,6 +420,8 @@ def main():
         "objective_after": phi,
         "stopping_statistic_after": stat,
     }
+    if args.race_objects > 0 and args.config == 2:
+        out["learned_race"] = learned_race(args.race_objects)
     if not args.no_cpu_baseline:
         sqrt_d = oracle_intensities(z_true, Q32, offs, cfg.peak, np.random.default_rng(args.seed))
         done, dt, nb = cpu_baseline(cfg.n, Q32, offs, sqrt_d, levels, batch, alpha, args.seed, args.cpu_seconds)

@@ -1,0 +1,368 @@
+"""Learned start: training set synthesis and training of the coarse-object network.
+
+Everything numeric runs in the HIP library: the forward model and the input
+map of each training object (a reconstruction context), the target
+(whole-object restriction), and the network's forward, loss, backward and
+Adam steps (:class:`CNN`).  This module only schedules those calls, shuffles
+minibatches and writes the trained parameters.
+
+Training geometry: the 512 x 512, 64 x 64-probe, 40 x 40 raster workload
+(1600 positions, step 10 px) at 1e4 peak photons.  Input: the 3 x 64 x 64 map
+(mean measured amplitude and the two diffraction centres of mass).  Target:
+the object restricted twice (128 x 128), which the prolongation maps back
+onto the three-level solver's fine grid.  Loss: masked complex MSE after
+removing the global phase, mask = coverage of the restricted illumination.
+
+Run ``python -m paper_2504_10118_amd.learned --help``.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from .magpie import CNN, Magpie, restrict_object
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(PKG, "weights", "coarse_cnn_512_m64.npz")
+SIDE = 64             # input map side
+LEVELS_DOWN = 2       # target = object restricted twice
+SEED_TRAIN = 250410118 + 5
+
+
+def geometry():
+    """Probe and scan of the 512 x 512 / 64 / 40 x 40 workload (fixed seed positions)."""
+    from synth import CONFIGS, make_problem_inputs
+    cfg = CONFIGS[2]
+    _, Q, offs, _, _ = make_problem_inputs(cfg)
+    return cfg, Q.astype(np.complex64), offs
+
+
+def coarse_mask(Q, offs, n: int, coarse: int) -> np.ndarray:
+    """Fraction of each coarse pixel's block with illumination >= 10 % of its maximum."""
+    m = Q.shape[0]
+    A = np.abs(Q.astype(np.complex128)) ** 2
+    ill = np.zeros((n, n))
+    for r, c in offs:
+        ill[r:r + m, c:c + m] += A
+    fine = (ill >= 0.1 * ill.max()).astype(np.float64)
+    f = n // coarse
+    return fine.reshape(coarse, f, coarse, f).mean(axis=(1, 3)).astype(np.float32)
+
+
+def init_params(seed: int, in_ch: int = 3, width: int = 32, in_mean=None, in_std=None) -> np.ndarray:
+    """He-normal weights, zero biases; the head starts at amplitude 0.9, phase 0.
+
+    With the input channels' mean and spread given, the first layer starts as
+    if its inputs were standardised: weights divided by the channel's spread,
+    biases shifted by the weighted means (the map's channels differ in scale
+    by orders of magnitude)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(width, in_ch), (width, width), (width, width), (width, width), (2, width)]
+    out = []
+    for i, (co, ci) in enumerate(shapes):
+        std = np.sqrt(2.0 / (9 * ci)) * (0.1 if i == len(shapes) - 1 else 1.0)
+        w = rng.normal(0.0, std, (co, ci, 9))
+        b = np.zeros(co)
+        if i == 0 and in_std is not None:
+            sd = np.maximum(np.asarray(in_std, dtype=np.float64), 1e-12)
+            w = w / sd[None, :, None]
+            b = b - (w * np.asarray(in_mean, dtype=np.float64)[None, :, None]).sum(axis=(1, 2))
+        if i == len(shapes) - 1:
+            b[0] = np.log(0.9)
+        out.append(w.ravel())
+        out.append(b)
+    return np.concatenate(out).astype(np.float32)
+
+
+def build_set(count: int, seed: int, peak, chunk: int = 128, log=print, noiseless_fraction: float = 0.0):
+    """(X [count, 3, 64, 64] float32, T [count, 128, 128] complex64) on the GPU, for objects of the
+    training model in the fixed geometry; peak = None gives noiseless data, otherwise each sample is
+    noiseless with probability noiseless_fraction and Poisson at `peak` photons otherwise."""
+    import torch
+    from synth import make_objects_device, poisson_counts_device
+    cfg, Q, offs = geometry()
+    n, m = cfg.n, cfg.m
+    # the context works on torch's current stream, so its kernels and torch's are ordered
+    ctx = Magpie(n, n, m, 1, 0.5, stream=_current_stream())
+    ctx.set_probe(Q)
+    ctx.set_positions(offs)
+    X = torch.empty((count, 3, SIDE, SIDE), dtype=torch.float32, device="cuda")
+    T = torch.empty((count, n >> LEVELS_DOWN, n >> LEVELS_DOWN), dtype=torch.complex64, device="cuda")
+    dt = torch.empty((len(offs), m, m), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(seed)
+    t0 = time.time()
+    for s in range(0, count, chunk):
+        k = min(chunk, count - s)
+        z = make_objects_device(k, n, rng, device="cuda")
+        restrict_object(z, LEVELS_DOWN, out=T[s:s + k])
+        for i in range(k):
+            ctx.forward_model(z[i], out=dt)
+            noisy = peak is not None and rng.random() >= noiseless_fraction
+            d = poisson_counts_device(dt, peak, int(rng.integers(0, 2**62))) if noisy else dt
+            ctx.load_intensities(d, is_sqrt=False)
+            ctx.input_map(SIDE, out=X[s + i])
+        ctx.sync()
+        if (s // chunk) % 20 == 0:
+            log(f"  built {s + k}/{count} samples ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    ctx.close()
+    return X, T
+
+
+def _current_stream() -> int:
+    """Handle of torch's current stream; it must not be the null stream (the library would
+    then create a stream of its own), so callers run under a torch.cuda.Stream."""
+    import torch
+    h = torch.cuda.current_stream().cuda_stream
+    if not h:
+        raise RuntimeError("run under `with torch.cuda.stream(torch.cuda.Stream())`")
+    return h
+
+
+def evaluate(net: CNN, X, T, mask_t, batch: int) -> float:
+    tot, n = 0.0, 0
+    for s in range(0, X.shape[0], batch):
+        k = min(batch, X.shape[0] - s)
+        net.forward(X[s:s + k])
+        tot += net.loss(T[s:s + k], mask_t, align_phase=True) * k
+        n += k
+    return tot / n
+
+
+def train(net: CNN, X, T, mask, epochs: int, batch: int, lr: float, seed: int, Xv=None, Tv=None, log=print):
+    """Adam with a cosine learning-rate decay over `epochs` passes of shuffled minibatches."""
+    import torch
+    mask_t = torch.as_tensor(mask, device="cuda")
+    rng = np.random.default_rng(seed)
+    N = X.shape[0]
+    steps = epochs * (N // batch)
+    hist = []
+    step = 0
+    t0 = time.time()
+    for ep in range(epochs):
+        order = torch.as_tensor(rng.permutation(N), device="cuda")
+        run = 0.0
+        nb = 0
+        for s in range(0, N - batch + 1, batch):
+            idx = order[s:s + batch]
+            xb = X.index_select(0, idx).contiguous()
+            tb = T.index_select(0, idx).contiguous()
+            net.forward(xb)
+            run += net.loss(tb, mask_t, align_phase=True)
+            net.backward(nbatch=batch)
+            cur = 0.5 * lr * (1.0 + np.cos(np.pi * step / steps))
+            net.adam_step(max(cur, 1e-6))
+            step += 1
+            nb += 1
+        val = evaluate(net, Xv, Tv, mask_t, batch) if Xv is not None else float("nan")
+        hist.append({"epoch": ep + 1, "train_loss": run / max(nb, 1), "val_loss": val,
+                     "seconds": time.time() - t0})
+        log(f"  epoch {ep + 1}/{epochs}: train {run / max(nb, 1):.5f}  val {val:.5f}  ({time.time() - t0:.1f} s)")
+    return hist
+
+
+def relative_error(z, z_true, mask) -> float:
+    """min over a global phase of ||e^{i phi} z - z*|| / ||z*|| on the mask (host, FP64)."""
+    a = np.asarray(z, dtype=np.complex128)[mask]
+    b = np.asarray(z_true, dtype=np.complex128)[mask]
+    ip = np.vdot(a, b)
+    ph = ip / abs(ip) if ip != 0 else 1.0
+    return float(np.linalg.norm(ph * a - b) / np.linalg.norm(b))
+
+
+def illumination_mask(Q, offs, n: int) -> np.ndarray:
+    m = Q.shape[0]
+    A = np.abs(np.asarray(Q, dtype=np.complex128)) ** 2
+    ill = np.zeros((n, n))
+    for r, c in offs:
+        ill[r:r + m, c:c + m] += A
+    return ill >= 0.1 * ill.max()
+
+
+def solve_to_error(ctx: Magpie, z_true, mask, target: float, batch: int, seed: int, start, net: CNN = None,
+                   check_every: int = 10, max_epochs: int = 4000):
+    """Run epochs from a flat start (start = 'flat') or the learned start (start = 'learned', with the
+    flat-start fallback) until the relative error reaches `target`.  Wall time of the solver calls
+    only (each chunk synchronised); the error checks between chunks run off the clock.
+    Returns a dict with seconds, epochs, error trace and the start's own error."""
+    import torch
+    torch.cuda.synchronize()
+    t_start = 0.0
+    used = False
+    if start == "flat":
+        ctx.set_object(np.ones((ctx.n_rows, ctx.n_cols), dtype=np.complex64))
+    else:
+        t0 = time.perf_counter()
+        used, _, _ = ctx.learned_start(net)
+        ctx.sync()
+        t_start = time.perf_counter() - t0
+    ctx.epoch_index = 0
+    err0 = relative_error(ctx.get_object(), z_true, mask)
+    trace = [(0, err0)]
+    t_solve = 0.0
+    e = 0
+    hit = None
+    while e < max_epochs:
+        t0 = time.perf_counter()
+        ctx.run_epochs(check_every, batch, seed=seed)
+        ctx.sync()
+        t_solve += time.perf_counter() - t0
+        e += check_every
+        err = relative_error(ctx.get_object(), z_true, mask)
+        trace.append((e, err))
+        if err <= target:
+            hit = e
+            break
+    return {"start": start, "learned_used": bool(used), "start_seconds": t_start, "solve_seconds": t_solve,
+            "seconds": t_start + t_solve, "epochs": hit, "reached": hit is not None, "error_start": err0,
+            "error_end": trace[-1][1], "trace": trace}
+
+
+def held_out_objects(count: int):
+    """The 512 x 512 workload's own object followed by count - 1 objects of the training model drawn
+    from a seed the training set does not use (complex64, host)."""
+    import torch
+    from synth import CONFIGS, make_problem_inputs, make_objects_device
+    z0 = make_problem_inputs(CONFIGS[2])[0].astype(np.complex64)
+    out = [z0]
+    if count > 1:
+        zs = make_objects_device(count - 1, CONFIGS[2].n, np.random.default_rng(SEED_TRAIN + 100), device="cuda")
+        out += [zs[i].cpu().numpy() for i in range(count - 1)]
+        del zs
+        torch.cuda.synchronize()
+    return out
+
+
+def race(net: CNN, objects, target: float = 1e-3, batch: int = 256, levels: int = 3, alpha: float = 0.5,
+         seed: int = 11, peak=None, check_every: int = 10, max_epochs: int = 4000, log=print):
+    """Time to `target` relative error from the flat and from the learned start on each object
+    (fixed geometry; noiseless data unless peak is given)."""
+    import torch
+    from synth import poisson_counts
+    cfg, Q, offs = geometry()
+    n, m = cfg.n, cfg.m
+    mask = illumination_mask(Q, offs, n)
+    ctx = Magpie(n, n, m, levels, alpha, stream=_current_stream())
+    ctx.set_probe(Q)
+    ctx.set_positions(offs)
+    res = []
+    for i, z in enumerate(objects):
+        d = ctx.forward_model(np.asarray(z, dtype=np.complex64))
+        if peak is not None:
+            d = poisson_counts(d, peak, np.random.default_rng(seed + i)).astype(np.float32)
+        ctx.load_intensities(d, is_sqrt=False)
+        plain = solve_to_error(ctx, z, mask, target, batch, seed, "flat", check_every=check_every,
+                               max_epochs=max_epochs)
+        learned = solve_to_error(ctx, z, mask, target, batch, seed, "learned", net, check_every=check_every,
+                                 max_epochs=max_epochs)
+        log(f"  object {i}: flat {plain['epochs']} epochs {plain['seconds'] * 1e3:.1f} ms (start err "
+            f"{plain['error_start']:.3f}); learned {learned['epochs']} epochs {learned['seconds'] * 1e3:.1f} ms "
+            f"(start err {learned['error_start']:.3f}, used {learned['learned_used']})")
+        res.append({"plain": plain, "learned": learned})
+    torch.cuda.synchronize()
+    ctx.close()
+    return res
+
+
+def save_weights(path: str, params: np.ndarray, meta: dict):
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, params=params.astype(np.float32), meta=np.array(json.dumps(meta)))
+
+
+def load_weights(path: str = DEFAULT_WEIGHTS):
+    """(params float32, meta dict) from a file written by save_weights (no pickles)."""
+    with np.load(path, allow_pickle=False) as f:
+        return f["params"].astype(np.float32), json.loads(str(f["meta"]))
+
+
+def load_network(path: str = DEFAULT_WEIGHTS, weight_dtype: int = 0, max_batch: int = 1, stream=None) -> CNN:
+    params, meta = load_weights(path)
+    net = CNN(in_ch=meta["in_ch"], side=meta["side"], max_batch=max_batch, weight_dtype=weight_dtype,
+              stream=stream)
+    net.set_params(params)
+    return net
+
+
+def net_eval(params, weight_dtype: int = 0) -> CNN:
+    net = CNN(in_ch=3, side=SIDE, max_batch=1, weight_dtype=weight_dtype, stream=_current_stream())
+    net.set_params(params)
+    return net
+
+
+def main():
+    ap = argparse.ArgumentParser(description="Train the learned-start network on the GPU.")
+    ap.add_argument("--train", type=int, default=20000, help="training objects")
+    ap.add_argument("--val", type=int, default=512, help="validation objects")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--peak", type=float, default=1e4, help="peak photons of the training data (0: noiseless)")
+    ap.add_argument("--noiseless-fraction", type=float, default=0.5,
+                    help="share of training samples drawn without noise (the rest at --peak photons)")
+    ap.add_argument("--weight-dtype", type=int, default=0, help="0: FP32 weights, 1: BF16 weights")
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--race-objects", type=int, default=3, help="objects in the closing time-to-1e-3 race")
+    args = ap.parse_args()
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    peak = None if args.peak <= 0 else args.peak
+    with torch.cuda.stream(torch.cuda.Stream()):
+        run_training(args, peak)
+
+
+def run_training(args, peak):
+    import torch
+    cfg, Q, offs = geometry()
+    mask = coarse_mask(Q, offs, cfg.n, cfg.n >> LEVELS_DOWN)
+    print(f"building {args.train} training + {args.val} validation samples", flush=True)
+    t0 = time.time()
+    X, T = build_set(args.train, SEED_TRAIN, peak, log=lambda s: print(s, flush=True),
+                     noiseless_fraction=args.noiseless_fraction)
+    Xv, Tv = build_set(args.val, SEED_TRAIN + 1, peak, log=lambda s: print(s, flush=True),
+                       noiseless_fraction=args.noiseless_fraction)
+    t_data = time.time() - t0
+    xs = X[:, :, 8:-8, 8:-8]
+    mean = [float(xs[:, c].mean()) for c in range(3)]
+    std = [float(xs[:, c].std()) for c in range(3)]
+    print("input channel mean/std (interior):", list(zip(mean, std)), flush=True)
+    net = CNN(in_ch=3, side=SIDE, max_batch=args.batch, weight_dtype=args.weight_dtype, stream=_current_stream())
+    net.set_params(init_params(SEED_TRAIN + 2, in_mean=mean, in_std=std))
+    mask_t = torch.as_tensor(mask, device="cuda")
+    base = evaluate(net, Xv, Tv, mask_t, args.batch)
+    print(f"validation loss at init: {base:.5f}", flush=True)
+    t1 = time.time()
+    hist = train(net, X, T, mask, args.epochs, args.batch, args.lr, SEED_TRAIN + 3, Xv, Tv,
+                 log=lambda s: print(s, flush=True))
+    t_train = time.time() - t1
+    params = net.get_params()
+    meta = {"in_ch": 3, "side": SIDE, "width": 32, "levels_down": LEVELS_DOWN, "train": args.train,
+            "val": args.val, "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "peak": args.peak,
+            "noiseless_fraction": args.noiseless_fraction,
+            "weight_dtype": args.weight_dtype, "seed": SEED_TRAIN, "val_loss_init": base,
+            "history": hist, "data_seconds": t_data, "train_seconds": t_train,
+            "geometry": f"object {cfg.n}, probe {cfg.m}, {cfg.P}x{cfg.P} raster step {cfg.step}"}
+    print("race to 1e-3 relative error, noiseless data:", flush=True)
+    objs = held_out_objects(args.race_objects)
+    ev = net_eval(params, args.weight_dtype)
+    rr = race(ev, objs, log=lambda s: print(s, flush=True))
+    if peak is not None:
+        print(f"start errors at {peak:g} photons:", flush=True)
+        race(ev, objs[:2], peak=peak, max_epochs=10, log=lambda s: print(s, flush=True))
+    meta["race"] = [{"plain_epochs": r["plain"]["epochs"], "learned_epochs": r["learned"]["epochs"],
+                     "plain_ms": r["plain"]["seconds"] * 1e3, "learned_ms": r["learned"]["seconds"] * 1e3,
+                     "plain_err0": r["plain"]["error_start"], "learned_err0": r["learned"]["error_start"],
+                     "learned_used": r["learned"]["learned_used"]} for r in rr]
+    save_weights(args.out, params, meta)
+    print(json.dumps({"out": args.out, "val_loss_init": base, "val_loss": hist[-1]["val_loss"],
+                      "data_seconds": t_data, "train_seconds": t_train}), flush=True)
+    net.close()
+
+
+if __name__ == "__main__":
+    main()

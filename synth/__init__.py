@@ -28,4 +28,5 @@ from .generators import (  # noqa: F401
     BatchedRecon,
     batched_workload,
     make_batched_inputs,
+    make_objects_device,
 )

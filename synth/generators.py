@@ -213,3 +213,41 @@ def poisson_counts_device(dtilde, peak: float, seed: int):
     gen.manual_seed(int(seed))
     sigma = float(peak) / float(dtilde.max())
     return torch.poisson(dtilde * sigma, generator=gen) / sigma
+
+
+def make_objects_device(count: int, n: int, rng: np.random.Generator, device="cuda", rectangles: bool = True):
+    """`count` objects of the make_object model as a complex64 torch tensor [count, n, n] on `device`.
+
+    Same distribution as :func:`make_object` (amplitude U[0.8, 1]; 8 Gaussian
+    phase bumps min-max mapped to [-pi/2, pi/2]; 20 rectangles of +0.5 rad),
+    with the per-object parameters drawn from `rng` and the pixel fields
+    evaluated on the device; the amplitude noise comes from a torch generator
+    seeded from `rng`.  Used where many objects are needed (training sets).
+    """
+    import torch
+    mu = rng.uniform(0.0, n, size=(count, 8, 2))
+    sig = rng.uniform(4.0, 16.0, size=(count, 8))
+    c = rng.uniform(-1.0, 1.0, size=(count, 8))
+    smin, smax = max(1, n // 32), max(1, n // 8)
+    r0 = rng.integers(0, n, size=(count, 20, 2))
+    hw = rng.integers(smin, smax + 1, size=(count, 20, 2))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(rng.integers(0, 2**62)))
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device)  # noqa: E731
+    ax = torch.arange(n, dtype=torch.float64, device=device)
+    s2 = 2.0 * t(sig) ** 2
+    gy = torch.exp(-(ax[None, None, :] - t(mu[..., 0])[..., None]) ** 2 / s2[..., None])   # [count, 8, n]
+    gx = torch.exp(-(ax[None, None, :] - t(mu[..., 1])[..., None]) ** 2 / s2[..., None])
+    phase = torch.einsum("bk,bky,bkx->byx", t(c), gy, gx)
+    lo = phase.amin(dim=(1, 2), keepdim=True)
+    hi = phase.amax(dim=(1, 2), keepdim=True)
+    span = torch.where(hi > lo, hi - lo, torch.ones_like(hi))
+    phase = torch.where(hi > lo, (phase - lo) / span * math.pi - math.pi / 2.0, torch.zeros_like(phase))
+    if rectangles:
+        ry = ((ax[None, None, :] >= t(r0[..., 0])[..., None]) &
+              (ax[None, None, :] < t(r0[..., 0] + hw[..., 0])[..., None])).to(torch.float64)
+        rx = ((ax[None, None, :] >= t(r0[..., 1])[..., None]) &
+              (ax[None, None, :] < t(r0[..., 1] + hw[..., 1])[..., None])).to(torch.float64)
+        phase = phase + 0.5 * torch.einsum("bky,bkx->byx", ry, rx)
+    amp = 0.8 + 0.2 * torch.rand((count, n, n), generator=gen, device=device, dtype=torch.float64)
+    return torch.polar(amp, phase).to(torch.complex64)

@@ -318,3 +318,45 @@ def test_learned_start_falls_back_to_the_flat_start():
     assert np.max(np.abs(g.get_object() - ol.prolong_object(zc, 1))) <= 1e-6
     net.close()
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# The trained network (weights shipped with the package)
+# ---------------------------------------------------------------------------
+def test_trained_network_gains_over_the_flat_start():
+    """On held-out objects (noiseless data, the 512 / 64 / 40 x 40 geometry) the learned start is
+    kept by the fallback rule, starts from a much smaller error and reaches 3e-3 relative
+    error in fewer epochs than the flat start."""
+    import torch
+    from paper_2504_10118_amd import learned as L
+    with torch.cuda.stream(torch.cuda.Stream()):
+        net = L.load_network(stream=L._current_stream())
+        objs = L.held_out_objects(3)
+        res = L.race(net, objs, target=3e-3, check_every=10, max_epochs=3000, log=lambda s: None)
+        net.close()
+    tot_plain = tot_learned = 0
+    for r in res:
+        p, q = r["plain"], r["learned"]
+        assert q["learned_used"]
+        assert q["error_start"] < 0.6 * p["error_start"]
+        assert p["reached"] and q["reached"]
+        assert q["epochs"] < p["epochs"]
+        tot_plain += p["epochs"]
+        tot_learned += q["epochs"]
+    assert tot_learned < 0.7 * tot_plain
+
+
+def test_trained_network_bf16_weights_give_the_same_start():
+    import torch
+    from paper_2504_10118_amd import W_BF16
+    from paper_2504_10118_amd import learned as L
+    with torch.cuda.stream(torch.cuda.Stream()):
+        n32 = L.load_network(stream=L._current_stream())
+        n16 = L.load_network(weight_dtype=W_BF16, stream=L._current_stream())
+        objs = L.held_out_objects(1)
+        r32 = L.race(n32, objs, max_epochs=10, log=lambda s: None)[0]["learned"]
+        r16 = L.race(n16, objs, max_epochs=10, log=lambda s: None)[0]["learned"]
+        n32.close()
+        n16.close()
+    assert r32["learned_used"] and r16["learned_used"]
+    assert abs(r16["error_start"] - r32["error_start"]) < 0.01
