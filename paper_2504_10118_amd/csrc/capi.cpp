@@ -32,7 +32,7 @@ int free_positions(magpie_ctx* c) {
 
 int rebuild_levels(magpie_ctx* c) {
   MG_HIP(mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->w0f, c->u0f,
-                                    c->qf, c->lvl, c->scr_q, c->scr_u, c->stream));
+                                    c->qf, c->lvl, c->lvl_a_off, c->scr_q, c->scr_u, c->rb, c->qtab, c->stream));
   return MAGPIE_OK;
 }
 
@@ -133,11 +133,14 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   const size_t half = (size_t)(m / 2) * (m / 2);
   size_t nlvl = 0;
   for (int l = 1; l < n_levels; ++l) nlvl += 3 * (size_t)(m >> l) * (m >> l);
+  nlvl = (nlvl + 1) & ~(size_t)1;          // the A block starts 16-byte aligned (read as double pairs)
   c->lvl_a_off = (int)nlvl;
   nlvl += (size_t)(n_levels - 1) * half;   // A_l coefficients per level-1 bin
   for (int l = 1; l <= n_levels - 2; ++l) nlvl += (size_t)(m >> l) * (m >> l);  // copies of V_l
+  nlvl += 2;                               // a pair read may cover one double past the block
   rc = dev_alloc(&c->z, (size_t)n_rows * n_cols);
   if (!rc) rc = dev_alloc(&c->qf, mm);
+  if (!rc) rc = dev_alloc(&c->qtab, mm);
   if (!rc) rc = dev_alloc(&c->q64, mm);
   if (!rc) rc = dev_alloc(&c->u0, mm);
   if (!rc) rc = dev_alloc(&c->w0, mm);
@@ -178,6 +181,7 @@ int magpie_destroy(magpie_ctx* c) {
   free_positions(c);
   dev_free(c->z);
   dev_free(c->qf);
+  dev_free(c->qtab);
   dev_free(c->q64);
   dev_free(c->u0);
   dev_free(c->w0);
@@ -496,6 +500,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   sa.n_rows = c->nr;
   sa.n_cols = c->nc;
   sa.q = c->qf;
+  sa.qtab = c->qtab;
   sa.sqrtd = c->sqrtd;
   sa.offs = c->offs;
   sa.stage = c->stage;
@@ -515,7 +520,8 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
     hipError_t e = mg::launch_probe_apply(m, count, nw, c->pnum, c->pden, c->pmax, c->beta, c->q64, c->stream);
     if (e == hipSuccess)
       e = mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->w0f,
-                                     c->u0f, c->qf, c->lvl, c->scr_q, c->scr_u, c->stream);
+                                     c->u0f, c->qf, c->lvl, c->lvl_a_off, c->scr_q, c->scr_u, c->rb, c->qtab,
+                                     c->stream);
     return e;
   };
   mg::AccumArgs aa{};
@@ -606,6 +612,7 @@ int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {
   sa.n_rows = c->nr;
   sa.n_cols = c->nc;
   sa.q = c->qf;
+  sa.qtab = c->qtab;
   sa.sqrtd = c->sqrtd;
   sa.offs = c->offs;
   sa.perm = nullptr;
@@ -729,6 +736,7 @@ int magpie_forward_model(magpie_ctx* c, const void* z, int z_on_device, float* d
   sa.n_rows = c->nr;
   sa.n_cols = c->nc;
   sa.q = c->qf;
+  sa.qtab = c->qtab;
   sa.offs = c->offs;
   sa.perm = nullptr;
   sa.count = c->n_pos;
@@ -815,6 +823,10 @@ int magpie_set_tuning(magpie_ctx* c, int threads_per_transform, int tile_rows) {
       if (e != hipSuccess) return fail(MAGPIE_ERR_HIP, std::string("re-layout of sqrt(d): ") + hipGetErrorString(e));
     }
     c->rb = rb;
+    if (c->has_probe) {
+      rc = rebuild_levels(c);   // the probe table follows the plan's thread order
+      if (rc) return rc;
+    }
     if (c->has_pos) {
       std::vector<double> nan((size_t)c->n_pos * mg::MAX_WAVES, std::nan(""));
       MG_HIP(hipMemcpy(c->step_part, nan.data(), nan.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -991,6 +1003,7 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
         a.n_rows = c->nr;
         a.n_cols = c->nc;
         a.q = c->qf;
+        a.qtab = c->qtab;
         a.sqrtd = c->sqrtd;
         a.offs = c->offs;
         a.stage = c->stage;

@@ -94,6 +94,7 @@ struct magpie_ctx {
   // device buffers
   float2* z = nullptr;
   float2* qf = nullptr;
+  float4* qtab = nullptr;   // (Re Q, Im Q, u0, 0) in the current plan's thread order
   double2* q64 = nullptr;
   double* u0 = nullptr;
   double* w0 = nullptr;

@@ -24,6 +24,7 @@ struct StepArgs {
   int count;              // number of workgroups / positions
   float2* stage;          // MODE_STEP: c_k = w0 * dz_k, natural order [count][m][m]
   const float* u0f;       // fine-grid u [m][m]
+  const float4* qtab;     // (Re Q, Im Q, u0, 0) in the plan's thread order: [n1][tid], pixel (RB*n1 + g, col)
   const double* lvl;      // coarse-level constants (V, rho, r per level), then A_l
   int lvl_a_off;          // offset in lvl of the in-wave V-cycle block: A_1..A_{L-1}, then V_1..V_{L-2}
   int levels;             // number of grids L
@@ -78,8 +79,8 @@ hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, in
                                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given,
                                   const double2* q64, double* u0, double* w0, float* w0f, float* u0f,
-                                  float2* qf, double* lvl, double2* scr_q, double* scr_u,
-                                  hipStream_t s);
+                                  float2* qf, double* lvl, int lvl_a_off, double2* scr_q, double* scr_u, int rb,
+                                  float4* qtab, hipStream_t s);
 hipError_t launch_permute_sqrt(int m, int rb, int n_pos, const float* src, int is_sqrt, float* dst,
                                int* bad_flag, hipStream_t s);
 hipError_t launch_unpermute_sqrt(int m, int rb, int n_pos, const float* src, float* dst, hipStream_t s);

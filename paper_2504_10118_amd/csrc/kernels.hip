@@ -62,6 +62,21 @@ __device__ __forceinline__ float2 twiddle(int j) {
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
+// w[j] = W_M^(b j) for 0 < j < R: the power-of-two exponents are read from
+// the table, every other one is the product of its highest power of two and
+// the remainder.
+template <int M, int R>
+__device__ __forceinline__ void powers(int b, float2 (&w)[R]) {
+#pragma unroll
+  for (int j = 1; j < R; j <<= 1) w[j] = twiddle<M>(b * j);
+#pragma unroll
+  for (int j = 3; j < R; ++j) {
+    if ((j & (j - 1)) == 0) continue;
+    const int hb = 1 << ilog2c(j);   // highest power of two <= j
+    w[j] = cmul(w[hb], w[j - hb]);
+  }
+}
+
 // In-wave V-cycle block (doubles): A_1..A_{L-1} at level-1 resolution, then
 // V_1..V_{L-2} at their own resolutions.
 __host__ __device__ constexpr int cst_count(int M, int L) {
@@ -228,32 +243,34 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // patch rows y = RB*n1 + g: per-lane byte offset (g, col), per-row scalar offset n1
   const float2* zbase = a.z + (size_t)off.x * a.n_cols + off.y;
   const rsrc_t zr = make_rsrc(zbase, (unsigned)(((size_t)(a.n_rows - off.x) * a.n_cols - off.y) * sizeof(float2)));
-  const rsrc_t qr = make_rsrc(a.q, (unsigned)(M * M * sizeof(float2)));
   const int zvo = (g * a.n_cols + col) * (int)sizeof(float2);
   const int zso = RB * a.n_cols * (int)sizeof(float2);
-  const int qvo = (g * M + col) * (int)sizeof(float2);
   constexpr int qso = RB * M * (int)sizeof(float2);
+  const float4* qt = a.qtab + tid;   // [n1][tid]: each load reads one contiguous block
   constexpr bool KEEP = (M <= 64);
+  constexpr bool CST = (MODE == MODE_STEP) && (M <= 64);
   float2 zk[KEEP ? RA : 1], qk[KEEP ? RA : 1];
+  float u0k[CST ? RA : 1];
 #pragma unroll
   for (int n1 = 0; n1 < RA; ++n1) {
-    const float2 qq = bload2(qr, qvo, n1 * qso);
+    const float4 t = qt[n1 * TPB];
+    const float2 qq = make_float2(t.x, t.y);
     const float2 zz = bload2(zr, zvo, n1 * zso);
     if constexpr (KEEP) {
       zk[n1] = zz;
       qk[n1] = qq;
     }
+    if constexpr (CST) u0k[n1] = t.z;
     v[n1] = cmul(qq, zz);
   }
   // twiddles: stage A uses W_M^(g k1); the inverse stage B uses W_M^(n2 (g CB + c)).
-  // At M = 128 (16 points per thread, 128 VGPRs) they are re-read at each use
+  // Powers of two of the base come from the table, the other exponents are
+  // products of two earlier ones (at most log2 RA roundings deep).
+  // At M = 128 (16 points per thread, 128 VGPRs) they are re-formed at each use
   // and sqrt(d) is fetched just before the row pass instead of at the start.
   constexpr bool LAZY = (M >= 128);
   float2 twA[RA];
-  auto load_twA = [&]() {
-#pragma unroll
-    for (int k1 = 1; k1 < RA; ++k1) twA[k1] = twiddle<M>(g * k1);
-  };
+  auto load_twA = [&]() { powers<M, RA>(g, twA); };
   load_twA();
   float sd[RA];
   auto load_sd = [&]() {
@@ -267,24 +284,23 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     }
   };
   if constexpr (!LAZY) load_sd();
-  // In-wave V-cycle constants (A_l, V_l; M <= 64): fetched now, parked in LDS
-  // at the first barrier, so their latency hides behind the forward FFT.
-  constexpr bool CST = (MODE == MODE_STEP) && (M <= 64);
+  // In-wave V-cycle constants (A_l, V_l; M <= 64): fetched now as 16-byte
+  // pairs (the block starts at an even offset and is padded by one double),
+  // parked in LDS at the first barrier, so their latency hides behind the
+  // forward FFT.
   constexpr int M1c = M / 2;
-  constexpr int CST_MAX = CST ? cst_count_max(M, LW) : 1;
-  constexpr int CST_PER = (CST_MAX + TPB - 1) / TPB;
+  constexpr int CST_MAX = CST ? cst_count_max(M, LW) : 2;
+  constexpr int CST_PER = ((CST_MAX + 1) / 2 + TPB - 1) / TPB;   // double2 per thread
   double* const Cst = reinterpret_cast<double*>(T + M * P);
   const int nCst = (CST && a.levels >= 2 && a.levels - 1 <= LW) ? cst_count(M, a.levels) : 0;
-  double cst[CST_PER];
-  float u0k[CST ? RA : 1];
+  double2 cst[CST_PER];
   if constexpr (CST) {
+    const double2* src = reinterpret_cast<const double2*>(a.lvl + a.lvl_a_off);
 #pragma unroll
     for (int i = 0; i < CST_PER; ++i) {
       const int e = tid + i * TPB;
-      cst[i] = (e < nCst) ? a.lvl[a.lvl_a_off + e] : 0.0;
+      cst[i] = (2 * e < nCst) ? src[e] : make_double2(0.0, 0.0);
     }
-#pragma unroll
-    for (int n1 = 0; n1 < RA; ++n1) u0k[n1] = a.u0f[(RB * n1 + g) * M + col];
   }
 
   // ---- forward, columns: stage A (radix RA over n1), twiddle, exchange, stage B
@@ -309,7 +325,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   if constexpr (CST) {
 #pragma unroll
     for (int i = 0; i < CST_PER; ++i)
-      if (tid + i * TPB < nCst) Cst[tid + i * TPB] = cst[i];
+      if (2 * (tid + i * TPB) < nCst) reinterpret_cast<double2*>(Cst)[tid + i * TPB] = cst[i];
   }
   __syncthreads();
 
@@ -371,9 +387,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       dft<RB, -1>(&v[c * RB]);
+      float2 twB[RB];
+      if constexpr (CB == 1) {
 #pragma unroll
-      for (int n2 = 1; n2 < RB; ++n2)
-        v[c * RB + n2] = cmulc(CB == 1 ? twA[n2] : twiddle<M>(n2 * (g * CB + c)), v[c * RB + n2]);
+        for (int n2 = 1; n2 < RB; ++n2) twB[n2] = twA[n2];
+      } else {
+        powers<M, RB>(g * CB + c, twB);
+      }
+#pragma unroll
+      for (int n2 = 1; n2 < RB; ++n2) v[c * RB + n2] = cmulc(twB[n2], v[c * RB + n2]);
     }
     wave_sync();
 #pragma unroll
@@ -398,9 +420,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       dft<RB, -1>(&v[c * RB]);
+      float2 twB[RB];
+      if constexpr (CB == 1) {
 #pragma unroll
-      for (int n2 = 1; n2 < RB; ++n2)
-        v[c * RB + n2] = cmulc(CB == 1 ? twA[n2] : twiddle<M>(n2 * (g * CB + c)), v[c * RB + n2]);
+        for (int n2 = 1; n2 < RB; ++n2) twB[n2] = twA[n2];
+      } else {
+        powers<M, RB>(g * CB + c, twB);
+      }
+#pragma unroll
+      for (int n2 = 1; n2 < RB; ++n2) v[c * RB + n2] = cmulc(twB[n2], v[c * RB + n2]);
     }
     wave_sync();
 #pragma unroll
@@ -422,7 +450,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         qq = qk[n1];
         zz = zk[n1];
       } else {
-        qq = bload2(qr, qvo, n1 * qso);
+        const float4 t = qt[n1 * TPB];
+        qq = make_float2(t.x, t.y);
         zz = bload2(zr, zvo, n1 * zso);
       }
       const float2 rk = cscale(v[n1], inv_m2);
@@ -527,7 +556,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
           for (int i = 0; i < NC; ++i) {
             const int y = RB * (n0 + i) + g;
-            const double uu = CST ? (double)u0k[n0 + i] : (double)a.u0f[y * M + col];
+            double uu;
+            if constexpr (CST) uu = (double)u0k[n0 + i];
+            else uu = (double)qt[(n0 + i) * TPB].z;
             bstore2(outr,
                     make_float2((float)(uu * e1[i].x - (double)v[n0 + i].x),
                                 (float)(uu * e1[i].y - (double)v[n0 + i].y)),
@@ -566,7 +597,7 @@ static size_t lds_bytes_m() {
   constexpr int TPB = M * RB, P = M + Plan<M, RB>::PAD;
   constexpr int LW = ilog2c((TPB < 64 ? TPB : 64) / RB);
   size_t b = (size_t)M * P * sizeof(float2);
-  if (M <= 64) b += (size_t)cst_count_max(M, LW) * sizeof(double);
+  if (M <= 64) b += (size_t)((cst_count_max(M, LW) + 1) & ~1) * sizeof(double);
   return b;
 }
 
@@ -831,7 +862,7 @@ hipError_t launch_accumulate(const AccumArgs& a, int th, int n_tiles, hipStream_
 __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels, double alpha, int u_given,
                                                                const double2* q64, double* u0, double* w0,
                                                                float* w0f, float* u0f, float2* qf, double* lvl,
-                                                               double2* scr_q, double* scr_u) {
+                                                               int a_off, double2* scr_q, double* scr_u) {
   __shared__ double red[1024];
   const int tid = threadIdx.x;
   const int n0 = m * m;
@@ -910,7 +941,7 @@ __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels
   __syncthreads();
   if (levels > 1) {
     const int M1 = m / 2;
-    double* A = lvl + lv;
+    double* A = lvl + a_off;
     for (int e = tid; e < M1 * M1; e += blockDim.x) {
       const int Y1 = e / M1, X1 = e % M1;
       double prod = 1.0;
@@ -937,12 +968,36 @@ __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels
   }
 }
 
+// (Re Q, Im Q, u0, 0) per pixel in the thread order of plan (M, RB): entry
+// [n1][tid] belongs to thread tid = g + RB*col at pixel (RB*n1 + g, col), so
+// each of the step kernel's loads of this table reads one contiguous block.
+template <int M, int RB>
+__global__ void qtab_kernel(const float2* qf, const float* u0f, float4* qtab) {
+  constexpr int TPB = M * RB;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int n1 = e / TPB, tid = e - n1 * TPB, g = tid & (RB - 1), col = tid / RB;
+  const int i = (RB * n1 + g) * M + col;
+  const float2 q = qf[i];
+  qtab[e] = make_float4(q.x, q.y, u0f[i], 0.0f);
+}
+
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given, const double2* q64,
                                   double* u0, double* w0, float* w0f, float* u0f, float2* qf, double* lvl,
-                                  double2* scr_q, double* scr_u, hipStream_t s) {
+                                  int lvl_a_off, double2* scr_q, double* scr_u, int rb, float4* qtab,
+                                  hipStream_t s) {
   hipLaunchKernelGGL(level_constants_kernel, dim3(1), dim3(1024), 0, s, m, levels, alpha, u_given, q64, u0,
-                     w0, w0f, u0f, qf, lvl, scr_q, scr_u);
-  return hipGetLastError();
+                     w0, w0f, u0f, qf, lvl, lvl_a_off, scr_q, scr_u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+#define MG_QT(MM, RR)                                                                                     \
+  if (m == MM && rb == RR) {                                                                              \
+    hipLaunchKernelGGL((qtab_kernel<MM, RR>), dim3((MM * MM + 255) / 256), dim3(256), 0, s, qf, u0f, qtab); \
+    return hipGetLastError();                                                                             \
+  }
+  MG_FOR_EACH_PLAN(MG_QT)
+#undef MG_QT
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
