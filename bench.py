@@ -296,6 +296,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2504)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT plan and tile height")
     ap.add_argument("--race-objects", type=int, default=4,
                     help="held-out objects of the learned-vs-plain time-to-1e-3 race (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -340,6 +341,10 @@ def main():
     d = poisson_counts(dtilde, cfg.peak, r_noise).astype(np.float32)
     ctx.load_intensities(d, is_sqrt=False)
     ctx.set_object(np.ones((cfg.n, cfg.n), dtype=np.complex64))
+    tuning = None
+    if not args.no_autotune:
+        rb, th, su, au = ctx.autotune(batch)             # the library's own autotuner, on this data
+        tuning = {"threads_per_transform": rb, "tile_rows": th, "trial_step_us": su, "trial_accumulate_us": au}
     if args.warmup:
         ctx.run_epochs(args.warmup, batch, seed=args.seed + 1)
     ctx.sync()
@@ -365,6 +370,7 @@ def main():
     ctx.run_epochs(args.steps, batch, seed=args.seed)
     tm = ctx.get_timing()                                    # synchronises
     t3 = time.perf_counter()
+    ctx_tile_rows = ctx.get_tuning()[1]
     ctx.close()
 
     wall = t1 - t0
@@ -373,7 +379,8 @@ def main():
     bytes_per_pattern = 20 * m * m          # sqrt(d) 4 m^2 + patch read 8 m^2 + staged update 8 m^2
     step_s = tm["step_ms"] * 1e-3
     achieved = tm["positions"] * bytes_per_pattern / step_s / 1e9 if step_s > 0 else None
-    n_tiles = ((cfg.n + 63) // 64) * ((cfg.n + 15) // 16)
+    th_used = ctx_tile_rows
+    n_tiles = ((cfg.n + 63) // 64) * ((cfg.n + th_used - 1) // th_used)
     traffic = stored_traffic(args.config, m) if batch == cfg.batch and levels == cfg.levels else None
     out = {
         "metric": "diffraction patterns/s (fused step)",
@@ -392,6 +399,7 @@ def main():
             "workload": describe(cfg, batch, levels, alpha),
             "object": cfg.n, "probe": m, "positions": N, "levels": levels, "batch": batch,
             "step": f"one epoch = {N} patterns in {(N + batch - 1) // batch} minibatches",
+            "tuning": tuning,
         },
         "roofline": {
             "bound": "hbm",

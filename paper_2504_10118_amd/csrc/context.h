@@ -82,7 +82,7 @@ struct magpie_ctx {
   bool own_stream = false;
   int nr = 0, nc = 0, m = 0, L = 1;
   int rb = 0;    // FFT plan of the step kernel (threads per 1-D transform)
-  int th = 16;   // accumulate tile height
+  int th = 8;    // accumulate tile height
   double alpha = 0.0;
   uint32_t flags = 0;
   double beta = 0.0;

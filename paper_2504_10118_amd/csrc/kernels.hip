@@ -795,7 +795,7 @@ static void launch_accumulate_t(const AccumArgs& a, int n_tiles, hipStream_t s, 
     hipLaunchKernelGGL(accumulate_kernel<TH>, dim3(n_tiles), dim3(ACC_THREADS), 0, s, a);
 }
 
-bool tile_valid(int th) { return th == 8 || th == 16 || th == 32; }
+bool tile_valid(int th) { return th == 4 || th == 8 || th == 16 || th == 32; }
 
 hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s,
                              hipEvent_t ev0, hipEvent_t ev1) {
@@ -831,6 +831,7 @@ hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, in
                                    hipEvent_t ev0, hipEvent_t ev1) {
   if (n_ctx <= 0 || max_tiles <= 0) return hipSuccess;
   switch (th) {
+    case 4: launch_acc_multi_t<4>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
     case 8: launch_acc_multi_t<8>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
     case 16: launch_acc_multi_t<16>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
     case 32: launch_acc_multi_t<32>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
@@ -843,6 +844,7 @@ hipError_t launch_accumulate(const AccumArgs& a, int th, int n_tiles, hipStream_
                              hipEvent_t ev1) {
   if (n_tiles <= 0) return hipSuccess;
   switch (th) {
+    case 4: launch_accumulate_t<4>(a, n_tiles, s, ev0, ev1); break;
     case 8: launch_accumulate_t<8>(a, n_tiles, s, ev0, ev1); break;
     case 16: launch_accumulate_t<16>(a, n_tiles, s, ev0, ev1); break;
     case 32: launch_accumulate_t<32>(a, n_tiles, s, ev0, ev1); break;
