@@ -1,6 +1,6 @@
 // gfx950 kernels of the MAGPIE hot path (arXiv 2504.10118).
 //
-// step_kernel<M, MODE>  one workgroup per scan position: gather z_k, exit wave
+// step_kernel<M, RB, MODE>  one workgroup per scan position: gather z_k, exit wave
 //                       Q * z_k, LDS-resident 2-D FFT, modulus replacement
 //                       (Definition 2.1), inverse FFT, gradient
 //                       g0 = conj(Q)(Q z_k - R_k) (eq. 2.2), MAGPS V-cycle in
@@ -90,6 +90,63 @@ __host__ __device__ constexpr int cst_v_off(int M, int L, int l) {
   return n;
 }
 constexpr int cst_count_max(int M, int LW) { return cst_count(M, LW + 1); }
+
+// Argument blocks read from memory through the constant address space: the
+// loads are scalar and the compiler may re-read a field instead of keeping it
+// live, so a descriptor costs no vector registers.
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+
+__device__ __forceinline__ StepArgs load_step_args(const StepArgs* p) {
+  const const_ptr<StepArgs> d = (const_ptr<StepArgs>)p;
+  StepArgs a;
+  a.z = d->z;
+  a.n_rows = d->n_rows;
+  a.n_cols = d->n_cols;
+  a.q = d->q;
+  a.sqrtd = d->sqrtd;
+  a.offs = d->offs;
+  a.pos = d->pos;
+  a.perm = d->perm;
+  a.epoch = d->epoch;
+  a.epoch_stride = d->epoch_stride;
+  a.count = d->count;
+  a.stage = d->stage;
+  a.u0f = d->u0f;
+  a.qtab = d->qtab;
+  a.lvl = d->lvl;
+  a.lvl_a_off = d->lvl_a_off;
+  a.levels = d->levels;
+  a.phi_part = d->phi_part;
+  a.gn_part = d->gn_part;
+  a.d_out = d->d_out;
+  a.probe_num = d->probe_num;
+  a.probe_den = d->probe_den;
+  a.probe_max = d->probe_max;
+  return a;
+}
+
+__device__ __forceinline__ AccumArgs load_accum_args(const AccumArgs* p) {
+  const const_ptr<AccumArgs> d = (const_ptr<AccumArgs>)p;
+  AccumArgs a;
+  a.z = d->z;
+  a.n_rows = d->n_rows;
+  a.n_cols = d->n_cols;
+  a.m = d->m;
+  a.tiles_x = d->tiles_x;
+  a.n_tiles = d->n_tiles;
+  a.tile_ptr = d->tile_ptr;
+  a.tile_ent = d->tile_ent;
+  a.inv = d->inv;
+  a.epoch = d->epoch;
+  a.epoch_stride = d->epoch_stride;
+  a.batch_index = d->batch_index;
+  a.batch = d->batch;
+  a.stage = d->stage;
+  a.offs = d->offs;
+  a.w0f = d->w0f;
+  return a;
+}
 
 // Orders this wave's LDS accesses around the call (LDS executes one wave's
 // operations in issue order; the fences keep the compiler from moving them).
@@ -247,21 +304,23 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   const int zso = RB * a.n_cols * (int)sizeof(float2);
   constexpr int qso = RB * M * (int)sizeof(float2);
   const float4* qt = a.qtab + tid;   // [n1][tid]: each load reads one contiguous block
+  // M <= 64 keeps the exit wave psi = Q z_k, Q and u0 in registers for the
+  // gradient conj(Q)(psi - R_k) and the V-cycle output; M = 128 re-reads
+  // z_k and its table entry there instead.
   constexpr bool KEEP = (M <= 64);
   constexpr bool CST = (MODE == MODE_STEP) && (M <= 64);
-  float2 zk[KEEP ? RA : 1], qk[KEEP ? RA : 1];
-  float u0k[CST ? RA : 1];
+  float2 psi[KEEP ? RA : 1], qk[KEEP ? RA : 1];
+  float u0k[KEEP ? RA : 1];
 #pragma unroll
   for (int n1 = 0; n1 < RA; ++n1) {
     const float4 t = qt[n1 * TPB];
-    const float2 qq = make_float2(t.x, t.y);
     const float2 zz = bload2(zr, zvo, n1 * zso);
+    v[n1] = cmul(make_float2(t.x, t.y), zz);
+    if constexpr (KEEP) psi[n1] = v[n1];
     if constexpr (KEEP) {
-      zk[n1] = zz;
-      qk[n1] = qq;
+      qk[n1] = make_float2(t.x, t.y);
+      u0k[n1] = t.z;
     }
-    if constexpr (CST) u0k[n1] = t.z;
-    v[n1] = cmul(qq, zz);
   }
   // twiddles: stage A uses W_M^(g k1); the inverse stage B uses W_M^(n2 (g CB + c)).
   // Powers of two of the base come from the table, the other exponents are
@@ -445,20 +504,21 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     float pmx = 0.0f;
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
-      float2 qq, zz;
+      float2 qq, ps;
       if constexpr (KEEP) {
         qq = qk[n1];
-        zz = zk[n1];
+        ps = psi[n1];
       } else {
         const float4 t = qt[n1 * TPB];
         qq = make_float2(t.x, t.y);
-        zz = bload2(zr, zvo, n1 * zso);
+        ps = cmul(qq, bload2(zr, zvo, n1 * zso));
       }
       const float2 rk = cscale(v[n1], inv_m2);
       if constexpr (MODE == MODE_STEP) {
         if (a.probe_num) {
           // probe step partials: conj(z_k)(R_k - Q z_k) and |z_k|^2
-          const float2 pn = cmulc(zz, csub(rk, cmul(qq, zz)));
+          const float2 zz = bload2(zr, zvo, n1 * zso);
+          const float2 pn = cmulc(zz, csub(rk, ps));
           const float pd = zz.x * zz.x + zz.y * zz.y;
           const size_t e = (size_t)wg * M * M + (size_t)(RB * n1 + g) * M + col;
           a.probe_num[e] = pn;
@@ -466,7 +526,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
           pmx = fmaxf(pmx, pd);
         }
       }
-      v[n1] = cmulc(qq, csub(cmul(qq, zz), rk));
+      v[n1] = cmulc(qq, csub(ps, rk));
     }
     if constexpr (MODE == MODE_STEP) {
       if (a.probe_num) {
@@ -557,7 +617,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
           for (int i = 0; i < NC; ++i) {
             const int y = RB * (n0 + i) + g;
             double uu;
-            if constexpr (CST) uu = (double)u0k[n0 + i];
+            if constexpr (KEEP) uu = (double)u0k[n0 + i];
             else uu = (double)qt[(n0 + i) * TPB].z;
             bstore2(outr,
                     make_float2((float)(uu * e1[i].x - (double)v[n0 + i].x),
@@ -586,8 +646,8 @@ __global__ __launch_bounds__(M * RBv) void step_kernel(StepArgs a) {
 // Many reconstructions in one launch: blockIdx.y selects a context's arguments
 // for this round (descs), blockIdx.x a position of its minibatch.
 template <int M, int RBv>
-__global__ __launch_bounds__(M * RBv) void step_multi_kernel(const StepArgs* descs) {
-  const StepArgs& a = descs[blockIdx.y];
+__global__ __launch_bounds__(M * RBv) void step_multi_kernel(const StepArgs* __restrict__ descs) {
+  const StepArgs a = load_step_args(descs + blockIdx.y);
   if ((int)blockIdx.x >= a.count) return;
   step_body<M, RBv, MODE_STEP>(a, (int)blockIdx.x);
 }
@@ -781,8 +841,8 @@ __global__ __launch_bounds__(ACC_THREADS) void accumulate_kernel(AccumArgs a) {
 }
 
 template <int TH>
-__global__ __launch_bounds__(ACC_THREADS) void accumulate_multi_kernel(const AccumArgs* descs) {
-  const AccumArgs& a = descs[blockIdx.y];
+__global__ __launch_bounds__(ACC_THREADS) void accumulate_multi_kernel(const AccumArgs* __restrict__ descs) {
+  const AccumArgs a = load_accum_args(descs + blockIdx.y);
   if ((int)blockIdx.x >= a.n_tiles) return;
   accumulate_body<TH>(a, (int)blockIdx.x);
 }
