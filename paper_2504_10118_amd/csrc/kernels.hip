@@ -308,19 +308,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // gradient conj(Q)(psi - R_k) and the V-cycle output; M = 128 re-reads
   // z_k and its table entry there instead.
   constexpr bool KEEP = (M <= 64);
+  constexpr bool ROWS = (M <= 64) && (M * M) % TPB == 0 && TPB % M == 0;
   constexpr bool CST = (MODE == MODE_STEP) && (M <= 64);
+  // Loads that do not depend on z_k are issued first: the probe table, the
+  // twiddles, sqrt(d) and the V-cycle constants.
   float2 psi[KEEP ? RA : 1], qk[KEEP ? RA : 1];
   float u0k[KEEP ? RA : 1];
+  float4 qtv[ROWS ? RA : 1];
+  if constexpr (ROWS) {
 #pragma unroll
-  for (int n1 = 0; n1 < RA; ++n1) {
-    const float4 t = qt[n1 * TPB];
-    const float2 zz = bload2(zr, zvo, n1 * zso);
-    v[n1] = cmul(make_float2(t.x, t.y), zz);
-    if constexpr (KEEP) psi[n1] = v[n1];
-    if constexpr (KEEP) {
-      qk[n1] = make_float2(t.x, t.y);
-      u0k[n1] = t.z;
-    }
+    for (int n1 = 0; n1 < RA; ++n1) qtv[n1] = qt[n1 * TPB];
   }
   // twiddles: stage A uses W_M^(g k1); the inverse stage B uses W_M^(n2 (g CB + c)).
   // Powers of two of the base come from the table, the other exponents are
@@ -359,6 +356,45 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     for (int i = 0; i < CST_PER; ++i) {
       const int e = tid + i * TPB;
       cst[i] = (2 * e < nCst) ? src[e] : make_double2(0.0, 0.0);
+    }
+  }
+
+  // Gather.  ROWS (M <= 64): the patch is read as whole rows (each wave reads
+  // contiguous row segments) into the LDS tile, and after one barrier every
+  // thread takes its column values (rows y = RB*n1 + g of column col) from
+  // it; the tile is then reused by the FFT.  M = 128 loads its column values
+  // directly.
+  if constexpr (ROWS) {
+#pragma unroll
+    for (int j = 0; j < RA; ++j) {
+      const int e = tid + TPB * j;
+      const int y = e / M, x = e & (M - 1);
+      T[y * P + x] = bload2(zr, (y * a.n_cols + x) * (int)sizeof(float2), 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n1 = 0; n1 < RA; ++n1) {
+      const float4 t = qtv[n1];
+      const float2 zz = T[(RB * n1 + g) * P + col];
+      v[n1] = cmul(make_float2(t.x, t.y), zz);
+      if constexpr (KEEP) {
+        psi[n1] = v[n1];
+        qk[n1] = make_float2(t.x, t.y);
+        u0k[n1] = t.z;
+      }
+    }
+    wave_sync();   // the column pass below reuses this wave's own column slice of the tile
+  } else {
+#pragma unroll
+    for (int n1 = 0; n1 < RA; ++n1) {
+      const float4 t = qt[n1 * TPB];
+      const float2 zz = bload2(zr, zvo, n1 * zso);
+      v[n1] = cmul(make_float2(t.x, t.y), zz);
+      if constexpr (KEEP) {
+        psi[n1] = v[n1];
+        qk[n1] = make_float2(t.x, t.y);
+        u0k[n1] = t.z;
+      }
     }
   }
 
@@ -757,6 +793,14 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int ti
   double nr[RPT], ni[RPT], dd[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) nr[i] = ni[i] = dd[i] = 0.0;
+  // the tile's current object values, fetched first: their latency overlaps
+  // the screening and the staged loads
+  float2 zo[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int Y = Y0 + 4 * i;
+    zo[i] = (X < a.n_cols && Y < a.n_rows) ? a.z[(size_t)Y * a.n_cols + X] : make_float2(0.0f, 0.0f);
+  }
   const int beg = a.tile_ptr[tile], end = a.tile_ptr[tile + 1];
   const int lo_idx = a.batch_index * a.batch;
   const int* inv = a.inv + (a.epoch ? (size_t)(*a.epoch) * a.epoch_stride : 0);
@@ -826,11 +870,9 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int ti
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int Y = Y0 + 4 * i;
-      if (Y < a.n_rows && dd[i] > 0.0) {
-        float2* zp = a.z + (size_t)Y * a.n_cols + X;
-        const float2 zo = *zp;
-        *zp = make_float2((float)((double)zo.x + nr[i] / dd[i]), (float)((double)zo.y + ni[i] / dd[i]));
-      }
+      if (Y < a.n_rows && dd[i] > 0.0)
+        a.z[(size_t)Y * a.n_cols + X] =
+            make_float2((float)((double)zo[i].x + nr[i] / dd[i]), (float)((double)zo[i].y + ni[i] / dd[i]));
     }
   }
 }
