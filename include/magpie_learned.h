@@ -40,7 +40,7 @@ typedef struct magpie_cnn magpie_cnn;
 #define MAGPIE_COARSE_C128 1    /* interleaved complex128 */
 #define MAGPIE_COARSE_LOGPOLAR 2 /* float32 planes [2][side][side]: log-amplitude, phase (network output) */
 
-/* Create a network on `device` for inputs of `in_ch` (1 or 3) channels of
+/* Create a network on `device` for inputs of `in_ch` (1, 3 or 4) channels of
  * side x side pixels (side a multiple of 2), width 32, batches of up to
  * max_batch.  weight_dtype: MAGPIE_W_F32 or MAGPIE_W_BF16.  stream: a
  * hipStream_t or NULL (the network creates its own).  Parameters start at 0. */
@@ -83,8 +83,11 @@ int magpie_cnn_sync(magpie_cnn* net);
  * of mass of d_k over signed frequency indices (rows, then columns); each is
  * spread over the object with weights |Q(p - o_k)|^2, normalised per pixel
  * (0 where no position covers p), then averaged over
- * (n_rows / side) x (n_cols / side) blocks.  out: float [3][side][side].
- * side must divide n_rows and n_cols. */
+ * (n_rows / side) x (n_cols / side) blocks; channel 3 is the phase those
+ * centres of mass integrate to (a centre of mass of f bins is a phase slope of
+ * 2 pi f / m per object pixel), least-squares over the whole map (spectral,
+ * periodic, mean 0).  out: float [4][side][side].  side must divide n_rows and
+ * n_cols and be at most 64. */
 int magpie_input_map(magpie_ctx* ctx, int side, float* out, int on_device);
 
 /* Object <- (I_H^h)^j applied to a coarse object (eq. 2.6: each coarse value
@@ -100,7 +103,7 @@ int magpie_restrict_object(const void* z, int n_rows, int n_cols, int times, voi
  * then the objective of the learned start and of the flat start (all ones)
  * are evaluated and the lower one is kept as the object.  *used = 1 if the
  * learned start was kept.  phi_learned / phi_flat / used may be NULL.
- * The network must have in_ch 1 (channel 0 of the map) or 3, and side such
+ * The network reads the map's first in_ch channels (1, 3 or 4), and side such
  * that 2 * side divides the object and the ratio is a power of two. */
 int magpie_learned_start(magpie_ctx* ctx, magpie_cnn* net, double* phi_learned, double* phi_flat, int* used);
 

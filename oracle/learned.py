@@ -11,7 +11,8 @@ the paper's own pieces where they apply:
 * the network input is built from the measured intensities d_k of Section 2.1
   only: per position k the mean measured amplitude a_k and the centre of mass
   (first moment) of d_k over signed frequency indices, spread back over the
-  object with illumination weights |Q(p - o_k)|^2 and average-pooled;
+  object with illumination weights |Q(p - o_k)|^2 and average-pooled, plus the
+  phase that the centre-of-mass field (a phase gradient) integrates to;
 * the network is five 3x3 convolutions (zero padding 1): Cin -> W, ReLU,
   W -> W, ReLU, nearest 2x upsampling, W -> W, ReLU, W -> W, ReLU, W -> 2.
   The two output channels are log-amplitude and phase of the coarse object;
@@ -41,7 +42,7 @@ __all__ = [
     "layer_shapes", "n_params", "unpack", "conv3x3", "conv3x3_backward", "relu", "upsample2",
     "upsample2_backward", "net_forward", "net_backward", "complex_mse", "complex_mse_aligned", "adam_step",
     "bf16_round",
-    "position_stats", "input_map", "restrict_object", "prolong_object",
+    "position_stats", "integrate_gradient", "input_map", "restrict_object", "prolong_object",
 ]
 
 
@@ -238,10 +239,31 @@ def position_stats(sqrt_d, Q):
     return out
 
 
+def integrate_gradient(gy, gx):
+    """Least-squares integration of a periodic gradient field (Frankot and Chellappa, 1988):
+    phi = Re F^-1[ -i (w_y G_y + w_x G_x) / (w_y^2 + w_x^2) ], mean 0, with w the angular
+    frequencies 2 pi f / S of the S x S grid (signed indices f).  Exact for the spectral
+    gradient of a periodic field."""
+    gy = np.asarray(gy, dtype=np.float64)
+    gx = np.asarray(gx, dtype=np.float64)
+    S0, S1 = gy.shape
+    f0 = np.fft.fftfreq(S0) * 2 * np.pi
+    f1 = np.fft.fftfreq(S1) * 2 * np.pi
+    wy, wx = np.meshgrid(f0, f1, indexing="ij")
+    den = wy ** 2 + wx ** 2
+    num = -1j * (wy * np.fft.fft2(gy) + wx * np.fft.fft2(gx))
+    out = np.zeros_like(num)
+    nz = den > 0
+    out[nz] = num[nz] / den[nz]
+    return np.real(np.fft.ifft2(out))
+
+
 def input_map(sqrt_d, Q, offsets, n_rows: int, n_cols: int, side: int):
-    """3 x side x side network input: each channel of position_stats spread over the object with
+    """4 x side x side network input: each channel of position_stats spread over the object with
     weights |Q(p - o_k)|^2 (normalised per pixel; 0 where no position covers p), then averaged
-    over (n_rows / side) x (n_cols / side) blocks."""
+    over (n_rows / side) x (n_cols / side) blocks; channel 3 is the phase whose gradient the two
+    centre-of-mass channels measure, integrated over the whole map (a centre of mass of f bins
+    is a phase slope of 2 pi f / m per object pixel, i.e. 2 pi f (n / side) / m per map cell)."""
     st = position_stats(sqrt_d, Q)
     m = Q.shape[0]
     A = np.abs(Q) ** 2
@@ -256,7 +278,9 @@ def input_map(sqrt_d, Q, offsets, n_rows: int, n_cols: int, side: int):
     for ch in range(3):
         fine[ch][pos] = num[ch][pos] / den[pos]
     fr, fc = n_rows // side, n_cols // side
-    return fine.reshape(3, side, fr, side, fc).mean(axis=(2, 4))
+    pooled = fine.reshape(3, side, fr, side, fc).mean(axis=(2, 4))
+    ph = integrate_gradient(pooled[1] * (2 * np.pi * fr / m), pooled[2] * (2 * np.pi * fc / m))
+    return np.concatenate([pooled, ph[None]], axis=0)
 
 
 # --------------------------------------------------------------------------

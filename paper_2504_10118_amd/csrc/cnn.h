@@ -67,6 +67,11 @@ hipError_t launch_map_fine(const double4* stats, const double2* q, int m, const 
                            int tiles_x, int tile_w, int tile_h, int nr, int nc, double* fine, hipStream_t s);
 // out[ch][i][j] = mean of fine[ch] over the fr x fc block (i, j).
 hipError_t launch_pool(const double* fine, int nr, int nc, int fr, int fc, float* out, hipStream_t s);
+// out = the S x S phase whose gradient is (sy * gy, sx * gx) in the least-squares
+// (periodic, spectral) sense, mean 0; S <= 64.
+constexpr int PHASE_MAX_SIDE = 64;
+hipError_t launch_integrate_phase(const float* gy, const float* gx, int S, double sy, double sx, float* out,
+                                  hipStream_t s);
 
 // z[r][c] = coarse[r / f][c / f]; format 0 complex64, 1 complex128, 2 planes
 // (log-amplitude, phase) float [2][sr][sc].

@@ -443,6 +443,96 @@ __global__ void pool_kernel(const double* __restrict__ fine, int nr, int nc, int
   out[((size_t)ch * sr + i) * so + j] = (float)(a / ((double)fr * fc));
 }
 
+// Phase channel: least-squares integration of the gradient field the two
+// centre-of-mass channels measure (Frankot and Chellappa), in FP64 on one
+// workgroup.  The two real fields are transformed together as
+// H = DFT(gy + i gx) and separated with the conjugate-symmetric parts; then
+// phi^ = -i (wy Gy + wx Gx) / (wy^2 + wx^2) (0 at zero frequency) and
+// phi = Re IDFT(phi^).  Direct DFT sums over rows and columns (S <= 64).
+constexpr int PHI_MAX_S = 64;
+constexpr int PHI_THREADS = 1024;
+
+__global__ __launch_bounds__(PHI_THREADS) void integrate_phase_kernel(const float* __restrict__ gy_in,
+                                                                      const float* __restrict__ gx_in, int S,
+                                                                      double sy, double sx,
+                                                                      float* __restrict__ out) {
+  __shared__ double2 A[PHI_MAX_S * PHI_MAX_S];
+  __shared__ double2 Bf[PHI_MAX_S * PHI_MAX_S];
+  __shared__ double2 W[PHI_MAX_S];
+  const int tid = threadIdx.x, SS = S * S;
+  for (int j = tid; j < S; j += PHI_THREADS) {
+    double sn, cs;
+    sincospi(-2.0 * j / S, &sn, &cs);
+    W[j] = make_double2(cs, sn);   // exp(-2 pi i j / S)
+  }
+  for (int e = tid; e < SS; e += PHI_THREADS) A[e] = make_double2(sy * gy_in[e], sx * gx_in[e]);
+  __syncthreads();
+  // forward: rows, then columns
+  for (int e = tid; e < SS; e += PHI_THREADS) {
+    const int y = e / S, k = e - y * S;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int x = 0; x < S; ++x) {
+      const double2 a = A[y * S + x], w = W[(k * x) % S];
+      acc.x += a.x * w.x - a.y * w.y;
+      acc.y += a.x * w.y + a.y * w.x;
+    }
+    Bf[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < SS; e += PHI_THREADS) {
+    const int k0 = e / S, k1 = e - k0 * S;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int y = 0; y < S; ++y) {
+      const double2 b = Bf[y * S + k1], w = W[(k0 * y) % S];
+      acc.x += b.x * w.x - b.y * w.y;
+      acc.y += b.x * w.y + b.y * w.x;
+    }
+    A[e] = acc;
+  }
+  __syncthreads();
+  // separate the two spectra, divide by |w|^2
+  for (int e = tid; e < SS; e += PHI_THREADS) {
+    const int k0 = e / S, k1 = e - k0 * S;
+    const int m0 = (S - k0) % S, m1 = (S - k1) % S;
+    const double2 h = A[e], hm = A[m0 * S + m1];
+    // Gy = (h + conj(hm)) / 2, Gx = (h - conj(hm)) / (2 i)
+    const double2 gy = make_double2(0.5 * (h.x + hm.x), 0.5 * (h.y - hm.y));
+    const double2 gx = make_double2(0.5 * (h.y + hm.y), -0.5 * (h.x - hm.x));
+    const int f0 = (k0 < (S + 1) / 2) ? k0 : k0 - S, f1 = (k1 < (S + 1) / 2) ? k1 : k1 - S;
+    const double wy = 6.283185307179586 * f0 / S, wx = 6.283185307179586 * f1 / S;
+    const double den = wy * wy + wx * wx;
+    double2 ph = make_double2(0.0, 0.0);
+    if (den > 0.0) {
+      // -i (wy gy + wx gx) / den
+      const double2 t = make_double2(wy * gy.x + wx * gx.x, wy * gy.y + wx * gx.y);
+      ph = make_double2(t.y / den, -t.x / den);
+    }
+    Bf[e] = ph;
+  }
+  __syncthreads();
+  // inverse: columns, then rows; real part / S^2
+  for (int e = tid; e < SS; e += PHI_THREADS) {
+    const int y = e / S, k1 = e - y * S;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < S; ++k0) {
+      const double2 b = Bf[k0 * S + k1], w = W[(k0 * y) % S];
+      acc.x += b.x * w.x + b.y * w.y;    // times conj(w)
+      acc.y += b.y * w.x - b.x * w.y;
+    }
+    A[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < SS; e += PHI_THREADS) {
+    const int y = e / S, x = e - y * S;
+    double acc = 0.0;
+    for (int k1 = 0; k1 < S; ++k1) {
+      const double2 a = A[y * S + k1], w = W[(k1 * x) % S];
+      acc += a.x * w.x + a.y * w.y;      // Re(a conj(w))
+    }
+    out[e] = (float)(acc / ((double)S * S));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Whole-object prolongation and restriction
 // ---------------------------------------------------------------------------
@@ -624,6 +714,13 @@ hipError_t launch_map_fine(const double4* stats, const double2* q, int m, const 
 hipError_t launch_pool(const double* fine, int nr, int nc, int fr, int fc, float* out, hipStream_t s) {
   const int so = nc / fc, sr = nr / fr;
   hipLaunchKernelGGL(pool_kernel, dim3((so + 63) / 64, sr, 3), dim3(64), 0, s, fine, nr, nc, fr, fc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_integrate_phase(const float* gy, const float* gx, int S, double sy, double sx, float* out,
+                                  hipStream_t s) {
+  if (S < 1 || S > PHI_MAX_S) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(integrate_phase_kernel, dim3(1), dim3(PHI_THREADS), 0, s, gy, gx, S, sy, sx, out);
   return hipGetLastError();
 }
 

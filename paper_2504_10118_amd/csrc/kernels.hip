@@ -305,17 +305,21 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr int qso = RB * M * (int)sizeof(float2);
   const float4* qt = a.qtab + tid;   // [n1][tid]: each load reads one contiguous block
   // M <= 64 keeps the exit wave psi = Q z_k, Q and u0 in registers for the
-  // gradient conj(Q)(psi - R_k) and the V-cycle output; M = 128 re-reads
-  // z_k and its table entry there instead.
+  // gradient conj(Q)(psi - R_k) and the V-cycle output; M = 128 (1024 threads
+  // at the 128-register cap) re-reads z_k and its table entry there instead.
   constexpr bool KEEP = (M <= 64);
-  constexpr bool ROWS = (M <= 64) && (M * M) % TPB == 0 && TPB % M == 0;
+  constexpr bool ROWS = true;             // row-wise gathers through the LDS tile
+  constexpr bool PREQ = (RA <= 8);        // probe table entries fetched before the gather
   constexpr bool CST = (MODE == MODE_STEP) && (M <= 64);
+  // M = 128: the V-cycle constants do not fit beside the FFT tile; they are
+  // staged into the tile once the FFT and the gradient are done with it.
+  constexpr bool CSTL = (MODE == MODE_STEP) && (M > 64);
   // Loads that do not depend on z_k are issued first: the probe table, the
   // twiddles, sqrt(d) and the V-cycle constants.
   float2 psi[KEEP ? RA : 1], qk[KEEP ? RA : 1];
   float u0k[KEEP ? RA : 1];
-  float4 qtv[ROWS ? RA : 1];
-  if constexpr (ROWS) {
+  float4 qtv[PREQ ? RA : 1];
+  if constexpr (PREQ) {
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) qtv[n1] = qt[n1 * TPB];
   }
@@ -359,11 +363,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     }
   }
 
-  // Gather.  ROWS (M <= 64): the patch is read as whole rows (each wave reads
-  // contiguous row segments) into the LDS tile, and after one barrier every
-  // thread takes its column values (rows y = RB*n1 + g of column col) from
-  // it; the tile is then reused by the FFT.  M = 128 loads its column values
-  // directly.
+  // Gather: the patch is read as whole rows (each wave reads contiguous row
+  // segments) into the LDS tile, and after one barrier every thread takes its
+  // column values (rows y = RB*n1 + g of column col) from it; the tile is then
+  // reused by the FFT.
   if constexpr (ROWS) {
 #pragma unroll
     for (int j = 0; j < RA; ++j) {
@@ -374,7 +377,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     __syncthreads();
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
-      const float4 t = qtv[n1];
+      float4 t;
+      if constexpr (PREQ) t = qtv[n1];
+      else t = qt[n1 * TPB];
       const float2 zz = T[(RB * n1 + g) * P + col];
       v[n1] = cmul(make_float2(t.x, t.y), zz);
       if constexpr (KEEP) {
@@ -597,6 +602,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         // Chunks of NC register rows: while every restriction pairs rows across
         // lanes (LW <= log2 RB) the rows n1 are independent.
         // in-thread row pairs (levels above log2 RB) stay inside aligned chunks of NC
+        if constexpr (CSTL) {
+          // every wave is done with the tile: stage A_l, V_l there
+          __syncthreads();
+          const int nC = cst_count(M, L);
+          const double2* src = reinterpret_cast<const double2*>(a.lvl + a.lvl_a_off);
+          double2* dst = reinterpret_cast<double2*>(T);
+          for (int e = tid; 2 * e < nC; e += TPB) dst[e] = src[e];
+          __syncthreads();
+        }
         constexpr int NCB = (M >= 128) ? 2 : 4;
         constexpr int NCP = (LW > LRB) ? (1 << (LW - LRB)) : 1;
         constexpr int NC0 = NCP > NCB ? NCP : NCB;
@@ -630,8 +644,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
                   s[i] = make_double2(cur[i].x + o.x, cur[i].y + o.y);
                 }
               }
-              const double* A = (CST ? (const double*)Cst : Abase) + (size_t)(l - 1) * M1c * M1c;
-              const double* V = CST ? (const double*)Cst + cst_v_off(M, L, l) : a.lvl + lv_off;
+              const double* Cb = CST ? (const double*)Cst : reinterpret_cast<const double*>(T);
+              const double* A = ((CST || CSTL) ? Cb : Abase) + (size_t)(l - 1) * M1c * M1c;
+              const double* V = (CST || CSTL) ? Cb + cst_v_off(M, L, l) : a.lvl + lv_off;
               const bool more = (l + 1 < L);
 #pragma unroll
               for (int i = 0; i < NC; ++i) {
@@ -693,7 +708,9 @@ static size_t lds_bytes_m() {
   constexpr int TPB = M * RB, P = M + Plan<M, RB>::PAD;
   constexpr int LW = ilog2c((TPB < 64 ? TPB : 64) / RB);
   size_t b = (size_t)M * P * sizeof(float2);
-  if (M <= 64) b += (size_t)((cst_count_max(M, LW) + 1) & ~1) * sizeof(double);
+  const size_t c = (size_t)((cst_count_max(M, LW) + 1) & ~1) * sizeof(double);
+  if (M <= 64) b += c;          // constants parked beside the tile
+  else if (c > b) b = c;        // constants staged into the tile after the FFT
   return b;
 }
 

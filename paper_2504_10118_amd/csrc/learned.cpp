@@ -102,11 +102,12 @@ int input_map_dev(magpie_ctx* c, int side) {
   if (rc) return rc;
   if (side < 1 || c->nr % side || c->nc % side)
     return fail(MAGPIE_ERR_INVALID_ARG, "side must divide the object's rows and columns");
+  if (side > cnn::PHASE_MAX_SIDE) return fail(MAGPIE_ERR_UNSUPPORTED, "side must be at most 64");
   const size_t mm = (size_t)c->m * c->m;
   rc = grow(&c->lrn_sd, &c->lrn_sd_cap, (size_t)c->n_pos * mm);
   if (!rc) rc = grow(&c->lrn_stats, &c->lrn_stats_cap, (size_t)c->n_pos);
   if (!rc) rc = grow(&c->lrn_fine, &c->lrn_fine_cap, 3 * (size_t)c->nr * c->nc);
-  if (!rc) rc = grow(&c->lrn_map, &c->lrn_map_cap, 3 * (size_t)side * side);
+  if (!rc) rc = grow(&c->lrn_map, &c->lrn_map_cap, 4 * (size_t)side * side);
   if (!rc && !c->lrn_q) rc = dev_alloc(&c->lrn_q, 1);
   if (rc) return rc;
   MG_HIP(mg::launch_unpermute_sqrt(c->m, c->rb, c->n_pos, c->sqrtd, c->lrn_sd, c->stream));
@@ -115,6 +116,12 @@ int input_map_dev(magpie_ctx* c, int side) {
   MG_HIP(cnn::launch_map_fine(c->lrn_stats, c->q64, c->m, c->tile_ptr, c->tile_ent, c->tiles_x, mg::ACC_TILE_W, c->th,
                               c->nr, c->nc, c->lrn_fine, c->stream));
   MG_HIP(cnn::launch_pool(c->lrn_fine, c->nr, c->nc, c->nr / side, c->nc / side, c->lrn_map, c->stream));
+  // channel 3: the phase the centre-of-mass channels (slopes of 2 pi f / m per
+  // object pixel, f in DFT bins) integrate to, per map cell
+  const size_t ss = (size_t)side * side;
+  const double two_pi = 6.283185307179586;
+  MG_HIP(cnn::launch_integrate_phase(c->lrn_map + ss, c->lrn_map + 2 * ss, side, two_pi * (c->nr / side) / c->m,
+                                     two_pi * (c->nc / side) / c->m, c->lrn_map + 3 * ss, c->stream));
   return MAGPIE_OK;
 }
 
@@ -141,7 +148,7 @@ int magpie_cnn_create(magpie_cnn** out, int in_ch, int width, int side, int max_
                       void* stream) {
   if (!out) return fail(MAGPIE_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (in_ch != 1 && in_ch != 3) return fail(MAGPIE_ERR_UNSUPPORTED, "in_ch must be 1 or 3");
+  if (in_ch != 1 && in_ch != 3 && in_ch != 4) return fail(MAGPIE_ERR_UNSUPPORTED, "in_ch must be 1, 3 or 4");
   if (width != WIDTH) return fail(MAGPIE_ERR_UNSUPPORTED, "width must be 32");
   if (side < 2 || (side & 1)) return fail(MAGPIE_ERR_INVALID_ARG, "side must be even and >= 2");
   if (max_batch < 1) return fail(MAGPIE_ERR_INVALID_ARG, "max_batch >= 1 required");
@@ -424,7 +431,7 @@ int magpie_input_map(magpie_ctx* c, int side, float* out, int on_device) {
   if (rc) return rc;
   rc = input_map_dev(c, side);
   if (rc) return rc;
-  return copy_out(out, c->lrn_map, 3 * (size_t)side * side * sizeof(float), on_device, c->stream);
+  return copy_out(out, c->lrn_map, 4 * (size_t)side * side * sizeof(float), on_device, c->stream);
 }
 
 int magpie_set_object_from_coarse(magpie_ctx* c, const void* coarse, int side, int format, int on_device) {
@@ -477,7 +484,7 @@ int magpie_learned_start(magpie_ctx* c, magpie_cnn* net, double* phi_learned, do
   rc = input_map_dev(c, S);
   if (rc) return rc;
   MG_HIP(hipStreamSynchronize(c->stream));
-  // the network reads channel 0 (one input channel) or all three
+  // the network reads the map's first in_ch channels (1, 3 or all 4)
   rc = magpie_cnn_forward(net, c->lrn_map, nullptr, 1, 1);
   if (rc) return rc;
   MG_HIP(hipStreamSynchronize(net->stream));

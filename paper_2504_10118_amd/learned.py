@@ -7,8 +7,9 @@ Adam steps (:class:`CNN`).  This module only schedules those calls, shuffles
 minibatches and writes the trained parameters.
 
 Training geometry: the 512 x 512, 64 x 64-probe, 40 x 40 raster workload
-(1600 positions, step 10 px) at 1e4 peak photons.  Input: the 3 x 64 x 64 map
-(mean measured amplitude and the two diffraction centres of mass).  Target:
+(1600 positions, step 10 px), half noiseless, half at 1e4 peak photons.  Input:
+the 64 x 64 map's mean measured amplitude and two diffraction centres of mass
+(``--in-ch 4`` adds its fourth channel, the phase the two integrate to).  Target:
 the object restricted twice (128 x 128), which the prolongation maps back
 onto the three-level solver's fine grid.  Loss: masked complex MSE after
 removing the global phase, mask = coverage of the restricted illumination.
@@ -30,6 +31,8 @@ from .magpie import CNN, Magpie, restrict_object
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(PKG, "weights", "coarse_cnn_512_m64.npz")
 SIDE = 64             # input map side
+MAP_CH = 4            # input map: mean amplitude, two centres of mass, integrated phase
+IN_CH = 3             # channels the shipped network reads (the map's first three)
 LEVELS_DOWN = 2       # target = object restricted twice
 SEED_TRAIN = 250410118 + 5
 
@@ -80,7 +83,7 @@ def init_params(seed: int, in_ch: int = 3, width: int = 32, in_mean=None, in_std
 
 
 def build_set(count: int, seed: int, peak, chunk: int = 128, log=print, noiseless_fraction: float = 0.0):
-    """(X [count, 3, 64, 64] float32, T [count, 128, 128] complex64) on the GPU, for objects of the
+    """(X [count, 4, 64, 64] float32, T [count, 128, 128] complex64) on the GPU, for objects of the
     training model in the fixed geometry; peak = None gives noiseless data, otherwise each sample is
     noiseless with probability noiseless_fraction and Poisson at `peak` photons otherwise."""
     import torch
@@ -91,7 +94,7 @@ def build_set(count: int, seed: int, peak, chunk: int = 128, log=print, noiseles
     ctx = Magpie(n, n, m, 1, 0.5, stream=_current_stream())
     ctx.set_probe(Q)
     ctx.set_positions(offs)
-    X = torch.empty((count, 3, SIDE, SIDE), dtype=torch.float32, device="cuda")
+    X = torch.empty((count, MAP_CH, SIDE, SIDE), dtype=torch.float32, device="cuda")
     T = torch.empty((count, n >> LEVELS_DOWN, n >> LEVELS_DOWN), dtype=torch.complex64, device="cuda")
     dt = torch.empty((len(offs), m, m), dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(seed)
@@ -288,8 +291,8 @@ def load_network(path: str = DEFAULT_WEIGHTS, weight_dtype: int = 0, max_batch: 
     return net
 
 
-def net_eval(params, weight_dtype: int = 0) -> CNN:
-    net = CNN(in_ch=3, side=SIDE, max_batch=1, weight_dtype=weight_dtype, stream=_current_stream())
+def net_eval(params, weight_dtype: int = 0, in_ch: int = IN_CH) -> CNN:
+    net = CNN(in_ch=in_ch, side=SIDE, max_batch=1, weight_dtype=weight_dtype, stream=_current_stream())
     net.set_params(params)
     return net
 
@@ -305,6 +308,8 @@ def main():
     ap.add_argument("--noiseless-fraction", type=float, default=0.5,
                     help="share of training samples drawn without noise (the rest at --peak photons)")
     ap.add_argument("--weight-dtype", type=int, default=0, help="0: FP32 weights, 1: BF16 weights")
+    ap.add_argument("--in-ch", type=int, default=IN_CH, choices=[1, 3, 4],
+                    help="input-map channels the network reads (the first in_ch of the 4)")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--race-objects", type=int, default=3, help="objects in the closing time-to-1e-3 race")
     args = ap.parse_args()
@@ -327,12 +332,16 @@ def run_training(args, peak):
     Xv, Tv = build_set(args.val, SEED_TRAIN + 1, peak, log=lambda s: print(s, flush=True),
                        noiseless_fraction=args.noiseless_fraction)
     t_data = time.time() - t0
+    in_ch = args.in_ch
+    if in_ch < MAP_CH:
+        X = X[:, :in_ch].contiguous()
+        Xv = Xv[:, :in_ch].contiguous()
     xs = X[:, :, 8:-8, 8:-8]
-    mean = [float(xs[:, c].mean()) for c in range(3)]
-    std = [float(xs[:, c].std()) for c in range(3)]
+    mean = [float(xs[:, c].mean()) for c in range(in_ch)]
+    std = [float(xs[:, c].std()) for c in range(in_ch)]
     print("input channel mean/std (interior):", list(zip(mean, std)), flush=True)
-    net = CNN(in_ch=3, side=SIDE, max_batch=args.batch, weight_dtype=args.weight_dtype, stream=_current_stream())
-    net.set_params(init_params(SEED_TRAIN + 2, in_mean=mean, in_std=std))
+    net = CNN(in_ch=in_ch, side=SIDE, max_batch=args.batch, weight_dtype=args.weight_dtype, stream=_current_stream())
+    net.set_params(init_params(SEED_TRAIN + 2, in_ch=in_ch, in_mean=mean, in_std=std))
     mask_t = torch.as_tensor(mask, device="cuda")
     base = evaluate(net, Xv, Tv, mask_t, args.batch)
     print(f"validation loss at init: {base:.5f}", flush=True)
@@ -341,7 +350,7 @@ def run_training(args, peak):
                  log=lambda s: print(s, flush=True))
     t_train = time.time() - t1
     params = net.get_params()
-    meta = {"in_ch": 3, "side": SIDE, "width": 32, "levels_down": LEVELS_DOWN, "train": args.train,
+    meta = {"in_ch": in_ch, "side": SIDE, "width": 32, "levels_down": LEVELS_DOWN, "train": args.train,
             "val": args.val, "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "peak": args.peak,
             "noiseless_fraction": args.noiseless_fraction,
             "weight_dtype": args.weight_dtype, "seed": SEED_TRAIN, "val_loss_init": base,
@@ -349,7 +358,7 @@ def run_training(args, peak):
             "geometry": f"object {cfg.n}, probe {cfg.m}, {cfg.P}x{cfg.P} raster step {cfg.step}"}
     print("race to 1e-3 relative error, noiseless data:", flush=True)
     objs = held_out_objects(args.race_objects)
-    ev = net_eval(params, args.weight_dtype)
+    ev = net_eval(params, args.weight_dtype, in_ch)
     rr = race(ev, objs, log=lambda s: print(s, flush=True))
     if peak is not None:
         print(f"start errors at {peak:g} photons:", flush=True)

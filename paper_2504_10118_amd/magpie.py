@@ -314,11 +314,11 @@ class Magpie:
 
     # -- learned start
     def input_map(self, side: int, out=None):
-        """Network input map [3, side, side] (float32) from this context's intensities."""
+        """Network input map [4, side, side] (float32) from this context's intensities."""
         if out is not None and _is_torch(out) and out.is_cuda:
             _check(self.lib.magpie_input_map(self._h, side, ctypes.c_void_p(out.data_ptr()), 1))
             return out
-        res = np.empty((3, side, side), dtype=np.float32)
+        res = np.empty((4, side, side), dtype=np.float32)
         _check(self.lib.magpie_input_map(self._h, side, res.ctypes.data_as(ctypes.c_void_p), 0))
         return res
 
@@ -371,7 +371,7 @@ def restrict_object(z, times: int, out=None, stream=None):
 class CNN:
     """Coarse-object network of the learned start (5 conv layers, width 32, FP32 or BF16 weights)."""
 
-    def __init__(self, in_ch: int = 3, side: int = 64, max_batch: int = 32, weight_dtype: int = W_F32,
+    def __init__(self, in_ch: int = 4, side: int = 64, max_batch: int = 32, weight_dtype: int = W_F32,
                  device: int = 0, stream=None):
         self.lib = load_library()
         self.in_ch, self.side, self.max_batch = in_ch, side, max_batch

@@ -1,0 +1,170 @@
+"""Levels sweep: MAGPIE with L grids, L = 1 (the rPIE update) .. log2(m) + 1, run
+with the library's kernels on a synthetic workload (the study of the number of
+coarse levels of Sec. 5.1, with minibatches and the synthetic probe).
+
+For every noise level, regularisation weight alpha and number of grids L the
+sweep runs `epochs` epochs from the flat start and records, after each epoch,
+the objective Phi (eq. 2.1) and the stopping statistic (the mean gradient norm
+of Sec. 5), and at log-spaced epochs the relative object error (minimum over a
+global phase, masked to the illuminated area) and the paper's magnitude error
+||(|z| - |z*|)|| / ||z*||.  It notes the first epoch at which the statistic
+falls below `tol` and the GPU wall time of the epochs (error checks and
+objective passes off the clock).
+
+Run ``python -m paper_2504_10118_amd.sweep --help``.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from .magpie import Magpie
+
+
+def checkpoints(epochs: int) -> list[int]:
+    """1, 2, 3, 5, 10, 20, 30, 50, ... up to and including `epochs`."""
+    out = []
+    dec = 1
+    while dec <= epochs:
+        for f in (1, 2, 3, 5):
+            if f * dec <= epochs:
+                out.append(f * dec)
+        dec *= 10
+    if not out or out[-1] != epochs:
+        out.append(epochs)
+    return sorted(set(out))
+
+
+def object_errors(z, z_true, mask) -> tuple[float, float]:
+    """(relative error after removing the global phase, relative magnitude error), both on the mask."""
+    a = np.asarray(z, dtype=np.complex128)[mask]
+    b = np.asarray(z_true, dtype=np.complex128)[mask]
+    ip = np.vdot(a, b)
+    ph = ip / abs(ip) if ip != 0 else 1.0
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(ph * a - b) / nb), float(np.linalg.norm(np.abs(a) - np.abs(b)) / nb)
+
+
+def illumination_mask(Q, offs, n: int) -> np.ndarray:
+    m = Q.shape[0]
+    A = np.abs(np.asarray(Q, dtype=np.complex128)) ** 2
+    ill = np.zeros((n, n))
+    for r, c in offs:
+        ill[r:r + m, c:c + m] += A
+    return ill >= 0.1 * ill.max()
+
+
+def run_one(ctx: Magpie, z_true, mask, epochs: int, batch: int, seed: int, tol: float) -> dict:
+    """Flat start, `epochs` epochs; per-epoch Phi and statistic, errors at the checkpoints."""
+    n_rows, n_cols = ctx.n_rows, ctx.n_cols
+    ctx.set_object(np.ones((n_rows, n_cols), dtype=np.complex64))
+    ctx.epoch_index = 0
+    phi0, stat0 = ctx.objective()
+    cps = set(checkpoints(epochs))
+    phi, stat, errs = [phi0], [stat0], []
+    e_rel, e_mag = object_errors(ctx.get_object(), z_true, mask)
+    errs.append((0, e_rel, e_mag))
+    hit = 0 if stat0 <= tol else None
+    gpu_s = 0.0
+    for e in range(1, epochs + 1):
+        t0 = time.perf_counter()
+        ctx.run_epochs(1, batch, seed=seed)
+        ctx.sync()
+        gpu_s += time.perf_counter() - t0
+        p, s = ctx.objective()
+        phi.append(p)
+        stat.append(s)
+        if hit is None and s <= tol:
+            hit = e
+        if e in cps or e == hit:
+            e_rel, e_mag = object_errors(ctx.get_object(), z_true, mask)
+            errs.append((e, e_rel, e_mag))
+    return {"phi": phi, "stat": stat, "errors": errs, "tol_epoch": hit, "seconds": gpu_s,
+            "finite": bool(np.all(np.isfinite(phi)))}
+
+
+def run(config: int = 2, levels=None, alphas=(0.2, 0.5, 1.0), peaks=(None, 1e4), epochs: int = 200,
+        batch: int | None = None, tol: float = 1e-4, seed: int = 7, log=print) -> dict:
+    """The whole sweep on workload `config` of the synthetic suite (object, probe and scan of
+    synth.CONFIGS); intensities from the library's forward model, Poisson noise at each peak
+    photon count (None = noiseless)."""
+    from synth import CONFIGS, make_problem_inputs, poisson_counts
+    cfg = CONFIGS[config]
+    z_true, Q, offs, _, _ = make_problem_inputs(cfg)
+    Q32 = Q.astype(np.complex64)
+    z32 = z_true.astype(np.complex64)
+    n, m = cfg.n, cfg.m
+    batch = batch or cfg.batch
+    max_l = int(np.log2(m)) + 1
+    levels = list(levels) if levels else list(range(1, max_l + 1))
+    mask = illumination_mask(Q32, offs, n)
+    out = {"config": config, "n": n, "m": m, "positions": int(len(offs)), "batch": batch, "epochs": epochs,
+           "tol": tol, "checkpoints": checkpoints(epochs), "runs": []}
+    with Magpie(n, n, m, 1, 0.5) as fm:
+        fm.set_probe(Q32)
+        fm.set_positions(offs)
+        dtilde = fm.forward_model(z32)
+    for peak in peaks:
+        if peak is None:
+            d = dtilde.astype(np.float32)
+        else:
+            d = poisson_counts(dtilde, peak, np.random.default_rng(seed + 1000)).astype(np.float32)
+        for alpha in alphas:
+            for L in levels:
+                with Magpie(n, n, m, L, alpha) as ctx:
+                    ctx.set_probe(Q32)
+                    ctx.set_positions(offs)
+                    ctx.load_intensities(d, is_sqrt=False)
+                    r = run_one(ctx, z32, mask, epochs, batch, seed, tol)
+                r.update({"peak": peak, "alpha": alpha, "levels": L})
+                out["runs"].append(r)
+                last = r["errors"][-1]
+                log(f"peak {peak if peak else 'none':>7} alpha {alpha:<5g} L {L}: Phi {r['phi'][0]:.3e} -> "
+                    f"{r['phi'][-1]:.3e}, err {last[1]:.3e} (magnitude {last[2]:.3e}) after {last[0]} epochs, "
+                    f"stat <= {tol:g} at epoch {r['tol_epoch']}, {r['seconds'] * 1e3:.1f} ms")
+    return out
+
+
+def table(res: dict, at=None) -> str:
+    """Markdown table: relative error at a few checkpoints per (peak, alpha, L)."""
+    cps = at or [c for c in res["checkpoints"] if c in (1, 10, 50, 100, 200, 500, 1000)] or res["checkpoints"][-3:]
+    head = "| peak | alpha | L | " + " | ".join(f"err @{c}" for c in cps) + " | Phi end | stat<=tol epoch |"
+    rows = [head, "|" + "---|" * (len(cps) + 5)]
+    for r in res["runs"]:
+        e = {ep: er for ep, er, _ in r["errors"]}
+        cells = " | ".join(f"{e[c]:.3e}" if c in e else "" for c in cps)
+        rows.append(f"| {r['peak'] or 'none'} | {r['alpha']:g} | {r['levels']} | {cells} | "
+                    f"{r['phi'][-1]:.3e} | {r['tol_epoch']} |")
+    return "\n".join(rows)
+
+
+def main():
+    ap = argparse.ArgumentParser(description="Sweep the number of multigrid levels on a synthetic workload.")
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--levels", type=str, default="", help="comma list (default 1 .. log2(m) + 1)")
+    ap.add_argument("--alphas", type=str, default="0.2,0.5,1.0")
+    ap.add_argument("--peaks", type=str, default="none,1e4", help="comma list; 'none' = noiseless")
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--out", type=str, default="")
+    a = ap.parse_args()
+    levels = [int(x) for x in a.levels.split(",") if x]
+    alphas = [float(x) for x in a.alphas.split(",") if x]
+    peaks = [None if x.strip().lower() == "none" else float(x) for x in a.peaks.split(",") if x]
+    res = run(a.config, levels, alphas, peaks, a.epochs, a.batch or None, a.tol, a.seed)
+    print(table(res), flush=True)
+    if a.out:
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        with open(a.out, "w") as f:
+            json.dump(res, f)
+
+
+if __name__ == "__main__":
+    main()

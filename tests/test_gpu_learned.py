@@ -167,20 +167,21 @@ def test_bf16_weight_variant_matches_oracle_with_rounded_weights():
     net.close()
 
 
-def test_one_input_channel_network():
-    rng = np.random.default_rng(106)
-    p = _params(rng, cin=1)
-    x, t, mask = _inputs(rng, 2, cin=1)
-    net = _net(cin=1)
-    assert net.n_params == ol.n_params(1, W)
+@pytest.mark.parametrize("cin", [1, 4])
+def test_other_input_channel_counts(cin):
+    rng = np.random.default_rng(106 + cin)
+    p = _params(rng, cin=cin)
+    x, t, mask = _inputs(rng, 2, cin=cin)
+    net = _net(cin=cin)
+    assert net.n_params == ol.n_params(cin, W)
     net.set_params(p)
     y = net.forward(x)
-    yo, cache = ol.net_forward(p.astype(np.float64), x.astype(np.float64), 1, W)
+    yo, cache = ol.net_forward(p.astype(np.float64), x.astype(np.float64), cin, W)
     assert _rel(y, yo) <= 1e-5
     net.loss(t, mask)
     net.backward(nbatch=2)
     _, dyo = ol.complex_mse(yo, t.astype(np.complex128), mask.astype(np.float64))
-    go, _ = ol.net_backward(p.astype(np.float64), cache, dyo, 1, W)
+    go, _ = ol.net_backward(p.astype(np.float64), cache, dyo, cin, W)
     assert _rel(net.get_grads(), go) <= 2e-5
     net.close()
 
@@ -232,7 +233,8 @@ def test_input_map_matches_oracle(n, m, step, side):
     g = c.gpu(2, 0.5)
     mp = g.input_map(side)
     mo = ol.input_map(c.sd32.astype(np.float64), c.Q, c.offs, n, n, side)
-    for ch in range(3):
+    assert mp.shape == mo.shape == (4, side, side)
+    for ch in range(4):
         scale = max(np.max(np.abs(mo[ch])), 1e-12)
         assert np.max(np.abs(mp[ch] - mo[ch])) <= 1e-6 * scale, ch
     # the map does not depend on the FFT plan that stores sqrt(d) in kernel order
