@@ -5,7 +5,7 @@
 //     v[k] <- sum_j v[j] exp(-DIR * 2 pi i j k / R),   DIR = +1 forward, -1 inverse
 // (unnormalised, the sign convention of the 2-D DFT in Section 2.1 of
 // arXiv 2504.10118; the inverse uses the conjugate kernel, Appendix A).
-// R is a power of two up to 16; the recursion is radix-2 decimation in time
+// R is a power of two up to 32; the recursion is radix-2 decimation in time
 // with compile-time twiddles, fully unrolled so that the reordering costs
 // nothing but register renaming.
 #pragma once
@@ -13,26 +13,29 @@
 
 namespace mg {
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+// The helpers are host-callable too, so that a host build can check them.
+#define MG_HD __host__ __device__ __forceinline__
+
+MG_HD float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+MG_HD float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+MG_HD float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 // conj(a) * b
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+MG_HD float2 cmulc(float2 a, float2 b) {
   return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+MG_HD float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
 // a * exp(-DIR * i pi / 2): forward multiplies by -i, inverse by +i.
 template <int DIR>
-__device__ __forceinline__ float2 mul_quarter(float2 a) {
+MG_HD float2 mul_quarter(float2 a) {
   return DIR > 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
 }
 
 // a * exp(-DIR * 2 pi i j / 16) for a compile-time j in [0, 8).
 template <int J, int DIR>
-__device__ __forceinline__ float2 mul_w16(float2 a) {
+MG_HD float2 mul_w16(float2 a) {
   constexpr float C1 = 0.92387953251128675613f;   // cos(pi/8)
   constexpr float S1 = 0.38268343236508977173f;   // sin(pi/8)
   constexpr float H = 0.70710678118654752440f;    // cos(pi/4)
@@ -55,8 +58,53 @@ __device__ __forceinline__ float2 mul_w16(float2 a) {
   }
 }
 
+// a * exp(-DIR * 2 pi i j / 32) for a compile-time j in [0, 16): even j reduce
+// to the 16-point twiddles; odd j use cos and sin of (2j + 1) pi / 32 folded
+// onto the first octant by the symmetries of the circle.
+template <int J, int DIR>
+MG_HD float2 mul_w32(float2 a) {
+  if constexpr (J % 2 == 0) {
+    return mul_w16<J / 2, DIR>(a);
+  } else {
+    constexpr float C1 = 0.98078528040323044913f;   // cos(pi/16)
+    constexpr float S1 = 0.19509032201612826785f;   // sin(pi/16)
+    constexpr float C3 = 0.83146961230254523708f;   // cos(3 pi/16)
+    constexpr float S3 = 0.55557023301960222474f;   // sin(3 pi/16)
+    constexpr float s = DIR > 0 ? -1.0f : 1.0f;
+    constexpr float c = (J == 1) ? C1 : (J == 3) ? C3 : (J == 5) ? S3 : (J == 7) ? S1
+                      : (J == 9) ? -S1 : (J == 11) ? -S3 : (J == 13) ? -C3 : -C1;
+    constexpr float sn = (J == 1) ? S1 : (J == 3) ? S3 : (J == 5) ? C3 : (J == 7) ? C1
+                       : (J == 9) ? C1 : (J == 11) ? C3 : (J == 13) ? S3 : S1;
+    return make_float2(a.x * c - a.y * (s * sn), a.x * (s * sn) + a.y * c);
+  }
+}
+
+// a * W_32^j for j known after unrolling (the switch folds away)
+template <int DIR>
+MG_HD float2 mul_w32_at(int j, float2 a) {
+  switch (j) {
+    case 0: return a;
+    case 1: return mul_w32<1, DIR>(a);
+    case 2: return mul_w32<2, DIR>(a);
+    case 3: return mul_w32<3, DIR>(a);
+    case 4: return mul_w32<4, DIR>(a);
+    case 5: return mul_w32<5, DIR>(a);
+    case 6: return mul_w32<6, DIR>(a);
+    case 7: return mul_w32<7, DIR>(a);
+    case 8: return mul_w32<8, DIR>(a);
+    case 9: return mul_w32<9, DIR>(a);
+    case 10: return mul_w32<10, DIR>(a);
+    case 11: return mul_w32<11, DIR>(a);
+    case 12: return mul_w32<12, DIR>(a);
+    case 13: return mul_w32<13, DIR>(a);
+    case 14: return mul_w32<14, DIR>(a);
+    default: return mul_w32<15, DIR>(a);
+  }
+}
+
 template <int R, int DIR>
-__device__ __forceinline__ void dft(float2* v) {
+MG_HD void dft(float2* v) {
+  static_assert(R >= 1 && R <= 32 && (R & (R - 1)) == 0, "dft: R must be a power of two up to 32");
   if constexpr (R == 1) {
     return;
   } else if constexpr (R == 2) {
@@ -80,21 +128,10 @@ __device__ __forceinline__ void dft(float2* v) {
     }
     dft<H, DIR>(e);
     dft<H, DIR>(o);
-    // twiddle W_R^k = W_16^(k * 16 / R)
+    // twiddle W_R^k = W_32^(k * 32 / R)
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-      float2 t;
-      constexpr int step = 16 / R;
-      switch (k * step) {
-        case 0: t = mul_w16<0, DIR>(o[k]); break;
-        case 1: t = mul_w16<1, DIR>(o[k]); break;
-        case 2: t = mul_w16<2, DIR>(o[k]); break;
-        case 3: t = mul_w16<3, DIR>(o[k]); break;
-        case 4: t = mul_w16<4, DIR>(o[k]); break;
-        case 5: t = mul_w16<5, DIR>(o[k]); break;
-        case 6: t = mul_w16<6, DIR>(o[k]); break;
-        default: t = mul_w16<7, DIR>(o[k]); break;
-      }
+      const float2 t = mul_w32_at<DIR>(k * (32 / R), o[k]);
       v[k] = cadd(e[k], t);
       v[k + H] = csub(e[k], t);
     }

@@ -91,6 +91,21 @@ __host__ __device__ constexpr int cst_v_off(int M, int L, int l) {
 }
 constexpr int cst_count_max(int M, int LW) { return cst_count(M, LW + 1); }
 
+// Deepest in-wave V-cycle (number of coarse levels, at most LW) whose constants
+// the LDS holds: M <= 64 parks them beside the M x P tile, larger M stages
+// them into the tile's space once the FFT is done with it.
+constexpr int LDS_MAX_BYTES = 160 * 1024;
+constexpr int inwave_levels(int M, int P, int LW) {
+  int lw = LW;
+  while (lw > 0) {
+    const long c = (long)cst_count(M, lw + 1) * 8, t = (long)M * P * 8;
+    const long need = (M <= 64) ? t + c : (c > t ? c : t);
+    if (need <= LDS_MAX_BYTES) break;
+    --lw;
+  }
+  return lw;
+}
+
 // Argument blocks read from memory through the constant address space: the
 // loads are scalar and the compiler may re-read a field instead of keeping it
 // live, so a descriptor costs no vector registers.
@@ -268,6 +283,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr int LANES = TPB < 64 ? TPB : 64;
   constexpr int CPW = LANES / RB;
   constexpr int LRB = ilog2c(RB), LW = ilog2c(CPW);
+  constexpr int LWI = inwave_levels(M, P, LW);   // coarse levels handled inside the wave
   constexpr int NW = (TPB + 63) / 64;
   extern __shared__ double2 smem_d2[];
   float2* T = reinterpret_cast<float2*>(smem_d2);
@@ -349,10 +365,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // parked in LDS at the first barrier, so their latency hides behind the
   // forward FFT.
   constexpr int M1c = M / 2;
-  constexpr int CST_MAX = CST ? cst_count_max(M, LW) : 2;
+  constexpr int CST_MAX = CST ? cst_count_max(M, LWI) : 2;
   constexpr int CST_PER = ((CST_MAX + 1) / 2 + TPB - 1) / TPB;   // double2 per thread
   double* const Cst = reinterpret_cast<double*>(T + M * P);
-  const int nCst = (CST && a.levels >= 2 && a.levels - 1 <= LW) ? cst_count(M, a.levels) : 0;
+  const int nCst = (CST && a.levels >= 2 && a.levels - 1 <= LWI) ? cst_count(M, a.levels) : 0;
   double2 cst[CST_PER];
   if constexpr (CST) {
     const double2* src = reinterpret_cast<const double2*>(a.lvl + a.lvl_a_off);
@@ -593,7 +609,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         for (int n1 = 0; n1 < RA; ++n1) bstore2(outr, make_float2(-v[n1].x, -v[n1].y), ovo, n1 * qso);
         return;
       }
-      if (L - 1 <= LW) {
+      if (L - 1 <= LWI) {
         // ---- MAGPS V-cycle inside the wave (gradient form, FP64).  Level-l
         // values are held replicated by every thread of their 2^l x 2^l bin,
         // so restriction is two cross-lane (or in-thread) pair sums and
@@ -626,7 +642,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
           }
           int lv_off = 0;
 #pragma unroll
-          for (int l = 1; l <= LW; ++l) {
+          for (int l = 1; l <= LWI; ++l) {
             if (l < L) {
               const int Ml = M >> l;
               double2 s[NC];
@@ -704,14 +720,19 @@ __global__ __launch_bounds__(M * RBv) void step_multi_kernel(const StepArgs* __r
 }
 
 template <int M, int RB>
-static size_t lds_bytes_m() {
+constexpr size_t lds_bytes_c() {
   constexpr int TPB = M * RB, P = M + Plan<M, RB>::PAD;
-  constexpr int LW = ilog2c((TPB < 64 ? TPB : 64) / RB);
+  constexpr int LW = inwave_levels(M, P, ilog2c((TPB < 64 ? TPB : 64) / RB));
   size_t b = (size_t)M * P * sizeof(float2);
   const size_t c = (size_t)((cst_count_max(M, LW) + 1) & ~1) * sizeof(double);
   if (M <= 64) b += c;          // constants parked beside the tile
   else if (c > b) b = c;        // constants staged into the tile after the FFT
   return b;
+}
+template <int M, int RB>
+static size_t lds_bytes_m() {
+  static_assert(lds_bytes_c<M, RB>() <= (size_t)LDS_MAX_BYTES, "step kernel LDS exceeds the CU's LDS");
+  return lds_bytes_c<M, RB>();
 }
 
 template <int M, int RB, int MODE>
@@ -738,7 +759,7 @@ static hipError_t launch_step_p(int mode, const StepArgs& a, hipStream_t s, hipE
 }
 
 // The compiled plans: (M, RB).  The first plan listed for an M is its default.
-#define MG_FOR_EACH_PLAN(X) X(8, 2) X(16, 4) X(16, 2) X(32, 4) X(32, 2) X(64, 8) X(64, 4) X(128, 8)
+#define MG_FOR_EACH_PLAN(X) X(8, 2) X(16, 4) X(16, 2) X(32, 4) X(32, 2) X(64, 8) X(64, 4) X(128, 8) X(128, 4)
 
 bool plan_valid(int m, int rb) {
 #define MG_PV(MM, RR) if (m == MM && rb == RR) return true;

@@ -291,7 +291,8 @@ def test_probe_update_parity(m, levels, batch):
     assert rq <= 1e-5
 
 
-@pytest.mark.parametrize("m,rb,levels", [(16, 2, 3), (32, 2, 3), (64, 4, 3), (64, 4, 5), (32, 2, 6)])
+@pytest.mark.parametrize("m,rb,levels", [(16, 2, 3), (32, 2, 3), (64, 4, 3), (64, 4, 5), (32, 2, 6), (128, 4, 4),
+                                          (128, 4, 7)])
 def test_fft_plan_variants(m, rb, levels):
     """Every compiled FFT plan matches the oracle (one epoch from the same z)."""
     from paper_2504_10118_amd import list_plans
