@@ -24,7 +24,8 @@ struct StepArgs {
   int count;              // number of workgroups / positions
   float2* stage;          // MODE_STEP: c_k = w0 * dz_k, natural order [count][m][m]
   const float* u0f;       // fine-grid u [m][m]
-  const float4* qtab;     // (Re Q, Im Q, u0, 0) in the plan's thread order: [n1][tid], pixel (RB*n1 + g, col)
+  const float4* qtab;     // probe table in the plan's thread order [n1][tid], pixel (RB*n1 + g, col): m <= 64
+                          // (Re Q, Im Q, u0, 0) per entry; m = 128 m*m float2 Q, then m*m float u0
   const double* lvl;      // coarse-level constants (V, rho, r per level), then A_l
   int lvl_a_off;          // offset in lvl of the in-wave V-cycle block: A_1..A_{L-1}, then V_1..V_{L-2}
   int levels;             // number of grids L

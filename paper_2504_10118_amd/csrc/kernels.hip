@@ -25,8 +25,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "cmath.h"
 #include "kernels.h"
+
+#ifndef MG_RGATHER
+#define MG_RGATHER 1
+#endif
+#ifndef MG_RGATHER_GROUP
+#define MG_RGATHER_GROUP 16
+#endif
 
 namespace mg {
 
@@ -61,6 +70,13 @@ __device__ __forceinline__ float2 twiddle(int j) {
 }
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+// M <= 64 keeps the exit wave, Q and u0 in registers from the gather to the
+// V-cycle and reads the probe table once, as (Re Q, Im Q, u0, 0) float4s.
+// Larger M re-reads Q and u0 where they are used, so its table holds Q as
+// float2s followed by u0 as floats (both in thread order): a re-read fetches
+// only the bytes it needs.
+constexpr bool keeps_exit_wave(int M) { return M <= 64; }
 
 // w[j] = W_M^(b j) for 0 < j < R: the power-of-two exponents are read from
 // the table, every other one is the product of its highest power of two and
@@ -320,10 +336,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   const int zso = RB * a.n_cols * (int)sizeof(float2);
   constexpr int qso = RB * M * (int)sizeof(float2);
   const float4* qt = a.qtab + tid;   // [n1][tid]: each load reads one contiguous block
+  const float2* qt2 = reinterpret_cast<const float2*>(a.qtab) + tid;            // split table: Q
+  const float* ut = reinterpret_cast<const float*>(reinterpret_cast<const float2*>(a.qtab) + M * M) + tid;  // u0
   // M <= 64 keeps the exit wave psi = Q z_k, Q and u0 in registers for the
   // gradient conj(Q)(psi - R_k) and the V-cycle output; M = 128 (1024 threads
   // at the 128-register cap) re-reads z_k and its table entry there instead.
-  constexpr bool KEEP = (M <= 64);
+  constexpr bool KEEP = keeps_exit_wave(M);
   constexpr bool ROWS = true;             // row-wise gathers through the LDS tile
   constexpr bool PREQ = (RA <= 8);        // probe table entries fetched before the gather
   constexpr bool CST = (MODE == MODE_STEP) && (M <= 64);
@@ -383,38 +401,65 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // segments) into the LDS tile, and after one barrier every thread takes its
   // column values (rows y = RB*n1 + g of column col) from it; the tile is then
   // reused by the FFT.
-  if constexpr (ROWS) {
+  // Row gather: load j of thread tid reads row tid / M + j * TPB / M, column
+  // tid % M: one per-lane offset, and a uniform per-load row step.
+  constexpr int GR = TPB / M;   // rows per load of the workgroup
+  // NG loads in flight at a time.  The re-gather passes a copy of tid the
+  // compiler cannot see through, so that it recomputes its LDS addresses
+  // instead of keeping the first gather's alive through the whole FFT.
+  auto row_gather = [&](auto ng, int t) {
+    constexpr int NG = decltype(ng)::value;
+    const int gvo = ((t / M) * a.n_cols + (t & (M - 1))) * (int)sizeof(float2);
+    const int gso = GR * a.n_cols * (int)sizeof(float2);
+    float2* const dst = T + (t / M) * P + (t & (M - 1));
 #pragma unroll
-    for (int j = 0; j < RA; ++j) {
-      const int e = tid + TPB * j;
-      const int y = e / M, x = e & (M - 1);
-      T[y * P + x] = bload2(zr, (y * a.n_cols + x) * (int)sizeof(float2), 0);
+    for (int j0 = 0; j0 < RA; j0 += NG) {
+#pragma unroll
+      for (int j = j0; j < j0 + NG; ++j) dst[j * GR * P] = bload2(zr, gvo, j * gso);
+      if constexpr (NG < RA) __builtin_amdgcn_sched_barrier(0);
     }
+  };
+  if constexpr (ROWS) {
+    row_gather(std::integral_constant<int, RA>{}, tid);
     __syncthreads();
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
-      float4 t;
-      if constexpr (PREQ) t = qtv[n1];
-      else t = qt[n1 * TPB];
+      float2 qv;
+      float uv = 0.0f;
+      if constexpr (KEEP) {
+        const float4 t = PREQ ? qtv[n1] : qt[n1 * TPB];
+        qv = make_float2(t.x, t.y);
+        uv = t.z;
+      } else {
+        qv = qt2[n1 * TPB];
+      }
       const float2 zz = T[(RB * n1 + g) * P + col];
-      v[n1] = cmul(make_float2(t.x, t.y), zz);
+      v[n1] = cmul(qv, zz);
       if constexpr (KEEP) {
         psi[n1] = v[n1];
-        qk[n1] = make_float2(t.x, t.y);
-        u0k[n1] = t.z;
+        qk[n1] = qv;
+        u0k[n1] = uv;
       }
     }
     wave_sync();   // the column pass below reuses this wave's own column slice of the tile
   } else {
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
-      const float4 t = qt[n1 * TPB];
+      float2 qv;
+      float uv = 0.0f;
+      if constexpr (KEEP) {
+        const float4 t = qt[n1 * TPB];
+        qv = make_float2(t.x, t.y);
+        uv = t.z;
+      } else {
+        qv = qt2[n1 * TPB];
+      }
       const float2 zz = bload2(zr, zvo, n1 * zso);
-      v[n1] = cmul(make_float2(t.x, t.y), zz);
+      v[n1] = cmul(qv, zz);
       if constexpr (KEEP) {
         psi[n1] = v[n1];
-        qk[n1] = make_float2(t.x, t.y);
-        u0k[n1] = t.z;
+        qk[n1] = qv;
+        u0k[n1] = uv;
       }
     }
   }
@@ -556,6 +601,24 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     for (int k1 = 0; k1 < RA; ++k1) v[k1] = *colslice(xi(k1, g));
     dft<RA, -1>(v);
 
+    // Plans that do not keep the exit wave read z_k again for the gradient:
+    // with RGATHER as whole rows through the tile (free once every wave is
+    // past its last exchange), otherwise straight from the object.
+    constexpr bool RGATHER = !KEEP && (MG_RGATHER != 0);
+    int t_opaque = tid;
+    if constexpr (RGATHER) {
+      __syncthreads();
+      asm volatile("" : "+v"(t_opaque));
+      row_gather(std::integral_constant<int, MG_RGATHER_GROUP>{}, t_opaque);
+      __syncthreads();
+    }
+    // column reads of the re-gathered tile, addressed from the opaque copy of tid
+    const float2* const Tz = T + (t_opaque & (RB - 1)) * P + t_opaque / RB;
+    auto z_again = [&](int n1) -> float2 {
+      if constexpr (RGATHER) return Tz[RB * n1 * P];
+      else return bload2(zr, zvo, n1 * zso);
+    };
+
     // ---- R_k = v / M^2; gradient g0 = conj(Q) (Q z_k - R_k) (eq. 2.2)
     constexpr float inv_m2 = 1.0f / (float)(M * M);
     float pmx = 0.0f;
@@ -566,15 +629,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         qq = qk[n1];
         ps = psi[n1];
       } else {
-        const float4 t = qt[n1 * TPB];
-        qq = make_float2(t.x, t.y);
-        ps = cmul(qq, bload2(zr, zvo, n1 * zso));
+        qq = qt2[n1 * TPB];
+        ps = cmul(qq, z_again(n1));
       }
       const float2 rk = cscale(v[n1], inv_m2);
       if constexpr (MODE == MODE_STEP) {
         if (a.probe_num) {
           // probe step partials: conj(z_k)(R_k - Q z_k) and |z_k|^2
-          const float2 zz = bload2(zr, zvo, n1 * zso);
+          const float2 zz = KEEP ? bload2(zr, zvo, n1 * zso) : z_again(n1);
           const float2 pn = cmulc(zz, csub(rk, ps));
           const float pd = zz.x * zz.x + zz.y * zz.y;
           const size_t e = (size_t)wg * M * M + (size_t)(RB * n1 + g) * M + col;
@@ -685,7 +747,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
             const int y = RB * (n0 + i) + g;
             double uu;
             if constexpr (KEEP) uu = (double)u0k[n0 + i];
-            else uu = (double)qt[(n0 + i) * TPB].z;
+            else uu = (double)ut[(n0 + i) * TPB];
             bstore2(outr,
                     make_float2((float)(uu * e1[i].x - (double)v[n0 + i].x),
                                 (float)(uu * e1[i].y - (double)v[n0 + i].y)),
@@ -736,26 +798,28 @@ static size_t lds_bytes_m() {
 }
 
 template <int M, int RB, int MODE>
-static void launch_step_mode(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+static hipError_t launch_step_mode(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   constexpr int TPB = M * RB;
   const size_t lds = lds_bytes_m<M, RB>();
-  hipFuncSetAttribute((const void*)step_kernel<M, RB, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const hipError_t e =
+      hipFuncSetAttribute((const void*)step_kernel<M, RB, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   if (ev0)
     hipExtLaunchKernelGGL((step_kernel<M, RB, MODE>), dim3(a.count), dim3(TPB), lds, s, ev0, ev1, 0, a);
   else
     hipLaunchKernelGGL((step_kernel<M, RB, MODE>), dim3(a.count), dim3(TPB), lds, s, a);
+  return hipGetLastError();
 }
 
 template <int M, int RB>
 static hipError_t launch_step_p(int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.count <= 0) return hipSuccess;
   switch (mode) {
-    case MODE_STEP: launch_step_mode<M, RB, MODE_STEP>(a, s, ev0, ev1); break;
-    case MODE_OBJECTIVE: launch_step_mode<M, RB, MODE_OBJECTIVE>(a, s, ev0, ev1); break;
-    case MODE_FORWARD: launch_step_mode<M, RB, MODE_FORWARD>(a, s, ev0, ev1); break;
+    case MODE_STEP: return launch_step_mode<M, RB, MODE_STEP>(a, s, ev0, ev1);
+    case MODE_OBJECTIVE: return launch_step_mode<M, RB, MODE_OBJECTIVE>(a, s, ev0, ev1);
+    case MODE_FORWARD: return launch_step_mode<M, RB, MODE_FORWARD>(a, s, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 // The compiled plans: (M, RB).  The first plan listed for an M is its default.
@@ -943,8 +1007,9 @@ hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, in
 #define MG_LM(MM, RR)                                                                                   \
   if (m == MM && rb == RR) {                                                                            \
     const size_t lds = lds_bytes_m<MM, RR>();                                                           \
-    hipFuncSetAttribute((const void*)step_multi_kernel<MM, RR>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                        (int)lds);                                                                      \
+    const hipError_t fe = hipFuncSetAttribute((const void*)step_multi_kernel<MM, RR>,                   \
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    if (fe != hipSuccess) return fe;                                                                    \
     if (ev0)                                                                                            \
       hipExtLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(max_count, n_ctx), dim3(MM * RR), lds, s, \
                             ev0, ev1, 0, descs);                                                        \
@@ -1121,7 +1186,13 @@ __global__ void qtab_kernel(const float2* qf, const float* u0f, float4* qtab) {
   const int n1 = e / TPB, tid = e - n1 * TPB, g = tid & (RB - 1), col = tid / RB;
   const int i = (RB * n1 + g) * M + col;
   const float2 q = qf[i];
-  qtab[e] = make_float4(q.x, q.y, u0f[i], 0.0f);
+  if constexpr (keeps_exit_wave(M)) {
+    qtab[e] = make_float4(q.x, q.y, u0f[i], 0.0f);
+  } else {
+    float2* q2 = reinterpret_cast<float2*>(qtab);
+    q2[e] = q;
+    reinterpret_cast<float*>(q2 + M * M)[e] = u0f[i];
+  }
 }
 
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given, const double2* q64,
