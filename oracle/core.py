@@ -12,7 +12,10 @@ Readings of points the paper leaves open (each also listed in the design notes):
   the inverse is F^* / m^2 as Appendix A derives.
 * theta(0) := 0 (Definition 2.1 footnote), so the revised exit wave takes the
   measured modulus with zero phase where F(Q z_k) vanishes exactly.  The
-  phase-recycling rule of eq. (3.2) is not used.
+  phase-recycling rule of eq. (3.2) is an option of the driver (``phases``):
+  where F(Q z_k) vanishes, the phase of position k's previous visit is used,
+  and theta = 0 before its first visit; "iteration j" of eq. (3.2) is read as
+  the j-th visit of position k.
 * Objective is reported in exit-wave form, eq. (2.1); the amplitude form
   printed before it is m^2 times larger (Appendix B.1).
 * Restriction is 2x2 average pooling on bins aligned to the patch origin
@@ -60,6 +63,7 @@ __all__ = [
     "illumination", "error_paper", "error_relative", "splitmix64",
     "library_permutation", "batches", "full_batch_surrogate_minimiser",
     "probe_update_step", "blind_minibatch_step", "run_epochs_blind",
+    "phase_factor_recycled", "revised_exit_wave_recycled", "initial_phases",
 ]
 
 M64 = (1 << 64) - 1
@@ -115,6 +119,22 @@ def revised_exit_wave(zk: np.ndarray, Q: np.ndarray, sqrt_dk: np.ndarray) -> np.
     """R_k(z_k) = F^{-1}(sqrt(d_k) * exp(i theta(F(Q * z_k))))."""
     Psi = fft2(Q * zk)
     return ifft2(sqrt_dk * phase_factor(Psi))
+
+
+def phase_factor_recycled(Psi: np.ndarray, previous: np.ndarray) -> np.ndarray:
+    """exp(i theta) with the specification of eq. (3.2): Psi / |Psi| where Psi is
+    nonzero, and where it vanishes the factor of the position's previous visit
+    (``previous``; all ones before the first visit, i.e. theta = 0)."""
+    out = np.array(previous, dtype=np.complex128, copy=True)
+    nz = Psi != 0
+    out[nz] = Psi[nz] / np.abs(Psi[nz])
+    return out
+
+
+def revised_exit_wave_recycled(zk, Q, sqrt_dk, previous):
+    """(R_k(z_k), phase factor used) under eq. (3.2)."""
+    ph = phase_factor_recycled(fft2(Q * zk), previous)
+    return ifft2(sqrt_dk * ph), ph
 
 
 # --------------------------------------------------------------------------
@@ -326,9 +346,10 @@ def batches(order, B: int):
     return [order[t:t + B] for t in range(0, len(order), B)]
 
 
-def minibatch_step(z, Q, offsets, sqrt_d, u, levels: int, batch, use_gradient_form=False):
+def minibatch_step(z, Q, offsets, sqrt_d, u, levels: int, batch, use_gradient_form=False, phases=None):
     """One minibatch step: every k in ``batch`` runs Alg 3 on the same z, updates are
-    averaged with precision weights w0 = u + |Q|^2 and applied where the weight sum > 0."""
+    averaged with precision weights w0 = u + |Q|^2 and applied where the weight sum > 0.
+    ``phases`` ([N][m][m] complex, updated in place): eq. (3.2) phase recycling."""
     m = Q.shape[0]
     w0 = u + np.abs(Q) ** 2
     num = np.zeros(z.shape, dtype=np.complex128)
@@ -337,7 +358,10 @@ def minibatch_step(z, Q, offsets, sqrt_d, u, levels: int, batch, use_gradient_fo
     for k in batch:
         o = offsets[k]
         zk = extract(z, o, m)
-        Rk = revised_exit_wave(zk, Q, sqrt_d[k])
+        if phases is None:
+            Rk = revised_exit_wave(zk, Q, sqrt_d[k])
+        else:
+            Rk, phases[k] = revised_exit_wave_recycled(zk, Q, sqrt_d[k], phases[k])
         if use_gradient_form:
             ck = magps_gradient_form(zk, Q, Rk, consts)
         else:
@@ -350,13 +374,19 @@ def minibatch_step(z, Q, offsets, sqrt_d, u, levels: int, batch, use_gradient_fo
     return znew
 
 
+def initial_phases(n_pos: int, m: int) -> np.ndarray:
+    """Phase factors before any visit: theta = 0 (eq. 3.2, j = 0)."""
+    return np.ones((n_pos, m, m), dtype=np.complex128)
+
+
 def run_epochs(z0, Q, offsets, sqrt_d, u, levels: int, orders, B: int,
-               use_gradient_form=False, callback=None):
-    """Epochs of minibatch MAGPIE over the given permutations (one per epoch)."""
+               use_gradient_form=False, callback=None, phases=None):
+    """Epochs of minibatch MAGPIE over the given permutations (one per epoch); with
+    ``phases`` (see ``initial_phases``, updated in place) eq. (3.2) phase recycling."""
     z = np.array(z0, dtype=np.complex128, copy=True)
     for e, order in enumerate(orders):
         for batch in batches(order, B):
-            z = minibatch_step(z, Q, offsets, sqrt_d, u, levels, batch, use_gradient_form)
+            z = minibatch_step(z, Q, offsets, sqrt_d, u, levels, batch, use_gradient_form, phases)
         if callback is not None:
             callback(e, z)
     return z

@@ -1,9 +1,10 @@
-"""Levels sweep: MAGPIE with L grids, L = 1 (the rPIE update) .. log2(m) + 1, run
-with the library's kernels on a synthetic workload (the study of the number of
-coarse levels of Sec. 5.1, with minibatches and the synthetic probe).
+"""Parameter sweeps with the library's kernels on a synthetic workload: the number
+of grids L = 1 (the rPIE update) .. log2(m) + 1 (the study of Sec. 5.1), the
+noise level (Sec. 5.2: d = eta * Poisson(d~ / eta)) and the overlap ratio of
+adjacent scans (Sec. 5.3), with minibatches and the synthetic probe.
 
-For every noise level, regularisation weight alpha and number of grids L the
-sweep runs `epochs` epochs from the flat start and records, after each epoch,
+For every overlap ratio, noise level, regularisation weight alpha and number of
+grids L the sweep runs `epochs` epochs from the flat start and records, after each epoch,
 the objective Phi (eq. 2.1) and the stopping statistic (the mean gradient norm
 of Sec. 5), and at log-spaced epochs the relative object error (minimum over a
 global phase, masked to the illuminated area) and the paper's magnitude error
@@ -17,6 +18,7 @@ Run ``python -m paper_2504_10118_amd.sweep --help``.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import time
@@ -88,57 +90,82 @@ def run_one(ctx: Magpie, z_true, mask, epochs: int, batch: int, seed: int, tol: 
             "finite": bool(np.all(np.isfinite(phi)))}
 
 
+def overlap_geometry(cfg, ratio: float):
+    """Scan of `cfg` with the step that gives adjacent positions the overlap `ratio` of the
+    probe's footprint (the disc of diameter 2R = 20 m / 32 of the synthetic probe), over the
+    same scanned span; None keeps the workload's own step."""
+    if ratio is None:
+        return cfg
+    step = max(1, int(round((1.0 - ratio) * 20.0 * cfg.m / 32.0)))
+    span = (cfg.P - 1) * cfg.step
+    return dataclasses.replace(cfg, step=step, P=span // step + 1)
+
+
+def noise_label(noise) -> str:
+    kind, val = noise
+    return "none" if kind == "none" else f"{kind} {val:g}"
+
+
 def run(config: int = 2, levels=None, alphas=(0.2, 0.5, 1.0), peaks=(None, 1e4), epochs: int = 200,
-        batch: int | None = None, tol: float = 1e-4, seed: int = 7, log=print) -> dict:
+        batch: int | None = None, tol: float = 1e-4, seed: int = 7, log=print, etas=(), overlaps=(None,)) -> dict:
     """The whole sweep on workload `config` of the synthetic suite (object, probe and scan of
-    synth.CONFIGS); intensities from the library's forward model, Poisson noise at each peak
-    photon count (None = noiseless)."""
+    synth.CONFIGS); intensities from the library's forward model with Poisson noise, given as
+    peak photon counts (None = noiseless) and as the paper's eta (d = eta Poisson(d~ / eta))."""
     from synth import CONFIGS, make_problem_inputs, poisson_counts
-    cfg = CONFIGS[config]
-    z_true, Q, offs, _, _ = make_problem_inputs(cfg)
-    Q32 = Q.astype(np.complex64)
-    z32 = z_true.astype(np.complex64)
-    n, m = cfg.n, cfg.m
-    batch = batch or cfg.batch
-    max_l = int(np.log2(m)) + 1
+    base = CONFIGS[config]
+    noises = [("none", 0.0) if p is None else ("peak", float(p)) for p in peaks] + [("eta", float(e)) for e in etas]
+    max_l = int(np.log2(base.m)) + 1
     levels = list(levels) if levels else list(range(1, max_l + 1))
-    mask = illumination_mask(Q32, offs, n)
-    out = {"config": config, "n": n, "m": m, "positions": int(len(offs)), "batch": batch, "epochs": epochs,
-           "tol": tol, "checkpoints": checkpoints(epochs), "runs": []}
-    with Magpie(n, n, m, 1, 0.5) as fm:
-        fm.set_probe(Q32)
-        fm.set_positions(offs)
-        dtilde = fm.forward_model(z32)
-    for peak in peaks:
-        if peak is None:
-            d = dtilde.astype(np.float32)
-        else:
-            d = poisson_counts(dtilde, peak, np.random.default_rng(seed + 1000)).astype(np.float32)
-        for alpha in alphas:
-            for L in levels:
-                with Magpie(n, n, m, L, alpha) as ctx:
-                    ctx.set_probe(Q32)
-                    ctx.set_positions(offs)
-                    ctx.load_intensities(d, is_sqrt=False)
-                    r = run_one(ctx, z32, mask, epochs, batch, seed, tol)
-                r.update({"peak": peak, "alpha": alpha, "levels": L})
-                out["runs"].append(r)
-                last = r["errors"][-1]
-                log(f"peak {peak if peak else 'none':>7} alpha {alpha:<5g} L {L}: Phi {r['phi'][0]:.3e} -> "
-                    f"{r['phi'][-1]:.3e}, err {last[1]:.3e} (magnitude {last[2]:.3e}) after {last[0]} epochs, "
-                    f"stat <= {tol:g} at epoch {r['tol_epoch']}, {r['seconds'] * 1e3:.1f} ms")
+    out = {"config": config, "n": base.n, "m": base.m, "epochs": epochs, "tol": tol,
+           "checkpoints": checkpoints(epochs), "runs": []}
+    for ov in overlaps:
+        cfg = overlap_geometry(base, ov)
+        z_true, Q, offs, _, _ = make_problem_inputs(cfg)
+        Q32 = Q.astype(np.complex64)
+        z32 = z_true.astype(np.complex64)
+        n, m = cfg.n, cfg.m
+        B = min(batch or cfg.batch, len(offs))
+        mask = illumination_mask(Q32, offs, n)
+        with Magpie(n, n, m, 1, 0.5) as fm:
+            fm.set_probe(Q32)
+            fm.set_positions(offs)
+            dtilde = fm.forward_model(z32)
+        for noise in noises:
+            kind, val = noise
+            if kind == "none":
+                d = dtilde.astype(np.float32)
+            else:
+                peak = val if kind == "peak" else float(dtilde.max()) / val
+                d = poisson_counts(dtilde, peak, np.random.default_rng(seed + 1000)).astype(np.float32)
+            for alpha in alphas:
+                for L in levels:
+                    with Magpie(n, n, m, L, alpha) as ctx:
+                        ctx.set_probe(Q32)
+                        ctx.set_positions(offs)
+                        ctx.load_intensities(d, is_sqrt=False)
+                        r = run_one(ctx, z32, mask, epochs, B, seed, tol)
+                    r.update({"noise": noise_label(noise), "peak": val if kind == "peak" else None,
+                              "eta": val if kind == "eta" else None, "alpha": alpha, "levels": L,
+                              "overlap": ov, "step": cfg.step, "positions": int(len(offs)), "batch": B})
+                    out["runs"].append(r)
+                    last = r["errors"][-1]
+                    log(f"overlap {ov if ov is not None else 'cfg'} (step {cfg.step}, {len(offs)} pos) "
+                        f"noise {noise_label(noise):>10} alpha {alpha:<5g} L {L}: Phi {r['phi'][0]:.3e} -> "
+                        f"{r['phi'][-1]:.3e}, err {last[1]:.3e} (magnitude {last[2]:.3e}) after {last[0]} epochs, "
+                        f"stat <= {tol:g} at epoch {r['tol_epoch']}, {r['seconds'] * 1e3:.1f} ms")
     return out
 
 
 def table(res: dict, at=None) -> str:
     """Markdown table: relative error at a few checkpoints per (peak, alpha, L)."""
     cps = at or [c for c in res["checkpoints"] if c in (1, 10, 50, 100, 200, 500, 1000)] or res["checkpoints"][-3:]
-    head = "| peak | alpha | L | " + " | ".join(f"err @{c}" for c in cps) + " | Phi end | stat<=tol epoch |"
-    rows = [head, "|" + "---|" * (len(cps) + 5)]
+    head = "| overlap | noise | alpha | L | " + " | ".join(f"err @{c}" for c in cps) + " | Phi end | stat<=tol epoch |"
+    rows = [head, "|" + "---|" * (len(cps) + 6)]
     for r in res["runs"]:
         e = {ep: er for ep, er, _ in r["errors"]}
         cells = " | ".join(f"{e[c]:.3e}" if c in e else "" for c in cps)
-        rows.append(f"| {r['peak'] or 'none'} | {r['alpha']:g} | {r['levels']} | {cells} | "
+        ov = "cfg" if r.get("overlap") is None else f"{r['overlap']:g}"
+        rows.append(f"| {ov} | {r.get('noise', 'none')} | {r['alpha']:g} | {r['levels']} | {cells} | "
                     f"{r['phi'][-1]:.3e} | {r['tol_epoch']} |")
     return "\n".join(rows)
 
@@ -149,6 +176,9 @@ def main():
     ap.add_argument("--levels", type=str, default="", help="comma list (default 1 .. log2(m) + 1)")
     ap.add_argument("--alphas", type=str, default="0.2,0.5,1.0")
     ap.add_argument("--peaks", type=str, default="none,1e4", help="comma list; 'none' = noiseless")
+    ap.add_argument("--etas", type=str, default="", help="comma list of the paper's noise levels eta")
+    ap.add_argument("--overlaps", type=str, default="",
+                    help="comma list of overlap ratios of adjacent scans (default: the workload's own step)")
     ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-4)
@@ -158,7 +188,10 @@ def main():
     levels = [int(x) for x in a.levels.split(",") if x]
     alphas = [float(x) for x in a.alphas.split(",") if x]
     peaks = [None if x.strip().lower() == "none" else float(x) for x in a.peaks.split(",") if x]
-    res = run(a.config, levels, alphas, peaks, a.epochs, a.batch or None, a.tol, a.seed)
+    etas = [float(x) for x in a.etas.split(",") if x]
+    overlaps = [float(x) for x in a.overlaps.split(",") if x] or [None]
+    res = run(a.config, levels, alphas, peaks, a.epochs, a.batch or None, a.tol, a.seed, etas=etas,
+              overlaps=overlaps)
     print(table(res), flush=True)
     if a.out:
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)

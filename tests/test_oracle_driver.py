@@ -5,7 +5,10 @@
 * the truth (and any global phase of it) is a fixed point for noiseless data;
 * near-truth starts converge on the cfg-1 geometry (noiseless);
 * the library's splitmix64 permutation generator reproduces the published
-  splitmix64 test vector and yields permutations.
+  splitmix64 test vector and yields permutations;
+* phase recycling (eq. 3.2): no effect without exact zeros, theta = 0 on the first
+  visit, and recycled phases of a visit at the truth recover the truth from a zeroed
+  patch (where theta = 0 does not).
 """
 
 import os
@@ -109,3 +112,53 @@ def test_error_metrics():
     mask = np.ones(z.shape, bool)
     assert oracle.error_relative(z * np.exp(0.7j), z, mask) < 1e-15
     assert np.isclose(oracle.error_paper(2 * z, z), np.linalg.norm(np.abs(z)))
+
+
+# --------------------------------------------------------------------------
+# Phase recycling, eq. (3.2)
+# --------------------------------------------------------------------------
+def test_phase_recycling_without_zeros_changes_nothing(rng):
+    """Generic data never make F(Q z_k) vanish, so eq. (3.2) reduces to Definition 2.1."""
+    z_true, Q, offs, sd = tiny_problem(rng, n=24, m=8, step=4, noiseless=False)
+    u = oracle.u_rpie(Q, 0.5)
+    z0 = z_true + 0.3 * crandn(rng, 24, 24)
+    orders = [rng.permutation(len(offs)) for _ in range(2)]
+    ph = oracle.initial_phases(len(offs), 8)
+    a = oracle.run_epochs(z0, Q, offs, sd, u, 2, orders, 3, phases=ph)
+    b = oracle.run_epochs(z0, Q, offs, sd, u, 2, orders, 3)
+    np.testing.assert_array_equal(a, b)
+    assert np.allclose(np.abs(ph), 1.0)
+
+
+def test_phase_recycling_first_visit_is_theta_zero(rng):
+    """j = 0: a vanishing exit wave takes theta = 0, as Definition 2.1's footnote."""
+    m = 8
+    Q = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    sd = rng.random((1, m, m)) + 0.5
+    zk = np.zeros((m, m), dtype=np.complex128)
+    R0 = oracle.revised_exit_wave(zk, Q, sd[0])
+    R1, ph = oracle.revised_exit_wave_recycled(zk, Q, sd[0], oracle.initial_phases(1, m)[0])
+    np.testing.assert_array_equal(R0, R1)
+    np.testing.assert_allclose(R1, oracle.ifft2(sd[0]), atol=1e-15)
+    np.testing.assert_array_equal(ph, np.ones((m, m)))
+
+
+def test_phase_recycling_recovers_truth_after_zeroing():
+    """One position, noiseless data.  A visit at z* stores the phases of F(Q z*); zero the
+    patch and visit again with one grid and u = 0: the recycled phases give back the true
+    exit wave (|F(Q z*)| e^{i arg F(Q z*)} = F(Q z*)), so the update returns z* wherever Q is
+    nonzero.  theta(0) = 0 instead leaves the real-valued F^{-1}(sqrt d) and misses z*."""
+    rng = np.random.default_rng(32)
+    m = 8
+    Q = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    z_true = (0.8 + 0.2 * rng.random((m, m))) * np.exp(1j * rng.uniform(-1.5, 1.5, (m, m)))
+    offs = np.zeros((1, 2), dtype=np.int32)
+    sd = np.sqrt(oracle.forward_model(z_true, Q, offs))
+    u = np.zeros((m, m))
+    ph = oracle.initial_phases(1, m)
+    z1 = oracle.run_epochs(z_true, Q, offs, sd, u, 1, [[0]], 1, phases=ph)
+    np.testing.assert_allclose(z1, z_true, atol=1e-13)            # z* is a fixed point
+    z2 = oracle.run_epochs(np.zeros((m, m)), Q, offs, sd, u, 1, [[0]], 1, phases=ph)
+    np.testing.assert_allclose(z2, z_true, atol=1e-12)
+    z3 = oracle.run_epochs(np.zeros((m, m)), Q, offs, sd, u, 1, [[0]], 1)
+    assert np.linalg.norm(z3 - z_true) > 0.1 * np.linalg.norm(z_true)

@@ -3,13 +3,25 @@
 import numpy as np
 import pytest
 
-from paper_2504_10118_amd.sweep import checkpoints, object_errors
+from paper_2504_10118_amd.sweep import checkpoints, object_errors, overlap_geometry
 
 
 def test_checkpoints_log_spaced():
     assert checkpoints(1) == [1]
     assert checkpoints(7) == [1, 2, 3, 5, 7]
     assert checkpoints(200) == [1, 2, 3, 5, 10, 20, 30, 50, 100, 200]
+
+
+def test_overlap_geometry_steps():
+    """Overlap ratio r of the probe's disc (diameter 20 m / 32) gives step (1 - r) * 2R over
+    the workload's own span; None keeps the workload."""
+    from synth import CONFIGS
+    cfg = CONFIGS[2]                      # m = 64: disc diameter 40 px, span 39 * 10 px
+    assert overlap_geometry(cfg, None) is cfg
+    for r, step, P in ((0.25, 30, 14), (0.5, 20, 20), (0.75, 10, 40)):
+        g = overlap_geometry(cfg, r)
+        assert (g.step, g.P) == (step, P)
+        assert (g.P - 1) * g.step <= (cfg.P - 1) * cfg.step
 
 
 def test_object_errors_global_phase_and_magnitude():
@@ -53,3 +65,14 @@ def test_short_sweep_runs_every_level():
         again = run_one(ctx, z_true.astype(np.complex64), illumination_mask(Q, offs, cfg.n), 20, cfg.batch, 7,
                         1e-4)
     assert again["phi"] == res["runs"][1]["phi"]
+
+
+@pytest.mark.gpu
+def test_sweep_noise_and_overlap_paths():
+    from paper_2504_10118_amd.sweep import run
+    res = run(config=1, levels=[1, 2], alphas=(0.5,), peaks=(), etas=(0.05,), overlaps=(None, 0.25), epochs=5,
+              log=lambda s: print(s, flush=True))
+    assert [(r["overlap"], r["levels"]) for r in res["runs"]] == [(None, 1), (None, 2), (0.25, 1), (0.25, 2)]
+    for r in res["runs"]:
+        assert r["finite"] and r["eta"] == 0.05 and r["phi"][-1] < r["phi"][0]
+    assert res["runs"][2]["positions"] < res["runs"][0]["positions"]
