@@ -59,6 +59,8 @@ extern "C" {
 #define MAGPIE_UPDATE_PROBE 0x1u  /* also update the probe each minibatch (beyond the paper) */
 #define MAGPIE_GRAPH        0x2u  /* replay a captured per-epoch hipGraph instead of
                                      launching each kernel directly (same results) */
+#define MAGPIE_PHASE_RECYCLE 0x4u /* eq. (3.2): where F(Q z_k) vanishes exactly, take the
+                                     phase of position k's previous visit instead of 0 */
 
 typedef struct magpie_ctx magpie_ctx;
 
@@ -163,10 +165,19 @@ int magpie_get_probe(magpie_ctx* ctx, void* out, int dtype, int on_device);
 /* Wait for all work enqueued on the context's stream. */
 int magpie_sync(magpie_ctx* ctx);
 
-/* Set behaviour flags (MAGPIE_UPDATE_PROBE, MAGPIE_GRAPH).  beta: probe-step
- * proximal weight.  With MAGPIE_GRAPH (and timing off) an epoch is one replay
- * of a hipGraph captured on first use for the current minibatch size; the
- * graph reads the epoch's permutation through a device counter. */
+/* Set behaviour flags (MAGPIE_UPDATE_PROBE, MAGPIE_GRAPH, MAGPIE_PHASE_RECYCLE).
+ * beta: probe-step proximal weight.  With MAGPIE_GRAPH (and timing off) an epoch
+ * is one replay of a hipGraph captured on first use for the current minibatch
+ * size; the graph reads the epoch's permutation through a device counter.
+ * MAGPIE_PHASE_RECYCLE (Section 3.1, eq. 3.2) keeps the phase of F(Q z_k) of
+ * every position's last visit in device memory the context owns (n_pos * m * m
+ * complex64, natural order) and uses it wherever F(Q z_k) is exactly zero
+ * (theta = 0 before a position's first visit).  The store starts over (theta =
+ * 0 everywhere) when the flag is switched on, on magpie_set_positions and on
+ * magpie_load_intensities; magpie_set_object keeps it.  Only object steps use
+ * it (the objective and its stopping statistic keep theta(0) = 0); the
+ * autotuner's trial epochs leave it untouched, and magpie_run_epochs_multi
+ * rejects contexts with this flag (MAGPIE_ERR_UNSUPPORTED). */
 int magpie_set_flags(magpie_ctx* ctx, uint32_t flags, double beta);
 
 /*

@@ -15,6 +15,7 @@ from .magpie import (  # noqa: F401
     W_BF16,
     W_F32,
     UPDATE_PROBE,
+    PHASE_RECYCLE,
     GRAPH,
     LIB_PATH,
     Magpie,

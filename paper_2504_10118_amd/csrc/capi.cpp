@@ -12,8 +12,30 @@ void drop_graph(magpie_ctx* c) {
   c->g_batch = 0;
 }
 
+// eq. (3.2) phase store: sized for the current positions and reset to theta = 0
+// (factor 1) while MAGPIE_PHASE_RECYCLE is on, freed while it is off.
+int reset_phases(magpie_ctx* c) {
+  const bool on = (c->flags & MAGPIE_PHASE_RECYCLE) && c->has_pos;
+  const size_t need = on ? (size_t)c->n_pos * c->m * c->m : 0;
+  if (!on || need != c->phase_cap) {
+    drop_graph(c);
+    dev_free(c->phase);
+    c->phase_cap = 0;
+  }
+  if (!on) return MAGPIE_OK;
+  if (!c->phase) {
+    int rc = dev_alloc(&c->phase, need);
+    if (rc) return rc;
+    c->phase_cap = need;
+  }
+  MG_HIP(mg::launch_fill_c64(c->phase, need, 1.0f, 0.0f, c->stream));
+  return MAGPIE_OK;
+}
+
 int free_positions(magpie_ctx* c) {
   drop_graph(c);
+  dev_free(c->phase);
+  c->phase_cap = 0;
   dev_free(c->offs);
   dev_free(c->sqrtd);
   dev_free(c->phi_step);
@@ -313,7 +335,7 @@ int magpie_set_positions(magpie_ctx* c, int n_pos, const int32_t* offsets) {
     return rc;
   }
   c->has_pos = true;
-  return MAGPIE_OK;
+  return reset_phases(c);
 }
 
 int magpie_load_intensities(magpie_ctx* c, const float* d, int is_sqrt, int on_device) {
@@ -345,7 +367,7 @@ int magpie_load_intensities(magpie_ctx* c, const float* d, int is_sqrt, int on_d
     return fail(MAGPIE_ERR_NUMERIC, "intensities contain negative or non-finite values");
   }
   c->has_data = true;
-  return MAGPIE_OK;
+  return reset_phases(c);
 }
 
 int magpie_set_object(magpie_ctx* c, const void* z, int dtype, int on_device) {
@@ -509,6 +531,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   sa.levels = c->L;
   sa.lvl_a_off = c->lvl_a_off;
   sa.phi_part = c->step_part;
+  sa.phase = (c->flags & MAGPIE_PHASE_RECYCLE) ? c->phase : nullptr;
   if (probe_step) {
     sa.probe_num = c->pnum;
     sa.probe_den = c->pden;
@@ -695,11 +718,17 @@ int magpie_sync(magpie_ctx* c) {
 
 int magpie_set_flags(magpie_ctx* c, uint32_t flags, double beta) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
-  if (flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_GRAPH)) return fail(MAGPIE_ERR_INVALID_ARG, "unknown flag");
+  if (flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_GRAPH | MAGPIE_PHASE_RECYCLE))
+    return fail(MAGPIE_ERR_INVALID_ARG, "unknown flag");
   if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(MAGPIE_ERR_INVALID_ARG, "beta must be finite, >= 0");
-  if (((c->flags ^ flags) & MAGPIE_UPDATE_PROBE) || beta != c->beta) drop_graph(c);
+  int rc = set_dev(c);
+  if (rc) return rc;
+  if (((c->flags ^ flags) & (MAGPIE_UPDATE_PROBE | MAGPIE_PHASE_RECYCLE)) || beta != c->beta) drop_graph(c);
+  const bool recycle_on = (flags & MAGPIE_PHASE_RECYCLE) && !(c->flags & MAGPIE_PHASE_RECYCLE);
+  const bool recycle_off = !(flags & MAGPIE_PHASE_RECYCLE) && (c->flags & MAGPIE_PHASE_RECYCLE);
   c->flags = flags;
   c->beta = beta;
+  if (recycle_on || recycle_off) return reset_phases(c);
   return MAGPIE_OK;
 }
 
@@ -860,7 +889,7 @@ int magpie_autotune(magpie_ctx* c, int batch, int trial_epochs, double* step_us,
   const uint64_t ep = c->epoch_index;
   const uint32_t flags = c->flags;
   const bool timing = c->timing;
-  c->flags = flags & ~MAGPIE_UPDATE_PROBE;
+  c->flags = flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_PHASE_RECYCLE);   // trials leave the phase store alone
   c->timing = true;
   double* sm = nullptr;
   double am = 0.0, best_step = 1e300, best_acc = 1e300;
@@ -922,6 +951,8 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     if (ctxs[i]->device != ctxs[0]->device) return fail(MAGPIE_ERR_INVALID_ARG, "contexts on different devices");
     if (ctxs[i]->flags & MAGPIE_UPDATE_PROBE)
       return fail(MAGPIE_ERR_UNSUPPORTED, "the probe step is not available in multi-context runs");
+    if (ctxs[i]->flags & MAGPIE_PHASE_RECYCLE)
+      return fail(MAGPIE_ERR_UNSUPPORTED, "phase recycling is not available in multi-context runs");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return fail(MAGPIE_ERR_INVALID_ARG, "a context appears twice");
   }

@@ -122,6 +122,8 @@ struct magpie_ctx {
 
   float2* stage = nullptr;
   size_t stage_cap = 0;  // in float2
+  float2* phase = nullptr;  // eq. (3.2) phase store [n_pos][m][m], natural order (flag MAGPIE_PHASE_RECYCLE)
+  size_t phase_cap = 0;     // in float2
   float2* pnum = nullptr;   // probe step partials (allocated with the staging when the flag is on)
   float* pden = nullptr;
   float* pmax = nullptr;

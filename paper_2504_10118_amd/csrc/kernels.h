@@ -7,6 +7,8 @@
 namespace mg {
 
 enum StepMode { MODE_STEP = 0, MODE_OBJECTIVE = 1, MODE_FORWARD = 2 };
+// (internal) MODE_STEP with the eq. (3.2) phase store, chosen by launch_step when StepArgs::phase is set
+constexpr int MODE_STEP_PR = 3;
 
 constexpr int MAX_WAVES = 16;   // per-position partial sums (one per wave of a workgroup)
 
@@ -35,6 +37,7 @@ struct StepArgs {
   float2* probe_num;      // probe step: conj(z_k)(R_k - Q z_k) per position [count][m][m] (nullable)
   float* probe_den;       // probe step: |z_k|^2 per position [count][m][m]
   float* probe_max;       // probe step: per-wave max |z_k|^2 [count][MAX_WAVES]
+  float2* phase;          // MODE_STEP, nullable: eq. (3.2) phase store [N][m][m] natural order
 };
 
 struct AccumArgs {
@@ -98,5 +101,6 @@ hipError_t launch_probe_apply(int m, int count, int nwaves, const float2* num, c
 hipError_t launch_convert_c64_c128(const float2* src, double2* dst, size_t n, hipStream_t s);
 hipError_t launch_convert_c128_c64(const double2* src, float2* dst, size_t n, hipStream_t s);
 hipError_t launch_check_finite_c64(const float2* src, size_t n, int* bad_flag, hipStream_t s);
+hipError_t launch_fill_c64(float2* dst, size_t n, float re, float im, hipStream_t s);
 
 }  // namespace mg

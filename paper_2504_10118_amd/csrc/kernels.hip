@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "cmath.h"
@@ -154,6 +155,7 @@ __device__ __forceinline__ StepArgs load_step_args(const StepArgs* p) {
   a.probe_num = d->probe_num;
   a.probe_den = d->probe_den;
   a.probe_max = d->probe_max;
+  a.phase = nullptr;   // multi-context runs do not recycle phases
   return a;
 }
 
@@ -344,10 +346,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr bool KEEP = keeps_exit_wave(M);
   constexpr bool ROWS = true;             // row-wise gathers through the LDS tile
   constexpr bool PREQ = (RA <= 8);        // probe table entries fetched before the gather
-  constexpr bool CST = (MODE == MODE_STEP) && (M <= 64);
+  // MODE_STEP_PR is the object step with the eq. (3.2) phase store
+  constexpr bool STEPM = (MODE == MODE_STEP) || (MODE == MODE_STEP_PR);
+  constexpr bool CST = STEPM && (M <= 64);
   // M = 128: the V-cycle constants do not fit beside the FFT tile; they are
   // staged into the tile once the FFT and the gradient are done with it.
-  constexpr bool CSTL = (MODE == MODE_STEP) && (M > 64);
+  constexpr bool CSTL = STEPM && (M > 64);
   // Loads that do not depend on z_k are issued first: the probe table, the
   // twiddles, sqrt(d) and the V-cycle constants.
   float2 psi[KEEP ? RA : 1], qk[KEEP ? RA : 1];
@@ -523,6 +527,32 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   } else {
     // ---- modulus replacement (Definition 2.1, theta(0) = 0); Phi_k partial in FP64
     double phis = 0.0;
+    if constexpr (MODE == MODE_STEP_PR) {
+      // eq. (3.2): every phase factor is kept for the position's next visit and
+      // read back where the spectrum vanishes exactly (theta = 0 before the
+      // first visit: the store starts as 1).  Natural order: row ky = col,
+      // column kx = g*CB + c + RA*k2 for j = c*RB + k2.
+      float2* const ph = a.phase + (size_t)k * M * M + (size_t)col * M;
+#pragma unroll
+      for (int j = 0; j < RA; ++j) {
+        const int kx = g * CB + j / RB + RA * (j % RB);
+        const float2 t = v[j];
+        const float a2 = t.x * t.x + t.y * t.y;
+        const float s = sd[j];
+        float2 e;
+        if (a2 > 0.0f) {
+          const float ra = __builtin_amdgcn_rsqf(a2);
+          const double dlt = (double)(a2 * ra) - (double)s;
+          phis += dlt * dlt;
+          e = make_float2(t.x * ra, t.y * ra);
+          ph[kx] = e;
+        } else {
+          phis += (double)s * (double)s;
+          e = ph[kx];
+        }
+        v[j] = make_float2(s * e.x, s * e.y);
+      }
+    } else {
 #pragma unroll
     for (int j = 0; j < RA; ++j) {
       const float2 t = v[j];
@@ -538,6 +568,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         phis += (double)s * (double)s;
         v[j] = make_float2(s, 0.0f);
       }
+    }
     }
     if (a.phi_part) {
       const double tot = wave_sum<LANES>(phis);
@@ -633,7 +664,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         ps = cmul(qq, z_again(n1));
       }
       const float2 rk = cscale(v[n1], inv_m2);
-      if constexpr (MODE == MODE_STEP) {
+      if constexpr (STEPM) {
         if (a.probe_num) {
           // probe step partials: conj(z_k)(R_k - Q z_k) and |z_k|^2
           const float2 zz = KEEP ? bload2(zr, zvo, n1 * zso) : z_again(n1);
@@ -647,7 +678,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       }
       v[n1] = cmulc(qq, csub(ps, rk));
     }
-    if constexpr (MODE == MODE_STEP) {
+    if constexpr (STEPM) {
       if (a.probe_num) {
         const float wm = wave_max<LANES>(pmx);
         if ((tid & 63) == 0) a.probe_max[(size_t)wg * MAX_WAVES + wave] = wm;
@@ -815,7 +846,9 @@ template <int M, int RB>
 static hipError_t launch_step_p(int mode, const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.count <= 0) return hipSuccess;
   switch (mode) {
-    case MODE_STEP: return launch_step_mode<M, RB, MODE_STEP>(a, s, ev0, ev1);
+    case MODE_STEP:
+      return a.phase ? launch_step_mode<M, RB, MODE_STEP_PR>(a, s, ev0, ev1)
+                     : launch_step_mode<M, RB, MODE_STEP>(a, s, ev0, ev1);
     case MODE_OBJECTIVE: return launch_step_mode<M, RB, MODE_OBJECTIVE>(a, s, ev0, ev1);
     case MODE_FORWARD: return launch_step_mode<M, RB, MODE_FORWARD>(a, s, ev0, ev1);
     default: return hipErrorInvalidValue;
@@ -1389,6 +1422,18 @@ hipError_t launch_convert_c128_c64(const double2* src, float2* dst, size_t n, hi
 hipError_t launch_check_finite_c64(const float2* src, size_t n, int* bad, hipStream_t s) {
   if (!n) return hipSuccess;
   hipLaunchKernelGGL(check_finite_c64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, n, bad);
+  return hipGetLastError();
+}
+
+__global__ void fill_c64_kernel(float2* dst, size_t n, float re, float im) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = make_float2(re, im);
+}
+
+hipError_t launch_fill_c64(float2* dst, size_t n, float re, float im, hipStream_t s) {
+  if (!n) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_c64_kernel, dim3(blocks), dim3(256), 0, s, dst, n, re, im);
   return hipGetLastError();
 }
 

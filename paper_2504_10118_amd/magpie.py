@@ -23,6 +23,7 @@ ERRORS = {
 C64, C128 = 0, 1
 UPDATE_PROBE = 0x1
 GRAPH = 0x2
+PHASE_RECYCLE = 0x4
 W_F32, W_BF16 = 0, 1
 COARSE_C64, COARSE_C128, COARSE_LOGPOLAR = 0, 1, 2
 
