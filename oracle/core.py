@@ -63,7 +63,7 @@ __all__ = [
     "illumination", "error_paper", "error_relative", "splitmix64",
     "library_permutation", "batches", "full_batch_surrogate_minimiser",
     "probe_update_step", "blind_minibatch_step", "run_epochs_blind",
-    "phase_factor_recycled", "revised_exit_wave_recycled", "initial_phases",
+    "phase_factor_recycled", "revised_exit_wave_recycled", "initial_phases", "error_scaled",
 ]
 
 M64 = (1 << 64) - 1
@@ -463,24 +463,28 @@ def probe_update_step(z, Q, offsets, sqrt_d, batch, beta):
     return Qn
 
 
-def blind_minibatch_step(z, Q, offsets, sqrt_d, alpha, levels: int, batch, beta, u=None):
-    """Object step (minibatch MAGPS) and probe step from the same (z, Q), applied together.
+def blind_minibatch_step(z, Q, offsets, sqrt_d, alpha, levels: int, batch, beta, u=None, alternate=False):
+    """Object step (minibatch MAGPS) and probe step.  Simultaneous (default): both from the
+    same (z, Q).  Alternating: the probe step is taken at the new object, so each half step
+    is a proximal majorisation-minimisation step in its own variable (Lemma C.1 applied to
+    z, then to Q) and, with one grid, the minibatch's partial objective cannot increase.
 
     u = u^rPIE(Q, alpha) of the current probe unless a fixed u is given.
     """
     uu = u_rpie(Q, alpha) if u is None else u
     znew = minibatch_step(z, Q, offsets, sqrt_d, uu, levels, batch)
-    Qnew = probe_update_step(z, Q, offsets, sqrt_d, batch, beta)
+    Qnew = probe_update_step(znew if alternate else z, Q, offsets, sqrt_d, batch, beta)
     return znew, Qnew
 
 
-def run_epochs_blind(z0, Q0, offsets, sqrt_d, alpha, levels: int, orders, B: int, beta, u=None):
-    """Epochs of minibatch MAGPIE with the simultaneous probe step after every minibatch."""
+def run_epochs_blind(z0, Q0, offsets, sqrt_d, alpha, levels: int, orders, B: int, beta, u=None,
+                     alternate=False):
+    """Epochs of minibatch MAGPIE with the probe step after every minibatch."""
     z = np.array(z0, dtype=np.complex128, copy=True)
     Q = np.array(Q0, dtype=np.complex128, copy=True)
     for order in orders:
         for batch in batches(order, B):
-            z, Q = blind_minibatch_step(z, Q, offsets, sqrt_d, alpha, levels, batch, beta, u)
+            z, Q = blind_minibatch_step(z, Q, offsets, sqrt_d, alpha, levels, batch, beta, u, alternate)
     return z, Q
 
 
@@ -521,6 +525,17 @@ def error_relative(z, z_true, mask) -> float:
     ip = np.vdot(a, b)
     ph = np.exp(1j * np.angle(ip)) if ip != 0 else 1.0
     return float(np.linalg.norm(ph * a - b) / np.linalg.norm(b))
+
+
+def error_scaled(z, z_true, mask) -> float:
+    """min_c ||c z - z*||_M / ||z*||_M over complex scalars c: with the probe also unknown,
+    (c z, Q / c) explain the same data, so only z up to a complex scale is determined;
+    c = <z, z*>_M / <z, z>_M (least squares)."""
+    a = z[mask]
+    b = z_true[mask]
+    den = np.vdot(a, a)
+    c = np.vdot(a, b) / den if den != 0 else 0.0
+    return float(np.linalg.norm(c * a - b) / np.linalg.norm(b))
 
 
 # --------------------------------------------------------------------------
