@@ -61,6 +61,9 @@ extern "C" {
                                      launching each kernel directly (same results) */
 #define MAGPIE_PHASE_RECYCLE 0x4u /* eq. (3.2): where F(Q z_k) vanishes exactly, take the
                                      phase of position k's previous visit instead of 0 */
+#define MAGPIE_PROBE_ALTERNATE 0x8u /* with MAGPIE_UPDATE_PROBE: take the probe step at the
+                                     minibatch's updated object (alternating half steps)
+                                     instead of at the object the step started from */
 
 typedef struct magpie_ctx magpie_ctx;
 
@@ -177,7 +180,13 @@ int magpie_sync(magpie_ctx* ctx);
  * magpie_load_intensities; magpie_set_object keeps it.  Only object steps use
  * it (the objective and its stopping statistic keep theta(0) = 0); the
  * autotuner's trial epochs leave it untouched, and magpie_run_epochs_multi
- * rejects contexts with this flag (MAGPIE_ERR_UNSUPPORTED). */
+ * rejects contexts with this flag (MAGPIE_ERR_UNSUPPORTED).
+ * MAGPIE_PROBE_ALTERNATE (only together with MAGPIE_UPDATE_PROBE, else
+ * MAGPIE_ERR_INVALID_ARG): the probe step of each minibatch is taken after its
+ * object update, at the new object, by a second pass of the step kernel over the
+ * minibatch; each half step then minimises its proximal surrogate in its own
+ * variable (Lemma C.1 in z, then in Q), so with one grid the minibatch's partial
+ * objective does not increase.  Costs one more step-kernel launch per minibatch. */
 int magpie_set_flags(magpie_ctx* ctx, uint32_t flags, double beta);
 
 /*

@@ -16,6 +16,7 @@ from .magpie import (  # noqa: F401
     W_F32,
     UPDATE_PROBE,
     PHASE_RECYCLE,
+    PROBE_ALTERNATE,
     GRAPH,
     LIB_PATH,
     Magpie,

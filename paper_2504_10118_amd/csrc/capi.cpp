@@ -537,6 +537,26 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
     sa.probe_den = c->pden;
     sa.probe_max = c->pmax;
   }
+  // Alternating probe step: after the minibatch's object update a second pass of
+  // the step kernel forms the probe partials at the new object (its staged
+  // object update is not used, and it neither records Phi_k nor visits the
+  // phase store).
+  const bool alternate = probe_step && (c->flags & MAGPIE_PROBE_ALTERNATE);
+  mg::StepArgs sp = sa;
+  if (alternate) {
+    sa.probe_num = nullptr;
+    sa.probe_den = nullptr;
+    sa.probe_max = nullptr;
+    sp.phi_part = nullptr;
+    sp.phase = nullptr;
+  }
+  auto probe_pass = [&]() -> hipError_t {
+    sp.pos = sa.pos;
+    sp.count = sa.count;
+    sp.epoch = sa.epoch;
+    sp.epoch_stride = sa.epoch_stride;
+    return mg::launch_step(m, c->rb, mg::MODE_STEP, sp, c->stream);
+  };
   const int nw = mg::step_waves(m, c->rb);
   // probe step after a minibatch's accumulation: apply, then rebuild the hierarchy
   auto probe_tail = [&](int count) -> hipError_t {
@@ -580,6 +600,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
         ce = mg::launch_step(m, c->rb, mg::MODE_STEP, sa, c->stream);
         aa.batch_index = t;
         if (ce == hipSuccess) ce = mg::launch_accumulate(aa, c->th, n_tiles, c->stream);
+        if (ce == hipSuccess && alternate) ce = probe_pass();
         if (ce == hipSuccess && probe_step) ce = probe_tail(sa.count);
       }
       if (ce == hipSuccess) ce = mg::launch_advance_counter(c->epoch_ctr, c->stream);
@@ -617,6 +638,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
       ti = timed_slot(c, 1, 0);
       MG_HIP(mg::launch_accumulate(aa, c->th, n_tiles, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
                                    ti >= 0 ? c->timed[ti].b : nullptr));
+      if (alternate) MG_HIP(probe_pass());
       if (probe_step) MG_HIP(probe_tail(sa.count));
     }
   }
@@ -718,12 +740,16 @@ int magpie_sync(magpie_ctx* c) {
 
 int magpie_set_flags(magpie_ctx* c, uint32_t flags, double beta) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
-  if (flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_GRAPH | MAGPIE_PHASE_RECYCLE))
+  if (flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_GRAPH | MAGPIE_PHASE_RECYCLE | MAGPIE_PROBE_ALTERNATE))
     return fail(MAGPIE_ERR_INVALID_ARG, "unknown flag");
+  if ((flags & MAGPIE_PROBE_ALTERNATE) && !(flags & MAGPIE_UPDATE_PROBE))
+    return fail(MAGPIE_ERR_INVALID_ARG, "MAGPIE_PROBE_ALTERNATE needs MAGPIE_UPDATE_PROBE");
   if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(MAGPIE_ERR_INVALID_ARG, "beta must be finite, >= 0");
   int rc = set_dev(c);
   if (rc) return rc;
-  if (((c->flags ^ flags) & (MAGPIE_UPDATE_PROBE | MAGPIE_PHASE_RECYCLE)) || beta != c->beta) drop_graph(c);
+  if (((c->flags ^ flags) & (MAGPIE_UPDATE_PROBE | MAGPIE_PHASE_RECYCLE | MAGPIE_PROBE_ALTERNATE)) ||
+      beta != c->beta)
+    drop_graph(c);
   const bool recycle_on = (flags & MAGPIE_PHASE_RECYCLE) && !(c->flags & MAGPIE_PHASE_RECYCLE);
   const bool recycle_off = !(flags & MAGPIE_PHASE_RECYCLE) && (c->flags & MAGPIE_PHASE_RECYCLE);
   c->flags = flags;
@@ -889,7 +915,8 @@ int magpie_autotune(magpie_ctx* c, int batch, int trial_epochs, double* step_us,
   const uint64_t ep = c->epoch_index;
   const uint32_t flags = c->flags;
   const bool timing = c->timing;
-  c->flags = flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_PHASE_RECYCLE);   // trials leave the phase store alone
+  // trials leave the probe and the phase store alone
+  c->flags = flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_PHASE_RECYCLE | MAGPIE_PROBE_ALTERNATE);
   c->timing = true;
   double* sm = nullptr;
   double am = 0.0, best_step = 1e300, best_acc = 1e300;

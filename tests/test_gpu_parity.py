@@ -267,10 +267,12 @@ def test_graph_replays_match_direct_launches():
     assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
 
 
+@pytest.mark.parametrize("alternate", [False, True])
 @pytest.mark.parametrize("m,levels,batch", [(16, 3, 6), (64, 3, 5), (128, 2, 4)])
-def test_probe_update_parity(m, levels, batch):
-    """MAGPIE_UPDATE_PROBE: object and probe after one epoch vs the oracle's simultaneous steps."""
-    from paper_2504_10118_amd import UPDATE_PROBE
+def test_probe_update_parity(m, levels, batch, alternate):
+    """MAGPIE_UPDATE_PROBE: object and probe after one epoch vs the oracle's simultaneous
+    steps, or (MAGPIE_PROBE_ALTERNATE) its alternating steps, the probe step at the new object."""
+    from paper_2504_10118_amd import PROBE_ALTERNATE, UPDATE_PROBE
     rng = np.random.default_rng(15 + m)
     c = Case(rng, 2 * m + 9, 2 * m + 4, m, max(2, m // 3), noise=0.05)
     Q0 = (c.Q32 * (1 + 0.1 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))))).astype(np.complex64)
@@ -278,17 +280,33 @@ def test_probe_update_parity(m, levels, batch):
     beta = 0.2
     g = c.gpu(levels, 0.5)
     g.set_probe(Q0)
-    g.set_flags(UPDATE_PROBE, beta)
+    g.set_flags(UPDATE_PROBE | (PROBE_ALTERNATE if alternate else 0), beta)
     g.run_epochs(1, batch, order=order[None])
     zg = g.get_object().astype(np.complex128)
     Qg = g.get_probe().astype(np.complex128)
     g.close()
-    zo, Qo = oracle.run_epochs_blind(c.z0, Q0.astype(np.complex128), c.offs, c.sd, 0.5, levels, [order], batch, beta)
+    zo, Qo = oracle.run_epochs_blind(c.z0, Q0.astype(np.complex128), c.offs, c.sd, 0.5, levels, [order], batch, beta,
+                                     alternate=alternate)
     rz = c.rel(zg, zo)
     rq = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo)
-    _print("probe update m", m, "object rel", rz, "probe rel", rq)
+    _print("probe update m", m, "alternate", alternate, "object rel", rz, "probe rel", rq)
     assert rz <= 1e-5
     assert rq <= 1e-5
+    if alternate:
+        # the two orders of the half steps give different probes
+        _, Qsim = oracle.run_epochs_blind(c.z0, Q0.astype(np.complex128), c.offs, c.sd, 0.5, levels, [order], batch,
+                                          beta)
+        assert np.linalg.norm(Qsim - Qo) > 100 * 1e-5 * np.linalg.norm(Qo)
+
+
+def test_probe_alternate_needs_probe_update():
+    from paper_2504_10118_amd import PROBE_ALTERNATE, MagpieError
+    rng = np.random.default_rng(19)
+    c = Case(rng, 40, 40, 16, 6)
+    g = c.gpu(2, 0.5)
+    with pytest.raises(MagpieError):
+        g.set_flags(PROBE_ALTERNATE)
+    g.close()
 
 
 @pytest.mark.parametrize("m,rb,levels", [(16, 2, 3), (32, 2, 3), (64, 4, 3), (64, 4, 5), (32, 2, 6), (128, 4, 4),
