@@ -52,6 +52,19 @@ def object_errors(z, z_true, mask) -> tuple[float, float]:
     return float(np.linalg.norm(ph * a - b) / nb), float(np.linalg.norm(np.abs(a) - np.abs(b)) / nb)
 
 
+def scaled_error(a, b, mask=None) -> float:
+    """min over complex c of ||c a - b|| / ||b|| (on the mask): the error of a blind
+    reconstruction, where (c z, Q / c) explain the same data."""
+    x = np.asarray(a, dtype=np.complex128)
+    y = np.asarray(b, dtype=np.complex128)
+    if mask is not None:
+        x, y = x[mask], y[mask]
+    x, y = x.ravel(), y.ravel()
+    den = np.vdot(x, x)
+    c = np.vdot(x, y) / den if den != 0 else 0.0
+    return float(np.linalg.norm(c * x - y) / np.linalg.norm(y))
+
+
 def illumination_mask(Q, offs, n: int) -> np.ndarray:
     m = Q.shape[0]
     A = np.abs(np.asarray(Q, dtype=np.complex128)) ** 2
@@ -156,6 +169,56 @@ def run(config: int = 2, levels=None, alphas=(0.2, 0.5, 1.0), peaks=(None, 1e4),
     return out
 
 
+def run_blind(config: int = 2, levels=(1, 3), modes=("fixed", "simultaneous", "alternating"), epochs: int = 300,
+              beta: float = 0.5, alpha: float = 0.5, batch: int | None = None, seed: int = 7, log=print) -> dict:
+    """Blind reconstruction from noiseless data with the probe's defocus phase unknown: the
+    start probe is |Q| (the aperture without its quadratic phase).  Modes: the probe kept
+    at that start ("fixed"), probe steps simultaneous with the object steps, or alternating
+    (each minibatch's probe step at its updated object).  Errors after removing the complex
+    scale that blind data cannot fix, at log-spaced epochs; GPU wall time of the epochs."""
+    from synth import CONFIGS, make_problem_inputs
+    from .magpie import PROBE_ALTERNATE, UPDATE_PROBE
+    cfg = CONFIGS[config]
+    z_true, Q, offs, _, _ = make_problem_inputs(cfg)
+    Q32 = Q.astype(np.complex64)
+    Q0 = np.abs(Q).astype(np.complex64)
+    z32 = z_true.astype(np.complex64)
+    n, m = cfg.n, cfg.m
+    B = min(batch or cfg.batch, len(offs))
+    mask = illumination_mask(Q32, offs, n)
+    with Magpie(n, n, m, 1, alpha) as fm:
+        fm.set_probe(Q32)
+        fm.set_positions(offs)
+        d = fm.forward_model(z32)
+    flags = {"fixed": 0, "simultaneous": UPDATE_PROBE, "alternating": UPDATE_PROBE | PROBE_ALTERNATE}
+    cps = set(checkpoints(epochs))
+    out = {"config": config, "epochs": epochs, "beta": beta, "alpha": alpha, "batch": B,
+           "probe_start": "|Q| (quadratic phase unknown)", "runs": []}
+    for L in levels:
+        for mode in modes:
+            with Magpie(n, n, m, L, alpha) as ctx:
+                ctx.set_probe(Q0)
+                ctx.set_positions(offs)
+                ctx.load_intensities(d, is_sqrt=False)
+                ctx.set_object(np.ones((n, n), dtype=np.complex64))
+                ctx.set_flags(flags[mode], beta)
+                rows, gpu_s = [], 0.0
+                for e in range(1, epochs + 1):
+                    t0 = time.perf_counter()
+                    ctx.run_epochs(1, B, seed=seed)
+                    ctx.sync()
+                    gpu_s += time.perf_counter() - t0
+                    if e in cps:
+                        phi, _ = ctx.objective()
+                        rows.append((e, scaled_error(ctx.get_object(), z32, mask),
+                                     scaled_error(ctx.get_probe(), Q32), phi))
+            out["runs"].append({"levels": L, "mode": mode, "trace": rows, "seconds": gpu_s})
+            last = rows[-1]
+            log(f"L {L} {mode:>12}: after {last[0]} epochs object err {last[1]:.3e}, probe err {last[2]:.3e}, "
+                f"Phi {last[3]:.3e} ({gpu_s * 1e3:.0f} ms)")
+    return out
+
+
 def table(res: dict, at=None) -> str:
     """Markdown table: relative error at a few checkpoints per (peak, alpha, L)."""
     cps = at or [c for c in res["checkpoints"] if c in (1, 10, 50, 100, 200, 500, 1000)] or res["checkpoints"][-3:]
@@ -184,7 +247,24 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", type=str, default="")
+    ap.add_argument("--blind", action="store_true",
+                    help="blind runs instead: the start probe lacks its phase; fixed / simultaneous / alternating "
+                         "probe steps at each --levels (default 1,3), --alphas[0], --beta")
+    ap.add_argument("--beta", type=float, default=0.5)
     a = ap.parse_args()
+    if a.blind:
+        lv = [int(x) for x in a.levels.split(",") if x] or [1, 3]
+        res = run_blind(a.config, lv, epochs=a.epochs, beta=a.beta, alpha=float(a.alphas.split(",")[0]),
+                        batch=a.batch or None, seed=a.seed)
+        print("| L | mode | " + " | ".join(f"obj/probe err @{r[0]}" for r in res["runs"][0]["trace"]) + " |")
+        for r in res["runs"]:
+            print(f"| {r['levels']} | {r['mode']} | " + " | ".join(f"{o:.2e} / {q:.2e}" for _, o, q, _ in r["trace"])
+                  + " |")
+        if a.out:
+            os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+            with open(a.out, "w") as f:
+                json.dump(res, f)
+        return
     levels = [int(x) for x in a.levels.split(",") if x]
     alphas = [float(x) for x in a.alphas.split(",") if x]
     peaks = [None if x.strip().lower() == "none" else float(x) for x in a.peaks.split(",") if x]

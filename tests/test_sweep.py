@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from paper_2504_10118_amd.sweep import checkpoints, object_errors, overlap_geometry
+from paper_2504_10118_amd.sweep import checkpoints, object_errors, overlap_geometry, scaled_error
 
 
 def test_checkpoints_log_spaced():
@@ -22,6 +22,18 @@ def test_overlap_geometry_steps():
         g = overlap_geometry(cfg, r)
         assert (g.step, g.P) == (step, P)
         assert (g.P - 1) * g.step <= (cfg.P - 1) * cfg.step
+
+
+def test_scaled_error_ignores_a_complex_scale():
+    rng = np.random.default_rng(4)
+    z = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    assert scaled_error((0.3 - 2j) * z, z) < 1e-14
+    w = z + 0.1 * (rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8)))
+    e = scaled_error(w, z)
+    assert 0 < e <= np.linalg.norm(w - z) / np.linalg.norm(z)
+    mask = np.zeros((8, 8), bool)
+    mask[2:6] = True
+    assert scaled_error(np.where(mask, 2j * z, 0), z, mask) < 1e-14
 
 
 def test_object_errors_global_phase_and_magnitude():
@@ -76,3 +88,18 @@ def test_sweep_noise_and_overlap_paths():
     for r in res["runs"]:
         assert r["finite"] and r["eta"] == 0.05 and r["phi"][-1] < r["phi"][0]
     assert res["runs"][2]["positions"] < res["runs"][0]["positions"]
+
+
+@pytest.mark.gpu
+def test_blind_runs():
+    from paper_2504_10118_amd.sweep import run_blind
+    from synth import CONFIGS, make_problem_inputs
+    res = run_blind(config=1, levels=(2,), epochs=20, log=lambda s: print(s, flush=True))
+    assert [r["mode"] for r in res["runs"]] == ["fixed", "simultaneous", "alternating"]
+    Q = make_problem_inputs(CONFIGS[1])[1]
+    start = scaled_error(np.abs(Q), Q)
+    for r in res["runs"]:
+        assert all(np.isfinite(v) for row in r["trace"] for v in row)
+    fixed = res["runs"][0]["trace"]
+    assert all(abs(q - start) < 1e-6 for _, _, q, _ in fixed)       # the probe never moves
+    assert res["runs"][2]["trace"][-1][2] != fixed[-1][2]              # the alternating probe does
