@@ -717,7 +717,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
           const int nC = cst_count(M, L);
           const double2* src = reinterpret_cast<const double2*>(a.lvl + a.lvl_a_off);
           double2* dst = reinterpret_cast<double2*>(T);
-          for (int e = tid; 2 * e < nC; e += TPB) dst[e] = src[e];
+          // every copy of a thread in flight at once (a loop trip per load was latency-bound)
+          constexpr int NSTG = (cst_count_max(M, LWI) / 2 + 1 + TPB - 1) / TPB;   // copies per thread at most
+          double2 tmp[NSTG];
+#pragma unroll
+          for (int i = 0; i < NSTG; ++i) {
+            const int e = tid + i * TPB;
+            tmp[i] = (2 * e < nC) ? src[e] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int i = 0; i < NSTG; ++i) {
+            const int e = tid + i * TPB;
+            if (2 * e < nC) dst[e] = tmp[i];
+          }
           __syncthreads();
         }
         constexpr int NCB = (M >= 128) ? 2 : 4;
