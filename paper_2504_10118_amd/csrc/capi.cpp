@@ -219,6 +219,7 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->pnum);
   dev_free(c->pden);
   dev_free(c->pmax);
+  dev_free(c->pacc);
   dev_free(c->perm);
   dev_free(c->posrec);
   dev_free(c->inv);
@@ -418,9 +419,12 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
   if (need_stage > c->stage_cap) {
     MG_HIP(hipStreamSynchronize(c->stream));
     dev_free(c->stage);
-  dev_free(c->pnum);
-  dev_free(c->pden);
-  dev_free(c->pmax);
+    // the probe-step partials are sized with the staging: reallocated on next use
+    dev_free(c->pnum);
+    dev_free(c->pden);
+    dev_free(c->pmax);
+    dev_free(c->pacc);
+    c->pcap = 0;
     rc = dev_alloc(&c->stage, need_stage);
     if (rc) {
       c->stage_cap = 0;
@@ -434,9 +438,11 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
     dev_free(c->pnum);
     dev_free(c->pden);
     dev_free(c->pmax);
+    dev_free(c->pacc);
     rc = dev_alloc(&c->pnum, need_stage);
     if (!rc) rc = dev_alloc(&c->pden, need_stage);
     if (!rc) rc = dev_alloc(&c->pmax, (size_t)B * mg::MAX_WAVES);
+    if (!rc) rc = dev_alloc(&c->pacc, mg::probe_scratch_doubles(m, B));
     if (rc) {
       c->pcap = 0;
       return rc;
@@ -560,7 +566,8 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   const int nw = mg::step_waves(m, c->rb);
   // probe step after a minibatch's accumulation: apply, then rebuild the hierarchy
   auto probe_tail = [&](int count) -> hipError_t {
-    hipError_t e = mg::launch_probe_apply(m, count, nw, c->pnum, c->pden, c->pmax, c->beta, c->q64, c->stream);
+    hipError_t e =
+        mg::launch_probe_apply(m, count, nw, c->pnum, c->pden, c->pmax, c->beta, c->q64, c->pacc, c->stream);
     if (e == hipSuccess)
       e = mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->w0f,
                                      c->u0f, c->qf, c->lvl, c->lvl_a_off, c->scr_q, c->scr_u, c->rb, c->qtab,

@@ -127,6 +127,7 @@ struct magpie_ctx {
   float2* pnum = nullptr;   // probe step partials (allocated with the staging when the flag is on)
   float* pden = nullptr;
   float* pmax = nullptr;
+  double* pacc = nullptr;   // probe step: per-chunk partial sums (mg::probe_scratch_doubles)
   size_t pcap = 0;
   int* perm = nullptr;   // [E][N]
   int4* posrec = nullptr;  // [E][N] (k, row, col, 0) in processing order

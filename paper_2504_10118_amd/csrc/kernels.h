@@ -95,9 +95,16 @@ hipError_t launch_reduce_parts(const double* parts, int n, int nw, int take_sqrt
 hipError_t launch_set_counter(int* counter, int value, hipStream_t s);
 hipError_t launch_advance_counter(int* counter, hipStream_t s);
 // Q += sum_s num_s / (sum_s den_s + beta sum_s max_s) where the denominator is
-// positive (FP64, slots in order); q64 is the FP64 master probe.
+// positive; q64 is the FP64 master probe.  Two passes: FP64 sums over fixed
+// chunks of PROBE_CHUNK slots (in slot order) into `scratch`, then the chunks in
+// order, so the result does not depend on the launch shape.
+constexpr int PROBE_CHUNK = 16;
+inline size_t probe_scratch_doubles(int m, int max_count) {
+  const size_t chunks = (size_t)(max_count + PROBE_CHUNK - 1) / PROBE_CHUNK;
+  return chunks * ((size_t)3 * m * m + 1);
+}
 hipError_t launch_probe_apply(int m, int count, int nwaves, const float2* num, const float* den,
-                              const float* pmax, double beta, double2* q64, hipStream_t s);
+                              const float* pmax, double beta, double2* q64, double* scratch, hipStream_t s);
 hipError_t launch_convert_c64_c128(const float2* src, double2* dst, size_t n, hipStream_t s);
 hipError_t launch_convert_c128_c64(const double2* src, float2* dst, size_t n, hipStream_t s);
 hipError_t launch_check_finite_c64(const float2* src, size_t n, int* bad_flag, hipStream_t s);

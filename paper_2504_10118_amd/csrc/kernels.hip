@@ -1376,35 +1376,71 @@ hipError_t launch_reduce_sum(const double* x, int n, double* out, hipStream_t s)
 
 // Probe step (beyond the paper; simultaneous with the object step): per pixel,
 // FP64 sums over the minibatch's slots in order.
-__global__ __launch_bounds__(256) void probe_apply_kernel(int mm, int count, int nwaves, const float2* num,
-                                                          const float* den, const float* pmax, double beta,
+// Pass 1: chunk c of PROBE_CHUNK slots; per pixel the FP64 sums of the probe
+// numerator and denominator in slot order, and per chunk (one thread) the sum
+// of the slots' largest |z_k|^2.  part: [chunk][3][mm], then [chunk] maxima.
+__global__ __launch_bounds__(256) void probe_partial_kernel(int mm, int count, int nwaves, const float2* num,
+                                                            const float* den, const float* pmax, double* part) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  const int s0 = c * PROBE_CHUNK, s1 = min(count, s0 + PROBE_CHUNK);
+  const int chunks = (count + PROBE_CHUNK - 1) / PROBE_CHUNK;
+  if (p < mm) {
+    double nr = 0.0, ni = 0.0, dd = 0.0;
+    for (int s = s0; s < s1; ++s) {
+      const float2 v = num[(size_t)s * mm + p];
+      nr += (double)v.x;
+      ni += (double)v.y;
+      dd += (double)den[(size_t)s * mm + p];
+    }
+    double* q = part + (size_t)c * 3 * mm;
+    q[p] = nr;
+    q[mm + p] = ni;
+    q[2 * mm + p] = dd;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int s = s0; s < s1; ++s) {
+      float w = 0.0f;
+      for (int j = 0; j < nwaves; ++j) w = fmaxf(w, pmax[(size_t)s * MAX_WAVES + j]);
+      mx += (double)w;
+    }
+    part[(size_t)chunks * 3 * mm + c] = mx;
+  }
+}
+
+// Pass 2: the chunks in order, then the probe step where the denominator is positive.
+__global__ __launch_bounds__(256) void probe_apply_kernel(int mm, int chunks, double beta, const double* part,
                                                           double2* q64) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= mm) return;
   double nr = 0.0, ni = 0.0, dd = 0.0, mx = 0.0;
-  for (int s = 0; s < count; ++s) {
-    const float2 c = num[(size_t)s * mm + p];
-    nr += (double)c.x;
-    ni += (double)c.y;
-    dd += (double)den[(size_t)s * mm + p];
-    float w = 0.0f;
-    for (int j = 0; j < nwaves; ++j) w = fmaxf(w, pmax[(size_t)s * MAX_WAVES + j]);
-    mx += (double)w;
+  for (int c = 0; c < chunks; ++c) {
+    const double* q = part + (size_t)c * 3 * mm;
+    nr += q[p];
+    ni += q[mm + p];
+    dd += q[2 * mm + p];
+    mx += part[(size_t)chunks * 3 * mm + c];
   }
   dd += beta * mx;
   if (dd > 0.0) {
-    double2 q = q64[p];
-    q.x += nr / dd;
-    q.y += ni / dd;
-    q64[p] = q;
+    double2 qq = q64[p];
+    qq.x += nr / dd;
+    qq.y += ni / dd;
+    q64[p] = qq;
   }
 }
 
 hipError_t launch_probe_apply(int m, int count, int nwaves, const float2* num, const float* den, const float* pmax,
-                              double beta, double2* q64, hipStream_t s) {
+                              double beta, double2* q64, double* scratch, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
   const int mm = m * m;
-  hipLaunchKernelGGL(probe_apply_kernel, dim3((mm + 255) / 256), dim3(256), 0, s, mm, count, nwaves, num, den,
-                     pmax, beta, q64);
+  const int chunks = (count + PROBE_CHUNK - 1) / PROBE_CHUNK;
+  hipLaunchKernelGGL(probe_partial_kernel, dim3((mm + 255) / 256, chunks), dim3(256), 0, s, mm, count, nwaves, num,
+                     den, pmax, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(probe_apply_kernel, dim3((mm + 255) / 256), dim3(256), 0, s, mm, chunks, beta, scratch, q64);
   return hipGetLastError();
 }
 

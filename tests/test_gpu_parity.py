@@ -299,6 +299,37 @@ def test_probe_update_parity(m, levels, batch, alternate):
         assert np.linalg.norm(Qsim - Qo) > 100 * 1e-5 * np.linalg.norm(Qo)
 
 
+def test_probe_buffers_follow_staging_growth():
+    """Probe step at a small minibatch, plain epoch at a larger one (the staging grows and
+    the probe buffers are released), probe step again at the small size: the buffers are
+    allocated anew and the run matches the oracle."""
+    from paper_2504_10118_amd import UPDATE_PROBE
+    rng = np.random.default_rng(23)
+    m = 16
+    c = Case(rng, 2 * m + 9, 2 * m + 4, m, 5, noise=0.05)
+    Q0 = (c.Q32 * (1 + 0.1 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))))).astype(np.complex64)
+    orders = [rng.permutation(c.n_pos).astype(np.int32) for _ in range(3)]
+    beta = 0.2
+    g = c.gpu(2, 0.5)
+    g.set_probe(Q0)
+    g.set_flags(UPDATE_PROBE, beta)
+    g.run_epochs(1, 4, order=orders[0][None])
+    g.set_flags(0)
+    g.run_epochs(1, c.n_pos, order=orders[1][None])
+    g.set_flags(UPDATE_PROBE, beta)
+    g.run_epochs(1, 4, order=orders[2][None])
+    zg = g.get_object().astype(np.complex128)
+    Qg = g.get_probe().astype(np.complex128)
+    g.close()
+    z1, Q1 = oracle.run_epochs_blind(c.z0, Q0.astype(np.complex128), c.offs, c.sd, 0.5, 2, [orders[0]], 4, beta)
+    z2 = oracle.run_epochs(z1, Q1, c.offs, c.sd, oracle.u_rpie(Q1, 0.5), 2, [orders[1]], c.n_pos)
+    zo, Qo = oracle.run_epochs_blind(z2, Q1, c.offs, c.sd, 0.5, 2, [orders[2]], 4, beta)
+    rz = c.rel(zg, zo)
+    rq = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo)
+    _print("probe buffers after staging growth: object rel", rz, "probe rel", rq)
+    assert rz <= 1e-4 and rq <= 1e-4
+
+
 def test_probe_alternate_needs_probe_update():
     from paper_2504_10118_amd import PROBE_ALTERNATE, MagpieError
     rng = np.random.default_rng(19)
