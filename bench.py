@@ -45,9 +45,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(cfg_id: int, m: int):
+def stored_traffic(cfg_id: int, m: int, rb: int):
     """Counter-measured HBM bytes per full launch of the step kernel, from the
-    committed rocprofv3 summary, if it was taken on the current sources."""
+    committed rocprofv3 summary, if it was taken on the current sources with the
+    same FFT plan (threads per transform rb)."""
     path = os.path.join(ROOT, "profiles", f"step_kernel_m{m}_cfg{cfg_id}.md")
     if not os.path.exists(path):
         return None
@@ -56,10 +57,10 @@ def stored_traffic(cfg_id: int, m: int):
         for line in f:
             if ":" in line and line.strip().startswith(("source_sha256", "traffic_bytes_per_launch",
                                                          "traffic_fetch_bytes", "traffic_write_bytes",
-                                                         "patterns_per_launch")):
+                                                         "patterns_per_launch", "plan_threads_per_transform")):
                 k, v = line.strip().split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != kernel_source_hash():
+    if vals.get("source_sha256") != kernel_source_hash() or vals.get("plan_threads_per_transform") != str(rb):
         return None
     try:
         return {"bytes_per_full_launch": float(vals["traffic_bytes_per_launch"]),
@@ -297,6 +298,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT plan and tile height")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="RB,TH: use this FFT plan (threads per transform) and tile height instead of the autotuner")
     ap.add_argument("--race-objects", type=int, default=4,
                     help="held-out objects of the learned-vs-plain time-to-1e-3 race (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -342,7 +345,11 @@ def main():
     ctx.load_intensities(d, is_sqrt=False)
     ctx.set_object(np.ones((cfg.n, cfg.n), dtype=np.complex64))
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        rb, th = (int(x) for x in args.tuning.split(","))
+        ctx.set_tuning(rb, th)
+        tuning = {"threads_per_transform": rb, "tile_rows": th, "source": "--tuning"}
+    elif not args.no_autotune:
         rb, th, su, au = ctx.autotune(batch)             # the library's own autotuner, on this data
         tuning = {"threads_per_transform": rb, "tile_rows": th, "trial_step_us": su, "trial_accumulate_us": au}
     if args.warmup:
@@ -370,7 +377,7 @@ def main():
     ctx.run_epochs(args.steps, batch, seed=args.seed)
     tm = ctx.get_timing()                                    # synchronises
     t3 = time.perf_counter()
-    ctx_tile_rows = ctx.get_tuning()[1]
+    ctx_rb, ctx_tile_rows = ctx.get_tuning()
     ctx.close()
 
     wall = t1 - t0
@@ -381,7 +388,7 @@ def main():
     achieved = tm["positions"] * bytes_per_pattern / step_s / 1e9 if step_s > 0 else None
     th_used = ctx_tile_rows
     n_tiles = ((cfg.n + 63) // 64) * ((cfg.n + th_used - 1) // th_used)
-    traffic = stored_traffic(args.config, m) if batch == cfg.batch and levels == cfg.levels else None
+    traffic = stored_traffic(args.config, m, ctx_rb) if batch == cfg.batch and levels == cfg.levels else None
     out = {
         "metric": "diffraction patterns/s (fused step)",
         "value": value,
@@ -403,7 +410,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"step_kernel<{m}, MODE_STEP>",
+            "kernel": f"step_kernel<{m}, {ctx_rb}, MODE_STEP>",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -240,8 +240,9 @@ int magpie_get_tuning(magpie_ctx* ctx, int* threads_per_transform, int* tile_row
 /*
  * Autotuner: times trial_epochs epochs of minibatch size `batch` with every
  * compiled FFT plan (step kernel) and then every tile height (accumulation
- * kernel), keeps the fastest of each, and restores the object and the epoch
- * counter (the trials' updates are discarded).  Outputs (nullable): mean
+ * kernel), each after one untimed epoch of the same variant, keeps the fastest
+ * of each, and restores the object and the epoch counter (the trials' updates
+ * are discarded).  Outputs (nullable): mean
  * per-launch times in microseconds of the chosen variants.
  * Errors: BAD_STATE, INVALID_ARG, HIP.
  */

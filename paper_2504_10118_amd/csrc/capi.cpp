@@ -931,7 +931,11 @@ int magpie_autotune(magpie_ctx* c, int batch, int trial_epochs, double* step_us,
   auto trial = [&](double* s_us, double* a_us) -> int {
     double s1, a1;
     int64_t sl, al, np;
-    int r = magpie_get_timing(c, &s1, &a1, &sl, &al, &np);   // reset
+    // one untimed epoch first: a kernel's first launch also loads its code
+    c->timing = false;
+    int r = magpie_run_epochs(c, 1, batch, 0x5eedull, nullptr);
+    c->timing = true;
+    if (!r) r = magpie_get_timing(c, &s1, &a1, &sl, &al, &np);   // reset
     if (!r) r = magpie_run_epochs(c, trial_epochs, batch, 0x5eedull, nullptr);
     if (!r) r = magpie_get_timing(c, &s1, &a1, &sl, &al, &np);
     if (!r) {
