@@ -418,6 +418,7 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
   const size_t need_stage = (size_t)B * m * m;
   if (need_stage > c->stage_cap) {
     MG_HIP(hipStreamSynchronize(c->stream));
+    drop_graph(c);   // a captured epoch holds the old buffers' addresses
     dev_free(c->stage);
     // the probe-step partials are sized with the staging: reallocated on next use
     dev_free(c->pnum);
@@ -435,6 +436,7 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
   const bool probe_step = (c->flags & MAGPIE_UPDATE_PROBE) != 0;
   if (probe_step && need_stage > c->pcap) {
     MG_HIP(hipStreamSynchronize(c->stream));
+    drop_graph(c);
     dev_free(c->pnum);
     dev_free(c->pden);
     dev_free(c->pmax);
@@ -452,6 +454,7 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
   const size_t nperm = (size_t)n_epochs * N;
   if (nperm > c->perm_cap) {
     MG_HIP(hipStreamSynchronize(c->stream));
+    drop_graph(c);
     dev_free(c->perm);
     dev_free(c->posrec);
     dev_free(c->inv);

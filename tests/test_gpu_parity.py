@@ -267,6 +267,30 @@ def test_graph_replays_match_direct_launches():
     assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
 
 
+def test_graph_replays_with_probe_steps_and_phase_store():
+    """The same with the probe step (alternating), the phase store, and buffers that grow
+    between calls (a larger minibatch, more epochs per call): every captured epoch is
+    dropped with the buffers it was built on."""
+    from paper_2504_10118_amd import GRAPH, PHASE_RECYCLE, PROBE_ALTERNATE, UPDATE_PROBE
+    rng = np.random.default_rng(24)
+    c = Case(rng, 120, 110, 16, 5, noise=0.05)
+    base = UPDATE_PROBE | PROBE_ALTERNATE | PHASE_RECYCLE
+    outs = []
+    for flags in (GRAPH | base, base):
+        g = c.gpu(2, 0.5)
+        g.set_flags(flags, 0.3)
+        g.run_epochs(2, 16, seed=5)
+        g.objective()
+        g.run_epochs(1, 60, seed=5)        # the staging and the probe buffers grow
+        g.run_epochs(4, 16, seed=5)        # the permutation buffers grow
+        _ = g.get_object()
+        g.run_epochs(1, 16, seed=5)
+        outs.append((g.get_object(), g.get_probe()))
+        g.close()
+    assert np.array_equal(outs[0][0].view(np.uint64), outs[1][0].view(np.uint64))
+    assert np.array_equal(outs[0][1].view(np.uint64), outs[1][1].view(np.uint64))
+
+
 @pytest.mark.parametrize("alternate", [False, True])
 @pytest.mark.parametrize("m,levels,batch", [(16, 3, 6), (64, 3, 5), (128, 2, 4)])
 def test_probe_update_parity(m, levels, batch, alternate):
