@@ -1061,12 +1061,19 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
   // descriptors for every round: step args per plan group, accum args per tile group
   std::vector<mg::StepArgs> hs((size_t)R * count);
   std::vector<mg::AccumArgs> ha((size_t)R * count);
-  std::vector<int> s_max((size_t)R * sgroups.size(), 0), a_max((size_t)R * agroups.size(), 0);
+  // per round and group: running totals of the members' positions (step) or
+  // tiles (accumulation), n_members + 1 ints each, consecutive in hp
+  size_t s_pre = 0, a_pre = 0;
+  for (auto& g : sgroups) s_pre += g.members.size() + 1;
+  for (auto& g : agroups) a_pre += g.members.size() + 1;
+  std::vector<int> hp((size_t)R * (s_pre + a_pre), 0);
+  auto s_prefix = [&](int r, size_t gi_off) { return (size_t)r * (s_pre + a_pre) + gi_off; };
+  auto a_prefix = [&](int r, size_t gi_off) { return (size_t)r * (s_pre + a_pre) + s_pre + gi_off; };
   for (int r = 0; r < R; ++r) {
     size_t base = (size_t)r * count;
-    int gi = 0;
-    size_t off = 0;
+    size_t off = 0, poff = 0;
     for (auto& g : sgroups) {
+      int* pre = hp.data() + s_prefix(r, poff);
       for (size_t j = 0; j < g.members.size(); ++j) {
         const int i = g.members[j];
         magpie_ctx* c = ctxs[i];
@@ -1091,15 +1098,16 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
         } else {
           a.count = 0;
         }
-        s_max[(size_t)r * sgroups.size() + gi] = std::max(s_max[(size_t)r * sgroups.size() + gi], a.count);
+        pre[j + 1] = pre[j] + a.count;
         hs[base + off + j] = a;
       }
       off += g.members.size();
-      ++gi;
+      poff += g.members.size() + 1;
     }
-    gi = 0;
     off = 0;
+    poff = 0;
     for (auto& g : agroups) {
+      int* pre = hp.data() + a_prefix(r, poff);
       for (size_t j = 0; j < g.members.size(); ++j) {
         const int i = g.members[j];
         magpie_ctx* c = ctxs[i];
@@ -1124,47 +1132,54 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
           a.inv = c->inv;
           a.n_tiles = 0;
         }
-        a_max[(size_t)r * agroups.size() + gi] = std::max(a_max[(size_t)r * agroups.size() + gi], a.n_tiles);
+        pre[j + 1] = pre[j] + a.n_tiles;
         ha[base + off + j] = a;
       }
       off += g.members.size();
-      ++gi;
+      poff += g.members.size() + 1;
     }
   }
   mg::StepArgs* ds = nullptr;
   mg::AccumArgs* da = nullptr;
+  int* dp = nullptr;
   rc = dev_alloc(&ds, hs.size());
   if (!rc) rc = dev_alloc(&da, ha.size());
+  if (!rc) rc = dev_alloc(&dp, hp.size());
   hipError_t e = hipSuccess;
   if (!rc) e = hipMemcpyAsync(ds, hs.data(), hs.size() * sizeof(mg::StepArgs), hipMemcpyHostToDevice, st);
   if (!rc && e == hipSuccess)
     e = hipMemcpyAsync(da, ha.data(), ha.size() * sizeof(mg::AccumArgs), hipMemcpyHostToDevice, st);
+  if (!rc && e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(int), hipMemcpyHostToDevice, st);
   for (int r = 0; r < R && !rc && e == hipSuccess; ++r) {
-    size_t off = 0;
+    size_t off = 0, poff = 0;
     for (size_t gi = 0; gi < sgroups.size() && e == hipSuccess; ++gi) {
       const auto& g = sgroups[gi];
-      int npat = 0;
-      for (size_t j = 0; j < g.members.size(); ++j) npat += hs[(size_t)r * count + off + j].count;
+      const int nm = (int)g.members.size();
+      const int npat = hp[s_prefix(r, poff) + nm];
       const int ti = (npat > 0) ? timed_slot(c0, 0, npat) : -1;
-      e = mg::launch_step_multi(g.m, g.rb, ds + (size_t)r * count + off, (int)g.members.size(),
-                                s_max[(size_t)r * sgroups.size() + gi], st, ti >= 0 ? c0->timed[ti].a : nullptr,
-                                ti >= 0 ? c0->timed[ti].b : nullptr);
+      e = mg::launch_step_multi(g.m, g.rb, ds + (size_t)r * count + off, dp + s_prefix(r, poff), nm, npat, st,
+                                ti >= 0 ? c0->timed[ti].a : nullptr, ti >= 0 ? c0->timed[ti].b : nullptr);
       off += g.members.size();
+      poff += g.members.size() + 1;
     }
     off = 0;
+    poff = 0;
     for (size_t gi = 0; gi < agroups.size() && e == hipSuccess; ++gi) {
       const auto& g = agroups[gi];
-      const int ti = (a_max[(size_t)r * agroups.size() + gi] > 0) ? timed_slot(c0, 1, 0) : -1;
-      e = mg::launch_accumulate_multi(g.m, da + (size_t)r * count + off, (int)g.members.size(),
-                                      a_max[(size_t)r * agroups.size() + gi], st, ti >= 0 ? c0->timed[ti].a : nullptr,
-                                      ti >= 0 ? c0->timed[ti].b : nullptr);
+      const int nm = (int)g.members.size();
+      const int ntile = hp[a_prefix(r, poff) + nm];
+      const int ti = (ntile > 0) ? timed_slot(c0, 1, 0) : -1;
+      e = mg::launch_accumulate_multi(g.m, da + (size_t)r * count + off, dp + a_prefix(r, poff), nm, ntile, st,
+                                      ti >= 0 ? c0->timed[ti].a : nullptr, ti >= 0 ? c0->timed[ti].b : nullptr);
       off += g.members.size();
+      poff += g.members.size() + 1;
     }
   }
   // the descriptor buffers are freed once the launches that read them are done
   if (e == hipSuccess && !rc) e = hipStreamSynchronize(st);
   dev_free(ds);
   dev_free(da);
+  dev_free(dp);
   if (!rc && e != hipSuccess) rc = fail(MAGPIE_ERR_HIP, std::string("multi-context run: ") + hipGetErrorString(e));
   for (int i = 1; i < count && !rc; ++i) rc = join(st, ctxs[i]->stream);
   cleanup();

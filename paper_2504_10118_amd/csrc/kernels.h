@@ -75,12 +75,14 @@ hipError_t launch_step(int m, int rb, int mode, const StepArgs& a, hipStream_t s
                        hipEvent_t ev1 = nullptr);
 hipError_t launch_accumulate(const AccumArgs& a, int th, int n_tiles, hipStream_t s, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);
-// one launch over several contexts: grid (max_count | max_tiles) x n_ctx,
-// descriptor y describes context y for this round (count / n_tiles 0 = idle)
-hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s,
-                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s,
-                                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// One launch over several contexts: descriptor j describes context j for this
+// round; prefix (device, n_ctx + 1 ints) holds the running totals of the
+// contexts' positions (step) or tiles (accumulation), prefix[0] = 0 and
+// prefix[n_ctx] = total = the number of workgroups (contexts with none: idle).
+hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, const int* prefix, int n_ctx, int total,
+                             hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, const int* prefix, int n_ctx, int total,
+                                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given,
                                   const double2* q64, double* u0, double* w0, float* w0f, float* u0f,
                                   float2* qf, double* lvl, int lvl_a_off, double2* scr_q, double* scr_u, int rb,

@@ -815,13 +815,27 @@ __global__ __launch_bounds__(M * RBv) void step_kernel(StepArgs a) {
   step_body<M, RBv, MODE>(a, (int)blockIdx.x);
 }
 
-// Many reconstructions in one launch: blockIdx.y selects a context's arguments
-// for this round (descs), blockIdx.x a position of its minibatch.
+// Many reconstructions in one launch: workgroup b belongs to the context j with
+// prefix[j] <= b < prefix[j + 1] (prefix: running totals of the contexts' work
+// items for this round, so contexts with none take no workgroups), and does its
+// item b - prefix[j].  The search is uniform across the workgroup.
+__device__ __forceinline__ int owner_of(const int* __restrict__ prefix, int n_ctx, int b) {
+  int lo = 0, hi = n_ctx;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 template <int M, int RBv>
-__global__ __launch_bounds__(M * RBv) void step_multi_kernel(const StepArgs* __restrict__ descs) {
-  const StepArgs a = load_step_args(descs + blockIdx.y);
-  if ((int)blockIdx.x >= a.count) return;
-  step_body<M, RBv, MODE_STEP>(a, (int)blockIdx.x);
+__global__ __launch_bounds__(M * RBv) void step_multi_kernel(const StepArgs* __restrict__ descs,
+                                                             const int* __restrict__ prefix, int n_ctx) {
+  const int b = (int)blockIdx.x;
+  const int j = owner_of(prefix, n_ctx, b);
+  const StepArgs a = load_step_args(descs + j);
+  step_body<M, RBv, MODE_STEP>(a, b - prefix[j]);
 }
 
 template <int M, int RB>
@@ -1030,10 +1044,12 @@ __global__ __launch_bounds__(ACC_THREADS) void accumulate_kernel(AccumArgs a) {
 }
 
 template <int TH>
-__global__ __launch_bounds__(ACC_THREADS) void accumulate_multi_kernel(const AccumArgs* __restrict__ descs) {
-  const AccumArgs a = load_accum_args(descs + blockIdx.y);
-  if ((int)blockIdx.x >= a.n_tiles) return;
-  accumulate_body<TH>(a, (int)blockIdx.x);
+__global__ __launch_bounds__(ACC_THREADS) void accumulate_multi_kernel(const AccumArgs* __restrict__ descs,
+                                                                       const int* __restrict__ prefix, int n_ctx) {
+  const int b = (int)blockIdx.x;
+  const int j = owner_of(prefix, n_ctx, b);
+  const AccumArgs a = load_accum_args(descs + j);
+  accumulate_body<TH>(a, b - prefix[j]);
 }
 
 template <int TH>
@@ -1046,9 +1062,9 @@ static void launch_accumulate_t(const AccumArgs& a, int n_tiles, hipStream_t s, 
 
 bool tile_valid(int th) { return th == 4 || th == 8 || th == 16 || th == 32; }
 
-hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, int max_count, hipStream_t s,
-                             hipEvent_t ev0, hipEvent_t ev1) {
-  if (n_ctx <= 0 || max_count <= 0) return hipSuccess;
+hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, const int* prefix, int n_ctx, int total,
+                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (n_ctx <= 0 || total <= 0) return hipSuccess;
 #define MG_LM(MM, RR)                                                                                   \
   if (m == MM && rb == RR) {                                                                            \
     const size_t lds = lds_bytes_m<MM, RR>();                                                           \
@@ -1056,10 +1072,10 @@ hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, in
                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     if (fe != hipSuccess) return fe;                                                                    \
     if (ev0)                                                                                            \
-      hipExtLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(max_count, n_ctx), dim3(MM * RR), lds, s, \
-                            ev0, ev1, 0, descs);                                                        \
+      hipExtLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(total), dim3(MM * RR), lds, s, ev0, ev1, 0, \
+                            descs, prefix, n_ctx);                                                      \
     else                                                                                                \
-      hipLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(max_count, n_ctx), dim3(MM * RR), lds, s, descs); \
+      hipLaunchKernelGGL((step_multi_kernel<MM, RR>), dim3(total), dim3(MM * RR), lds, s, descs, prefix, n_ctx); \
     return hipGetLastError();                                                                           \
   }
   MG_FOR_EACH_PLAN(MG_LM)
@@ -1068,23 +1084,23 @@ hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, int n_ctx, in
 }
 
 template <int TH>
-static void launch_acc_multi_t(const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s, hipEvent_t ev0,
-                               hipEvent_t ev1) {
+static void launch_acc_multi_t(const AccumArgs* descs, const int* prefix, int n_ctx, int total, hipStream_t s,
+                               hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0)
-    hipExtLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, ev0, ev1,
-                          0, descs);
+    hipExtLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(total), dim3(ACC_THREADS), 0, s, ev0, ev1, 0, descs,
+                          prefix, n_ctx);
   else
-    hipLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(max_tiles, n_ctx), dim3(ACC_THREADS), 0, s, descs);
+    hipLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(total), dim3(ACC_THREADS), 0, s, descs, prefix, n_ctx);
 }
 
-hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, int n_ctx, int max_tiles, hipStream_t s,
-                                   hipEvent_t ev0, hipEvent_t ev1) {
-  if (n_ctx <= 0 || max_tiles <= 0) return hipSuccess;
+hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, const int* prefix, int n_ctx, int total,
+                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (n_ctx <= 0 || total <= 0) return hipSuccess;
   switch (th) {
-    case 4: launch_acc_multi_t<4>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
-    case 8: launch_acc_multi_t<8>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
-    case 16: launch_acc_multi_t<16>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
-    case 32: launch_acc_multi_t<32>(descs, n_ctx, max_tiles, s, ev0, ev1); break;
+    case 4: launch_acc_multi_t<4>(descs, prefix, n_ctx, total, s, ev0, ev1); break;
+    case 8: launch_acc_multi_t<8>(descs, prefix, n_ctx, total, s, ev0, ev1); break;
+    case 16: launch_acc_multi_t<16>(descs, prefix, n_ctx, total, s, ev0, ev1); break;
+    case 32: launch_acc_multi_t<32>(descs, prefix, n_ctx, total, s, ev0, ev1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
