@@ -142,6 +142,8 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   c->rb = mg::default_plan(m);
   int rc = set_dev(c);
   if (rc) { delete c; return rc; }
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
+    c->n_cu = 256;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -541,6 +543,9 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   sa.lvl_a_off = c->lvl_a_off;
   sa.phi_part = c->step_part;
   sa.phase = (c->flags & MAGPIE_PHASE_RECYCLE) ? c->phase : nullptr;
+  // a minibatch that fits in one workgroup per compute unit: stage with device
+  // scope (see StepArgs::stage_wt)
+  sa.stage_wt = (B <= c->n_cu) ? 1 : 0;
   if (probe_step) {
     sa.probe_num = c->pnum;
     sa.probe_den = c->pden;

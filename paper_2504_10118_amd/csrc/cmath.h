@@ -211,12 +211,22 @@ __device__ __forceinline__ float4 bload4(rsrc_t r, int voff, int soff) {
 // store device scope, i.e. written through this XCD's L2.
 constexpr int kPolicyDeviceScope = 0x10;
 
+__device__ __forceinline__ void bstore2(rsrc_t r, float2 v, int voff, int soff) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
 // Store for data the next kernel reads on other XCDs (the staged updates): with
 // device scope it leaves no dirty L2 lines to be written back when the kernel
-// ends (measured: -1.6 us per 256-pattern launch at m = 64, -1 us at m = 128).
+// ends (measured: -1.6 us per 256-pattern launch at m = 64, -1 us at m = 128),
+// but in launches of many workgroups per CU the write-through costs more than
+// the write-back it saves (+6 % on 16 k-workgroup launches).
 __device__ __forceinline__ void bstore2_device(rsrc_t r, float2 v, int voff, int soff) {
   typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, kPolicyDeviceScope);
+}
+__device__ __forceinline__ void bstore2_stage(rsrc_t r, float2 v, int voff, int soff, bool device_scope) {
+  if (device_scope) bstore2_device(r, v, voff, soff);
+  else bstore2(r, v, voff, soff);
 }
 
 }  // namespace mg

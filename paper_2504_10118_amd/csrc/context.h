@@ -78,6 +78,7 @@ inline void fisher_yates(uint64_t seed, uint64_t epoch, int n, int32_t* out) {
 
 struct magpie_ctx {
   int device = 0;
+  int n_cu = 256;   // compute units of the device
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int nr = 0, nc = 0, m = 0, L = 1;

@@ -38,6 +38,8 @@ struct StepArgs {
   float* probe_den;       // probe step: |z_k|^2 per position [count][m][m]
   float* probe_max;       // probe step: per-wave max |z_k|^2 [count][MAX_WAVES]
   float2* phase;          // MODE_STEP, nullable: eq. (3.2) phase store [N][m][m] natural order
+  int stage_wt;           // MODE_STEP: store the staged updates with device scope (written through
+                          // L2): faster when the launch is one workgroup per CU, slower for large launches
 };
 
 struct AccumArgs {

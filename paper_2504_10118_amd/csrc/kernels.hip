@@ -156,6 +156,7 @@ __device__ __forceinline__ StepArgs load_step_args(const StepArgs* p) {
   a.probe_den = d->probe_den;
   a.probe_max = d->probe_max;
   a.phase = nullptr;   // multi-context runs do not recycle phases
+  a.stage_wt = 0;      // ... and stage through L2 (their launches are large)
   return a;
 }
 
@@ -284,8 +285,8 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     const int y = RB * n1 + g;
     const double2 e1 = C[(y >> 1) * M1 + (col >> 1)];
     const double uu = (double)a.u0f[y * M + col];
-    bstore2_device(outr, make_float2((float)(uu * e1.x - (double)v[n1].x), (float)(uu * e1.y - (double)v[n1].y)),
-                   (y * M + col) * (int)sizeof(float2), 0);
+    bstore2_stage(outr, make_float2((float)(uu * e1.x - (double)v[n1].x), (float)(uu * e1.y - (double)v[n1].y)),
+                  (y * M + col) * (int)sizeof(float2), 0, a.stage_wt != 0);
   }
 }
 
@@ -701,7 +702,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       const int L = a.levels;
       if (L <= 1) {
 #pragma unroll
-        for (int n1 = 0; n1 < RA; ++n1) bstore2_device(outr, make_float2(-v[n1].x, -v[n1].y), ovo, n1 * qso);
+        for (int n1 = 0; n1 < RA; ++n1)
+          bstore2_stage(outr, make_float2(-v[n1].x, -v[n1].y), ovo, n1 * qso, a.stage_wt != 0);
         return;
       }
       if (L - 1 <= LWI) {
@@ -793,10 +795,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
             double uu;
             if constexpr (KEEP) uu = (double)u0k[n0 + i];
             else uu = (double)ut[(n0 + i) * TPB];
-            bstore2_device(outr,
-                    make_float2((float)(uu * e1[i].x - (double)v[n0 + i].x),
-                                (float)(uu * e1[i].y - (double)v[n0 + i].y)),
-                    ovo, (n0 + i) * qso);
+            bstore2_stage(outr,
+                          make_float2((float)(uu * e1[i].x - (double)v[n0 + i].x),
+                                      (float)(uu * e1[i].y - (double)v[n0 + i].y)),
+                          ovo, (n0 + i) * qso, a.stage_wt != 0);
           }
         }
         return;
