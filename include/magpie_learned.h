@@ -4,9 +4,9 @@
  *
  * The paper leaves the initial guess of Alg 4 unspecified (a flat start is
  * the plain method).  This interface adds a starting guess predicted by a
- * small convolutional network; the plain method stays the fallback and the
- * judge of the guess (magpie_learned_start keeps whichever start has the
- * lower objective, eq. 2.1).
+ * small convolutional network; the plain method stays the fallback and
+ * decides whether the guess is used (magpie_learned_start keeps whichever
+ * start has the lower objective, eq. 2.1).
  *
  * Network (fixed architecture, width W = 32): five 3x3 convolutions with zero
  * padding 1: Cin -> W, ReLU, W -> W, ReLU, nearest 2x upsampling, W -> W, ReLU,
