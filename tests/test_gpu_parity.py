@@ -267,6 +267,30 @@ def test_graph_replays_match_direct_launches():
     assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
 
 
+@pytest.mark.parametrize("m,levels,flags_name", [(64, 3, "plain"), (64, 3, "recycle"), (128, 2, "plain")])
+def test_every_graph_replay_matches_direct_launches(m, levels, flags_name):
+    """Each replay of a captured epoch, with the program's own eager work and
+    synchronisations between replays, equals the same epoch launched directly, bit for
+    bit, checked after every replay (not only at the end)."""
+    from paper_2504_10118_amd import GRAPH, PHASE_RECYCLE
+    extra = PHASE_RECYCLE if flags_name == "recycle" else 0
+    rng = np.random.default_rng(34 + m)
+    c = Case(rng, 2 * m + 40, 2 * m + 30, m, max(5, m // 6), noise=0.05)
+    gg, gd = c.gpu(levels, 0.5), c.gpu(levels, 0.5)
+    gg.set_flags(GRAPH | extra)
+    gd.set_flags(extra)
+    batch = max(3, c.n_pos // 5)
+    for i in range(5):
+        gg.run_epochs(1, batch, seed=7)
+        gd.run_epochs(1, batch, seed=7)
+        zg, zd = gg.get_object(), gd.get_object()        # synchronises
+        assert np.array_equal(zg.view(np.uint64), zd.view(np.uint64)), f"replay {i}"
+        pg, pd = gg.objective(), gd.objective()          # eager kernels between replays
+        assert pg == pd
+    gg.close()
+    gd.close()
+
+
 def test_graph_replays_with_probe_steps_and_phase_store():
     """The same with the probe step (alternating), the phase store, and buffers that grow
     between calls (a larger minibatch, more epochs per call): every captured epoch is
