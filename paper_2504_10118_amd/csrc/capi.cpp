@@ -933,8 +933,7 @@ int magpie_autotune(magpie_ctx* c, int batch, int trial_epochs, double* step_us,
   // trials leave the probe and the phase store alone
   c->flags = flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_PHASE_RECYCLE | MAGPIE_PROBE_ALTERNATE);
   c->timing = true;
-  double* sm = nullptr;
-  double am = 0.0, best_step = 1e300, best_acc = 1e300;
+  double best_step = 1e300, best_acc = 1e300;
   int best_rb = c->rb, best_th = c->th;
   auto trial = [&](double* s_us, double* a_us) -> int {
     double s1, a1;
@@ -952,8 +951,6 @@ int magpie_autotune(magpie_ctx* c, int batch, int trial_epochs, double* step_us,
     }
     return r;
   };
-  (void)sm;
-  (void)am;
   int rbs[8];
   const int nplans = mg::plans_for(c->m, rbs, 8);
   for (int i = 0; i < nplans && !rc; ++i) {
