@@ -143,48 +143,69 @@ MG_HD void dft(float2* v) {
 namespace mg {
 
 // Value of the lane whose id differs from this lane's in bit MASK (a power of
-// two below 64).  Masks 1, 2 and 8 use DPP (quad_perm, row_ror:8), 4 and 16
-// ds_swizzle in bit-mask mode; 32 crosses the half-waves with ds_bpermute.
-template <int MASK>
+// two below 64).  Masks 1 and 2 are DPP quad_perm, 8 is DPP row_ror:8.  The
+// others come in two forms:
+//   VALU = true: VALU cross-lane operations only, for latency-bound kernels
+//     with few waves per SIMD (the LDS-pipe round trips of the other form sit
+//     on their critical path): 4 selects between row_ror:12 and row_ror:4
+//     (row_ror:N gives lane l the value of lane l - N of its 16-lane row, mod
+//     16: N = 12 reads lane l + 4, the partner of lanes with bit 2 clear, N = 4
+//     reads lane l - 4, the partner of the others); 16 and 32 use gfx950's
+//     v_permlane16_swap / v_permlane32_swap of the value with itself, which give
+//     (row 0, row 0, row 2, row 2) and (row 1, row 1, row 3, row 3) for 16-lane
+//     rows (halves 0, 0 and 1, 1 for 32), so the partner's value is the first
+//     result in odd rows (halves) and the second in even ones;
+//   VALU = false: ds_swizzle (4, 16) and ds_bpermute (32) in the LDS pipe, which
+//     cost no VALU issue slots where enough waves hide their latency.
+template <int MASK, bool VALU = true>
 __device__ __forceinline__ int xor_lane(int v) {
   static_assert(MASK > 0 && MASK < 64 && (MASK & (MASK - 1)) == 0, "power of two below 64");
   if constexpr (MASK == 1) {
     return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
   } else if constexpr (MASK == 2) {
     return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-  } else if constexpr (MASK == 4) {
-    return __builtin_amdgcn_ds_swizzle(v, 0x101F);                      // and 0x1f, xor 4
   } else if constexpr (MASK == 8) {
     return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (!VALU) {
+    if constexpr (MASK == 4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);    // and 0x1f, xor 4
+    else if constexpr (MASK == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // and 0x1f, xor 16
+    else return __shfl_xor(v, MASK);
+  } else if constexpr (MASK == 4) {
+    const int r4 = __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);    // row_ror:4
+    const int r12 = __builtin_amdgcn_update_dpp(0, v, 0x12C, 0xF, 0xF, false);   // row_ror:12
+    return (__lane_id() & 4) ? r4 : r12;
   } else if constexpr (MASK == 16) {
-    return __builtin_amdgcn_ds_swizzle(v, 0x401F);                      // and 0x1f, xor 16
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (__lane_id() & 16) ? (int)r[0] : (int)r[1];
   } else {
-    return __shfl_xor(v, MASK);
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (__lane_id() & 32) ? (int)r[0] : (int)r[1];
   }
 }
 
-template <int MASK>
+template <int MASK, bool VALU = true>
 __device__ __forceinline__ double xor_lane(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = xor_lane<MASK>((int)(b & 0xffffffffll));
-  const int hi = xor_lane<MASK>((int)(b >> 32));
+  const int lo = xor_lane<MASK, VALU>((int)(b & 0xffffffffll));
+  const int hi = xor_lane<MASK, VALU>((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int MASK>
+template <int MASK, bool VALU = true>
 __device__ __forceinline__ double2 xor_lane(double2 v) {
-  return make_double2(xor_lane<MASK>(v.x), xor_lane<MASK>(v.y));
+  return make_double2(xor_lane<MASK, VALU>(v.x), xor_lane<MASK, VALU>(v.y));
 }
 
 // Runtime mask dispatch (the mask is uniform and comes from a small set).
+template <bool VALU = true>
 __device__ __forceinline__ double2 xor_lane_rt(double2 v, int mask) {
   switch (mask) {
-    case 1: return xor_lane<1>(v);
-    case 2: return xor_lane<2>(v);
-    case 4: return xor_lane<4>(v);
-    case 8: return xor_lane<8>(v);
-    case 16: return xor_lane<16>(v);
-    default: return xor_lane<32>(v);
+    case 1: return xor_lane<1, VALU>(v);
+    case 2: return xor_lane<2, VALU>(v);
+    case 4: return xor_lane<4, VALU>(v);
+    case 8: return xor_lane<8, VALU>(v);
+    case 16: return xor_lane<16, VALU>(v);
+    default: return xor_lane<32, VALU>(v);
   }
 }
 

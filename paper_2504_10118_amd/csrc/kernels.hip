@@ -190,18 +190,31 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum over the lanes of one wave (LANES active lanes), fixed order.
-template <int LANES>
+// Sum over the lanes of one wave (LANES active lanes, a power of two), fixed
+// order: butterflies over lane distances LANES / 2, ..., 1 (VALU: which form of
+// the cross-lane exchange, see xor_lane).
+template <int LANES, bool VALU>
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LANES);
+  if constexpr (LANES >= 64) v += xor_lane<32, VALU>(v);
+  if constexpr (LANES >= 32) v += xor_lane<16, VALU>(v);
+  if constexpr (LANES >= 16) v += xor_lane<8, VALU>(v);
+  if constexpr (LANES >= 8) v += xor_lane<4, VALU>(v);
+  if constexpr (LANES >= 4) v += xor_lane<2, VALU>(v);
+  if constexpr (LANES >= 2) v += xor_lane<1, VALU>(v);
   return v;
 }
 
-template <int LANES>
+template <int LANES, bool VALU>
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = LANES / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, LANES));
+  auto x = [](float a, auto mask) {
+    return __int_as_float(xor_lane<decltype(mask)::value, VALU>(__float_as_int(a)));
+  };
+  if constexpr (LANES >= 64) v = fmaxf(v, x(v, std::integral_constant<int, 32>{}));
+  if constexpr (LANES >= 32) v = fmaxf(v, x(v, std::integral_constant<int, 16>{}));
+  if constexpr (LANES >= 16) v = fmaxf(v, x(v, std::integral_constant<int, 8>{}));
+  if constexpr (LANES >= 8) v = fmaxf(v, x(v, std::integral_constant<int, 4>{}));
+  if constexpr (LANES >= 4) v = fmaxf(v, x(v, std::integral_constant<int, 2>{}));
+  if constexpr (LANES >= 2) v = fmaxf(v, x(v, std::integral_constant<int, 1>{}));
   return v;
 }
 
@@ -306,6 +319,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr int LRB = ilog2c(RB), LW = ilog2c(CPW);
   constexpr int LWI = inwave_levels(M, P, LW);   // coarse levels handled inside the wave
   constexpr int NW = (TPB + 63) / 64;
+  // cross-lane exchanges in VALU form while the plan runs few waves per SIMD
+  // (up to 512 threads), in the LDS pipe for the 1024-thread plans
+  constexpr bool XV = TPB <= 512;
   extern __shared__ double2 smem_d2[];
   float2* T = reinterpret_cast<float2*>(smem_d2);
 
@@ -574,7 +590,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     }
     }
     if (a.phi_part) {
-      const double tot = wave_sum<LANES>(phis);
+      const double tot = wave_sum<LANES, XV>(phis);
       if ((tid & 63) == 0) a.phi_part[(size_t)k * MAX_WAVES + wave] = tot * (0.5 / ((double)M * (double)M));
     }
 
@@ -683,7 +699,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     }
     if constexpr (STEPM) {
       if (a.probe_num) {
-        const float wm = wave_max<LANES>(pmx);
+        const float wm = wave_max<LANES, XV>(pmx);
         if ((tid & 63) == 0) a.probe_max[(size_t)wg * MAX_WAVES + wave] = wm;
       }
     }
@@ -692,7 +708,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       double gs = 0.0;
 #pragma unroll
       for (int n1 = 0; n1 < RA; ++n1) gs += (double)v[n1].x * v[n1].x + (double)v[n1].y * v[n1].y;
-      const double tot = wave_sum<LANES>(gs);
+      const double tot = wave_sum<LANES, XV>(gs);
       if ((tid & 63) == 0) a.gn_part[(size_t)k * MAX_WAVES + wave] = tot;
       return;
     } else {
@@ -758,7 +774,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
               if (l - 1 < LRB) {
 #pragma unroll
                 for (int i = 0; i < NC; ++i) {
-                  const double2 o = xor_lane_rt(cur[i], 1 << (l - 1));
+                  const double2 o = xor_lane_rt<XV>(cur[i], 1 << (l - 1));
                   s[i] = make_double2(cur[i].x + o.x, cur[i].y + o.y);
                 }
               } else {
@@ -775,7 +791,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
               const bool more = (l + 1 < L);
 #pragma unroll
               for (int i = 0; i < NC; ++i) {
-                const double2 o = xor_lane_rt(s[i], RB << (l - 1));
+                const double2 o = xor_lane_rt<XV>(s[i], RB << (l - 1));
                 const double2 gh = make_double2(0.25 * (s[i].x + o.x), 0.25 * (s[i].y + o.y));
                 const int y = RB * (n0 + i) + g;
                 const double aa = A[(y >> 1) * (M / 2) + (col >> 1)];
