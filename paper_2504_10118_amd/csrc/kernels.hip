@@ -31,13 +31,6 @@
 #include "cmath.h"
 #include "kernels.h"
 
-#ifndef MG_RGATHER
-#define MG_RGATHER 1
-#endif
-#ifndef MG_RGATHER_GROUP
-#define MG_RGATHER_GROUP 16
-#endif
-
 namespace mg {
 
 // W_128^j = exp(-2 pi i j / 128), j in [0, 128); filled once per device.
@@ -72,12 +65,12 @@ __device__ __forceinline__ float2 twiddle(int j) {
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
-// M <= 64 keeps the exit wave, Q and u0 in registers from the gather to the
-// V-cycle and reads the probe table once, as (Re Q, Im Q, u0, 0) float4s.
-// Larger M re-reads Q and u0 where they are used, so its table holds Q as
-// float2s followed by u0 as floats (both in thread order): a re-read fetches
-// only the bytes it needs.
-constexpr bool keeps_exit_wave(int M) { return M <= 64; }
+// M <= 64 keeps Q and u0 in registers from the gather to the V-cycle and
+// reads the probe table once, as (Re Q, Im Q, u0, 0) float4s.  Larger M
+// re-reads Q and u0 where they are used, so its table holds Q as float2s
+// followed by u0 as floats (both in thread order): a re-read fetches only the
+// bytes it needs.
+constexpr bool keeps_table(int M) { return M <= 64; }
 
 // w[j] = W_M^(b j) for 0 < j < R: the power-of-two exponents are read from
 // the table, every other one is the product of its highest power of two and
@@ -359,10 +352,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   const float4* qt = a.qtab + tid;   // [n1][tid]: each load reads one contiguous block
   const float2* qt2 = reinterpret_cast<const float2*>(a.qtab) + tid;            // split table: Q
   const float* ut = reinterpret_cast<const float*>(reinterpret_cast<const float2*>(a.qtab) + M * M) + tid;  // u0
-  // M <= 64 keeps the exit wave psi = Q z_k, Q and u0 in registers for the
-  // gradient conj(Q)(psi - R_k) and the V-cycle output; M = 128 (1024 threads
-  // at the 128-register cap) re-reads z_k and its table entry there instead.
-  constexpr bool KEEP = keeps_exit_wave(M);
+  // M <= 64 keeps Q and u0 in registers for the gradient conj(Q)(Q z_k - R_k)
+  // and the V-cycle output; M = 128 (1024 threads at the 128-register cap)
+  // re-reads its table entries there instead.
+  constexpr bool KEEP = keeps_table(M);
   constexpr bool ROWS = true;             // row-wise gathers through the LDS tile
   constexpr bool PREQ = (RA <= 8);        // probe table entries fetched before the gather
   // MODE_STEP_PR is the object step with the eq. (3.2) phase store
@@ -373,7 +366,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr bool CSTL = STEPM && (M > 64);
   // Loads that do not depend on z_k are issued first: the probe table, the
   // twiddles, sqrt(d) and the V-cycle constants.
-  float2 psi[KEEP ? RA : 1], qk[KEEP ? RA : 1];
+  float2 qk[KEEP ? RA : 1];
   float u0k[KEEP ? RA : 1];
   float4 qtv[PREQ ? RA : 1];
   if constexpr (PREQ) {
@@ -427,23 +420,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // Row gather: load j of thread tid reads row tid / M + j * TPB / M, column
   // tid % M: one per-lane offset, and a uniform per-load row step.
   constexpr int GR = TPB / M;   // rows per load of the workgroup
-  // NG loads in flight at a time.  The re-gather passes a copy of tid the
-  // compiler cannot see through, so that it recomputes its LDS addresses
-  // instead of keeping the first gather's alive through the whole FFT.
-  auto row_gather = [&](auto ng, int t) {
-    constexpr int NG = decltype(ng)::value;
-    const int gvo = ((t / M) * a.n_cols + (t & (M - 1))) * (int)sizeof(float2);
+  auto row_gather = [&]() {
+    const int gvo = ((tid / M) * a.n_cols + (tid & (M - 1))) * (int)sizeof(float2);
     const int gso = GR * a.n_cols * (int)sizeof(float2);
-    float2* const dst = T + (t / M) * P + (t & (M - 1));
+    float2* const dst = T + (tid / M) * P + (tid & (M - 1));
 #pragma unroll
-    for (int j0 = 0; j0 < RA; j0 += NG) {
-#pragma unroll
-      for (int j = j0; j < j0 + NG; ++j) dst[j * GR * P] = bload2(zr, gvo, j * gso);
-      if constexpr (NG < RA) __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int j = 0; j < RA; ++j) dst[j * GR * P] = bload2(zr, gvo, j * gso);
   };
   if constexpr (ROWS) {
-    row_gather(std::integral_constant<int, RA>{}, tid);
+    row_gather();
     __syncthreads();
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
@@ -459,7 +444,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       const float2 zz = T[(RB * n1 + g) * P + col];
       v[n1] = cmul(qv, zz);
       if constexpr (KEEP) {
-        psi[n1] = v[n1];
         qk[n1] = qv;
         u0k[n1] = uv;
       }
@@ -480,7 +464,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       const float2 zz = bload2(zr, zvo, n1 * zso);
       v[n1] = cmul(qv, zz);
       if constexpr (KEEP) {
-        psi[n1] = v[n1];
         qk[n1] = qv;
         u0k[n1] = uv;
       }
@@ -544,7 +527,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       }
     return;
   } else {
-    // ---- modulus replacement (Definition 2.1, theta(0) = 0); Phi_k partial in FP64
+    // ---- modulus replacement (Definition 2.1, theta(0) = 0); Phi_k partial in FP64.
+    // The spectrum is replaced by the difference F(Q z_k) - F(R_k) = F(Q z_k)
+    // (1 - sqrt(d) / |F(Q z_k)|) (-sqrt(d) theta where the spectrum vanishes), so
+    // the inverse transform yields Q z_k - R_k itself: the gradient needs
+    // neither the exit wave kept nor the patch read again.
     double phis = 0.0;
     if constexpr (MODE == MODE_STEP_PR) {
       // eq. (3.2): every phase factor is kept for the position's next visit and
@@ -565,11 +552,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
           phis += dlt * dlt;
           e = make_float2(t.x * ra, t.y * ra);
           ph[kx] = e;
+          const float f = fmaf(-s, ra, 1.0f);
+          v[j] = make_float2(t.x * f, t.y * f);
         } else {
           phis += (double)s * (double)s;
           e = ph[kx];
+          v[j] = make_float2(-s * e.x, -s * e.y);
         }
-        v[j] = make_float2(s * e.x, s * e.y);
       }
     } else {
 #pragma unroll
@@ -581,11 +570,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       if (a2 > 0.0f) {
         const double dlt = (double)(a2 * ra) - (double)s;
         phis += dlt * dlt;
-        const float f = s * ra;
+        const float f = fmaf(-s, ra, 1.0f);
         v[j] = make_float2(t.x * f, t.y * f);
       } else {
         phis += (double)s * (double)s;
-        v[j] = make_float2(s, 0.0f);
+        v[j] = make_float2(-s, 0.0f);
       }
     }
     }
@@ -651,43 +640,21 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     for (int k1 = 0; k1 < RA; ++k1) v[k1] = *colslice(xi(k1, g));
     dft<RA, -1>(v);
 
-    // Plans that do not keep the exit wave read z_k again for the gradient:
-    // with RGATHER as whole rows through the tile (free once every wave is
-    // past its last exchange), otherwise straight from the object.
-    constexpr bool RGATHER = !KEEP && (MG_RGATHER != 0);
-    int t_opaque = tid;
-    if constexpr (RGATHER) {
-      __syncthreads();
-      asm volatile("" : "+v"(t_opaque));
-      row_gather(std::integral_constant<int, MG_RGATHER_GROUP>{}, t_opaque);
-      __syncthreads();
-    }
-    // column reads of the re-gathered tile, addressed from the opaque copy of tid
-    const float2* const Tz = T + (t_opaque & (RB - 1)) * P + t_opaque / RB;
-    auto z_again = [&](int n1) -> float2 {
-      if constexpr (RGATHER) return Tz[RB * n1 * P];
-      else return bload2(zr, zvo, n1 * zso);
-    };
-
-    // ---- R_k = v / M^2; gradient g0 = conj(Q) (Q z_k - R_k) (eq. 2.2)
+    // ---- gradient g0 = conj(Q) (Q z_k - R_k) (eq. 2.2): v / M^2 is Q z_k - R_k
     constexpr float inv_m2 = 1.0f / (float)(M * M);
     float pmx = 0.0f;
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
-      float2 qq, ps;
-      if constexpr (KEEP) {
-        qq = qk[n1];
-        ps = psi[n1];
-      } else {
-        qq = qt2[n1 * TPB];
-        ps = cmul(qq, z_again(n1));
-      }
-      const float2 rk = cscale(v[n1], inv_m2);
+      float2 qq;
+      if constexpr (KEEP) qq = qk[n1];
+      else qq = qt2[n1 * TPB];
+      const float2 dk = cscale(v[n1], inv_m2);
       if constexpr (STEPM) {
         if (a.probe_num) {
-          // probe step partials: conj(z_k)(R_k - Q z_k) and |z_k|^2
-          const float2 zz = KEEP ? bload2(zr, zvo, n1 * zso) : z_again(n1);
-          const float2 pn = cmulc(zz, csub(rk, ps));
+          // probe step partials: conj(z_k)(R_k - Q z_k) and |z_k|^2 (the patch
+          // is read again for them, at the column stride)
+          const float2 zz = bload2(zr, zvo, n1 * zso);
+          const float2 pn = cmulc(zz, make_float2(-dk.x, -dk.y));
           const float pd = zz.x * zz.x + zz.y * zz.y;
           const size_t e = (size_t)wg * M * M + (size_t)(RB * n1 + g) * M + col;
           a.probe_num[e] = pn;
@@ -695,7 +662,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
           pmx = fmaxf(pmx, pd);
         }
       }
-      v[n1] = cmulc(qq, csub(ps, rk));
+      v[n1] = cmulc(qq, dk);
     }
     if constexpr (STEPM) {
       if (a.probe_num) {
@@ -1267,7 +1234,7 @@ __global__ void qtab_kernel(const float2* qf, const float* u0f, float4* qtab) {
   const int n1 = e / TPB, tid = e - n1 * TPB, g = tid & (RB - 1), col = tid / RB;
   const int i = (RB * n1 + g) * M + col;
   const float2 q = qf[i];
-  if constexpr (keeps_exit_wave(M)) {
+  if constexpr (keeps_table(M)) {
     qtab[e] = make_float4(q.x, q.y, u0f[i], 0.0f);
   } else {
     float2* q2 = reinterpret_cast<float2*>(qtab);
