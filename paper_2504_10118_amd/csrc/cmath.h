@@ -145,7 +145,8 @@ namespace mg {
 // Value of the lane whose id differs from this lane's in bit MASK (a power of
 // two below 64).  Masks 1 and 2 are DPP quad_perm, 8 is DPP row_ror:8.  The
 // others come in two forms:
-//   VALU = true: VALU cross-lane operations only, for latency-bound kernels
+//   VALU = true (VF: a bit mask of the distances 4, 16, 32 that take this form):
+//     VALU cross-lane operations only, for latency-bound kernels
 //     with few waves per SIMD (the LDS-pipe round trips of the other form sit
 //     on their critical path): 4 selects between row_ror:12 and row_ror:4
 //     (row_ror:N gives lane l the value of lane l - N of its 16-lane row, mod
@@ -157,8 +158,10 @@ namespace mg {
 //     result in odd rows (halves) and the second in even ones;
 //   VALU = false: ds_swizzle (4, 16) and ds_bpermute (32) in the LDS pipe, which
 //     cost no VALU issue slots where enough waves hide their latency.
-template <int MASK, bool VALU = true>
+constexpr int XOR_ALL_VALU = 4 | 16 | 32;
+template <int MASK, int VF = XOR_ALL_VALU>
 __device__ __forceinline__ int xor_lane(int v) {
+  constexpr bool VALU = (VF & MASK) != 0;
   static_assert(MASK > 0 && MASK < 64 && (MASK & (MASK - 1)) == 0, "power of two below 64");
   if constexpr (MASK == 1) {
     return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
@@ -183,29 +186,29 @@ __device__ __forceinline__ int xor_lane(int v) {
   }
 }
 
-template <int MASK, bool VALU = true>
+template <int MASK, int VF = XOR_ALL_VALU>
 __device__ __forceinline__ double xor_lane(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = xor_lane<MASK, VALU>((int)(b & 0xffffffffll));
-  const int hi = xor_lane<MASK, VALU>((int)(b >> 32));
+  const int lo = xor_lane<MASK, VF>((int)(b & 0xffffffffll));
+  const int hi = xor_lane<MASK, VF>((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int MASK, bool VALU = true>
+template <int MASK, int VF = XOR_ALL_VALU>
 __device__ __forceinline__ double2 xor_lane(double2 v) {
-  return make_double2(xor_lane<MASK, VALU>(v.x), xor_lane<MASK, VALU>(v.y));
+  return make_double2(xor_lane<MASK, VF>(v.x), xor_lane<MASK, VF>(v.y));
 }
 
 // Runtime mask dispatch (the mask is uniform and comes from a small set).
-template <bool VALU = true>
+template <int VF = XOR_ALL_VALU>
 __device__ __forceinline__ double2 xor_lane_rt(double2 v, int mask) {
   switch (mask) {
-    case 1: return xor_lane<1, VALU>(v);
-    case 2: return xor_lane<2, VALU>(v);
-    case 4: return xor_lane<4, VALU>(v);
-    case 8: return xor_lane<8, VALU>(v);
-    case 16: return xor_lane<16, VALU>(v);
-    default: return xor_lane<32, VALU>(v);
+    case 1: return xor_lane<1, VF>(v);
+    case 2: return xor_lane<2, VF>(v);
+    case 4: return xor_lane<4, VF>(v);
+    case 8: return xor_lane<8, VF>(v);
+    case 16: return xor_lane<16, VF>(v);
+    default: return xor_lane<32, VF>(v);
   }
 }
 

@@ -186,7 +186,7 @@ __device__ __forceinline__ void wave_sync() {
 // Sum over the lanes of one wave (LANES active lanes, a power of two), fixed
 // order: butterflies over lane distances LANES / 2, ..., 1 (VALU: which form of
 // the cross-lane exchange, see xor_lane).
-template <int LANES, bool VALU>
+template <int LANES, int VALU>
 __device__ __forceinline__ double wave_sum(double v) {
   if constexpr (LANES >= 64) v += xor_lane<32, VALU>(v);
   if constexpr (LANES >= 32) v += xor_lane<16, VALU>(v);
@@ -197,7 +197,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int LANES, bool VALU>
+template <int LANES, int VALU>
 __device__ __forceinline__ float wave_max(float v) {
   auto x = [](float a, auto mask) {
     return __int_as_float(xor_lane<decltype(mask)::value, VALU>(__float_as_int(a)));
@@ -313,8 +313,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr int LWI = inwave_levels(M, P, LW);   // coarse levels handled inside the wave
   constexpr int NW = (TPB + 63) / 64;
   // cross-lane exchanges in VALU form while the plan runs few waves per SIMD
-  // (up to 512 threads), in the LDS pipe for the 1024-thread plans
-  constexpr bool XV = TPB <= 512;
+  // (up to 512 threads); the 1024-thread plans, whose LDS pipe and VALU are both
+  // about half busy, keep distances 4 and 16 in the LDS pipe (measured: all in
+  // VALU form +4 us per cfg 3 launch, 4 or 16 as well +0.3-0.8 us, 32 alone -0.2 us)
+  constexpr int XV = TPB <= 512 ? XOR_ALL_VALU : 32;
   extern __shared__ double2 smem_d2[];
   float2* T = reinterpret_cast<float2*>(smem_d2);
 
