@@ -2,7 +2,8 @@
 //
 // step_kernel<M, RB, MODE>  one workgroup per scan position: gather z_k, exit wave
 //                       Q * z_k, LDS-resident 2-D FFT, modulus replacement
-//                       (Definition 2.1), inverse FFT, gradient
+//                       (Definition 2.1) kept as the difference F(Q z_k) - F(R_k),
+//                       inverse FFT of it, gradient
 //                       g0 = conj(Q)(Q z_k - R_k) (eq. 2.2), MAGPS V-cycle in
 //                       gradient form (Alg 3 / eq. 4.6), write c_k = w0 * dz_k.
 // accumulate_kernel     one workgroup per 64 x TH object tile: fixed-order sum
