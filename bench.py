@@ -342,7 +342,10 @@ def main():
     ctx.set_positions(offs)
     dtilde = ctx.forward_model(z_true)                       # GPU forward model
     d = poisson_counts(dtilde, cfg.peak, r_noise).astype(np.float32)
-    ctx.load_intensities(d, is_sqrt=False)
+    torch.cuda.synchronize()
+    tl0 = time.perf_counter()
+    ctx.load_intensities(d, is_sqrt=False)                   # host -> device, checked (synchronises)
+    load_s = time.perf_counter() - tl0
     ctx.set_object(np.ones((cfg.n, cfg.n), dtype=np.complex64))
     tuning = None
     if args.tuning:
@@ -365,6 +368,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     phi, stat = ctx.objective()
+    tr0 = time.perf_counter()
+    ctx.get_object()                                         # device -> host read-back of the object
+    readback_s = time.perf_counter() - tr0
 
     # kernel timing: the same epochs again, every launch bracketed by HIP events
     # that its own dispatch records on the context's stream
@@ -432,6 +438,12 @@ def main():
             "step_share": step_s / (t3 - t2),
             "accumulate_share": tm["accum_ms"] * 1e-3 / (t3 - t2),
         },
+        "pcie_inclusive": {
+            "note": "the same job with the host-buffer boundary crossings added: the measured intensities "
+                    "uploaded (and square-rooted, re-laid out, checked) by magpie_load_intensities, and the "
+                    "object read back; not the value",
+            "value": patterns / (wall + load_s + readback_s),
+            "load_ms": load_s * 1e3, "readback_ms": readback_s * 1e3},
         "objective_after": phi,
         "stopping_statistic_after": stat,
     }
