@@ -367,8 +367,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // M = 128: the V-cycle constants do not fit beside the FFT tile; they are
   // staged into the tile once the FFT and the gradient are done with it.
   constexpr bool CSTL = STEPM && (M > 64);
-  // Loads that do not depend on z_k are issued first: the probe table, the
-  // twiddles, sqrt(d) and the V-cycle constants.
+  // The probe table and the twiddles do not depend on z_k and are needed with
+  // it: they are issued first.
   float2 qk[KEEP ? RA : 1];
   float u0k[KEEP ? RA : 1];
   float4 qtv[PREQ ? RA : 1];
@@ -396,25 +396,26 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       }
     }
   };
-  if constexpr (!LAZY) load_sd();
-  // In-wave V-cycle constants (A_l, V_l; M <= 64): fetched now as 16-byte
-  // pairs (the block starts at an even offset and is padded by one double),
-  // parked in LDS at the first barrier, so their latency hides behind the
-  // forward FFT.
+  // In-wave V-cycle constants (A_l, V_l; M <= 64): fetched as 16-byte pairs
+  // (the block starts at an even offset and is padded by one double) right
+  // after the patch, parked in LDS at the first barrier, so their latency
+  // hides behind the forward FFT.
   constexpr int M1c = M / 2;
   constexpr int CST_MAX = CST ? cst_count_max(M, LWI) : 2;
   constexpr int CST_PER = ((CST_MAX + 1) / 2 + TPB - 1) / TPB;   // double2 per thread
   double* const Cst = reinterpret_cast<double*>(T + M * P);
   const int nCst = (CST && a.levels >= 2 && a.levels - 1 <= LWI) ? cst_count(M, a.levels) : 0;
   double2 cst[CST_PER];
-  if constexpr (CST) {
-    const double2* src = reinterpret_cast<const double2*>(a.lvl + a.lvl_a_off);
+  auto load_cst = [&]() {
+    if constexpr (CST) {
+      const double2* src = reinterpret_cast<const double2*>(a.lvl + a.lvl_a_off);
 #pragma unroll
-    for (int i = 0; i < CST_PER; ++i) {
-      const int e = tid + i * TPB;
-      cst[i] = (2 * e < nCst) ? src[e] : make_double2(0.0, 0.0);
+      for (int i = 0; i < CST_PER; ++i) {
+        const int e = tid + i * TPB;
+        cst[i] = (2 * e < nCst) ? src[e] : make_double2(0.0, 0.0);
+      }
     }
-  }
+  };
 
   // Gather: the patch is read as whole rows (each wave reads contiguous row
   // segments) into the LDS tile, and after one barrier every thread takes its
@@ -432,6 +433,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   };
   if constexpr (ROWS) {
     row_gather();
+    // sqrt(d) (needed at the modulus) and the constants (at the V-cycle) are
+    // issued after the patch: loads return in issue order, so issued first they
+    // had held up the patch the barrier below waits for (cfg 2 epoch -2 %)
+    if constexpr (!LAZY) load_sd();
+    load_cst();
     __syncthreads();
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
@@ -453,6 +459,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     }
     wave_sync();   // the column pass below reuses this wave's own column slice of the tile
   } else {
+    if constexpr (!LAZY) load_sd();
+    load_cst();
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
       float2 qv;
