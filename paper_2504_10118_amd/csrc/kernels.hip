@@ -360,22 +360,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // re-reads its table entries there instead.
   constexpr bool KEEP = keeps_table(M);
   constexpr bool ROWS = true;             // row-wise gathers through the LDS tile
-  constexpr bool PREQ = (RA <= 8);        // probe table entries fetched before the gather
+  constexpr bool PREQ = (RA <= 8);        // probe table entries in flight with the gather
   // MODE_STEP_PR is the object step with the eq. (3.2) phase store
   constexpr bool STEPM = (MODE == MODE_STEP) || (MODE == MODE_STEP_PR);
   constexpr bool CST = STEPM && (M <= 64);
   // M = 128: the V-cycle constants do not fit beside the FFT tile; they are
   // staged into the tile once the FFT and the gradient are done with it.
   constexpr bool CSTL = STEPM && (M > 64);
-  // The probe table and the twiddles do not depend on z_k and are needed with
-  // it: they are issued first.
+  // The twiddle table reads go first (small, needed by the first FFT stage).
   float2 qk[KEEP ? RA : 1];
   float u0k[KEEP ? RA : 1];
   float4 qtv[PREQ ? RA : 1];
-  if constexpr (PREQ) {
-#pragma unroll
-    for (int n1 = 0; n1 < RA; ++n1) qtv[n1] = qt[n1 * TPB];
-  }
   // twiddles: stage A uses W_M^(g k1); the inverse stage B uses W_M^(n2 (g CB + c)).
   // Powers of two of the base come from the table, the other exponents are
   // products of two earlier ones (at most log2 RA roundings deep).
@@ -433,9 +428,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   };
   if constexpr (ROWS) {
     row_gather();
-    // sqrt(d) (needed at the modulus) and the constants (at the V-cycle) are
-    // issued after the patch: loads return in issue order, so issued first they
-    // had held up the patch the barrier below waits for (cfg 2 epoch -2 %)
+    // The probe table (needed with the patch), sqrt(d) (at the modulus) and the
+    // constants (at the V-cycle) are issued after the patch: loads return in
+    // issue order, so issued first they had held up the patch the barrier below
+    // waits for (cfg 2 epoch: -2 % for sqrt(d) and the constants, -1.3 % for the
+    // table).
+    if constexpr (PREQ) {
+#pragma unroll
+      for (int n1 = 0; n1 < RA; ++n1) qtv[n1] = qt[n1 * TPB];
+    }
     if constexpr (!LAZY) load_sd();
     load_cst();
     __syncthreads();
