@@ -428,17 +428,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   };
   if constexpr (ROWS) {
     row_gather();
-    // The probe table (needed with the patch), sqrt(d) (at the modulus) and the
-    // constants (at the V-cycle) are issued after the patch: loads return in
-    // issue order, so issued first they had held up the patch the barrier below
-    // waits for (cfg 2 epoch: -2 % for sqrt(d) and the constants, -1.3 % for the
-    // table).
+    // The probe table (needed with the patch), the constants (parked in LDS
+    // before the first transpose) and sqrt(d) (needed at the modulus) are issued
+    // after the patch, in the order they are needed: loads return in issue
+    // order, so issued first they had held up the patch the barrier below waits
+    // for (cfg 2 epoch: -2 % for sqrt(d) and the constants, -1.3 % for the
+    // table, -0.6 % for the constants ahead of sqrt(d)).
     if constexpr (PREQ) {
 #pragma unroll
       for (int n1 = 0; n1 < RA; ++n1) qtv[n1] = qt[n1 * TPB];
     }
-    if constexpr (!LAZY) load_sd();
     load_cst();
+    if constexpr (!LAZY) load_sd();
     __syncthreads();
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
@@ -460,8 +461,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     }
     wave_sync();   // the column pass below reuses this wave's own column slice of the tile
   } else {
-    if constexpr (!LAZY) load_sd();
     load_cst();
+    if constexpr (!LAZY) load_sd();
 #pragma unroll
     for (int n1 = 0; n1 < RA; ++n1) {
       float2 qv;
