@@ -227,7 +227,7 @@ int magpie_get_timing(magpie_ctx* ctx, double* step_ms, double* accum_ms, int64_
  * Kernel variants (no effect on the mathematics; results agree to FP32
  * rounding).  The step kernel's FFT plan is the number of threads per 1-D
  * transform (each thread then holds m / threads points); the accumulation
- * kernel works on object tiles of 64 columns x tile_rows rows (4, 8, 16 or
+ * kernel works on object tiles of 32 columns x tile_rows rows (8, 16 or
  * 32).
  * magpie_list_plans writes the compiled plans of m (default first) and
  * returns their count.  magpie_set_tuning (0 = keep) changes them, moving the

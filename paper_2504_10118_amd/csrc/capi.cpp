@@ -875,7 +875,7 @@ int magpie_set_tuning(magpie_ctx* c, int threads_per_transform, int tile_rows) {
   const int rb = threads_per_transform ? threads_per_transform : c->rb;
   const int th = tile_rows ? tile_rows : c->th;
   if (!mg::plan_valid(c->m, rb)) return fail(MAGPIE_ERR_UNSUPPORTED, "no such FFT plan for this m");
-  if (!mg::tile_valid(th)) return fail(MAGPIE_ERR_UNSUPPORTED, "tile rows must be 4, 8, 16 or 32");
+  if (!mg::tile_valid(th)) return fail(MAGPIE_ERR_UNSUPPORTED, "tile rows must be 8, 16 or 32");
   int rc = set_dev(c);
   if (rc) return rc;
   if (rb != c->rb) {
@@ -962,8 +962,8 @@ int magpie_autotune(magpie_ctx* c, int batch, int trial_epochs, double* step_us,
       best_rb = rbs[i];
     }
   }
-  const int ths[4] = {4, 8, 16, 32};
-  for (int i = 0; i < 4 && !rc; ++i) {
+  const int ths[3] = {8, 16, 32};
+  for (int i = 0; i < 3 && !rc; ++i) {
     rc = magpie_set_tuning(c, best_rb, ths[i]);
     double su = 0, au = 0;
     if (!rc) rc = trial(&su, &au);

@@ -58,7 +58,7 @@ struct AccumArgs {
   const float* w0f;       // u + |Q|^2 [m][m], FP32 copy
 };
 
-constexpr int ACC_TILE_W = 64;
+constexpr int ACC_TILE_W = 32;   // accumulation tile width (two rows per wave)
 constexpr int ACC_THREADS = 256;
 
 // FFT plans (m, rb): rb threads per 1-D transform.  plans_for lists the
@@ -66,7 +66,7 @@ constexpr int ACC_THREADS = 256;
 bool plan_valid(int m, int rb);
 int default_plan(int m);
 int plans_for(int m, int* rbs, int cap);
-bool tile_valid(int th);                    // accumulate tile heights: 4, 8, 16, 32
+bool tile_valid(int th);                    // accumulate tile heights: 8, 16, 32
 int step_threads(int m, int rb);            // workgroup size of the per-position kernel
 int step_waves(int m, int rb);
 size_t step_lds_bytes(int m, int rb);       // dynamic LDS of the per-position kernel

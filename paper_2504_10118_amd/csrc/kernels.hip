@@ -6,7 +6,7 @@
 //                       inverse FFT of it, gradient
 //                       g0 = conj(Q)(Q z_k - R_k) (eq. 2.2), MAGPS V-cycle in
 //                       gradient form (Alg 3 / eq. 4.6), write c_k = w0 * dz_k.
-// accumulate_kernel     one workgroup per 64 x TH object tile: fixed-order sum
+// accumulate_kernel     one workgroup per 32 x TH object tile: fixed-order sum
 //                       of the overlapping c_k and of w0 (FP64), z += N / D.
 // level_constants_kernel FP64 probe hierarchy (eq. 4.4) and per-level
 //                       coefficients of the gradient-form V-cycle.
@@ -928,8 +928,12 @@ size_t step_lds_bytes(int m, int rb) {
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic segmented accumulation + apply.  One workgroup per 64 x TH
-// tile; lane = column, wave w owns rows w, w+4, w+8, ... .  The positions
+// Deterministic segmented accumulation + apply.  One workgroup per 32 x TH
+// tile; a wave covers two rows (lanes 0-31 and 32-63 = columns), wave w owns
+// rows 2w, 2w+1, 2w+8, 2w+9, ... .  32-column tiles are overlapped by fewer
+// positions than 64-column ones (a window reaches a tile from a 32 + m - 1
+// column range instead of 64 + m - 1), so each pixel loops over fewer members
+// that do not cover it (cfg 2 epoch -3 % against 64 x 4 tiles).  The positions
 // overlapping the tile (ascending index, with their offsets) are screened 256
 // at a time in parallel: those in minibatch t are compacted, order preserved,
 // into LDS, then every thread sums their staged c_k and w0 over its pixels in
@@ -938,7 +942,7 @@ size_t step_lds_bytes(int m, int rb) {
 // ---------------------------------------------------------------------------
 template <int TH>
 __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int tile) {
-  constexpr int RPT = TH / (ACC_THREADS / 64);
+  constexpr int RPT = TH / (2 * ACC_THREADS / 64);
   constexpr int NW = ACC_THREADS / 64;
   constexpr int U = 4;   // positions whose loads are in flight together
   __shared__ int s_slot[ACC_THREADS];
@@ -947,8 +951,8 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int ti
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int X = tx * ACC_TILE_W + lane;
-  const int Y0 = ty * TH + wave;
+  const int X = tx * ACC_TILE_W + (lane & 31);
+  const int Y0 = ty * TH + 2 * wave + (lane >> 5);
   const int m = a.m;
   const size_t mm = (size_t)m * m;
   double nr[RPT], ni[RPT], dd[RPT];
@@ -959,7 +963,7 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int ti
   float2 zo[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int Y = Y0 + 4 * i;
+    const int Y = Y0 + 8 * i;
     zo[i] = (X < a.n_cols && Y < a.n_rows) ? a.z[(size_t)Y * a.n_cols + X] : make_float2(0.0f, 0.0f);
   }
   const int beg = a.tile_ptr[tile], end = a.tile_ptr[tile + 1];
@@ -1008,7 +1012,7 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int ti
         const bool okx = have && (unsigned)xx < (unsigned)m;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          const int yy = Y0 + 4 * i - o.x;
+          const int yy = Y0 + 8 * i - o.x;
           ok[u][i] = okx && ((unsigned)yy < (unsigned)m);
           const int e = ok[u][i] ? (yy * m + xx) : 0;
           cv[u][i] = a.stage[(size_t)sl * mm + e];
@@ -1030,7 +1034,7 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int ti
   if (X < a.n_cols) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int Y = Y0 + 4 * i;
+      const int Y = Y0 + 8 * i;
       if (Y < a.n_rows && dd[i] > 0.0)
         a.z[(size_t)Y * a.n_cols + X] =
             make_float2((float)((double)zo[i].x + nr[i] / dd[i]), (float)((double)zo[i].y + ni[i] / dd[i]));
@@ -1060,7 +1064,7 @@ static void launch_accumulate_t(const AccumArgs& a, int n_tiles, hipStream_t s, 
     hipLaunchKernelGGL(accumulate_kernel<TH>, dim3(n_tiles), dim3(ACC_THREADS), 0, s, a);
 }
 
-bool tile_valid(int th) { return th == 4 || th == 8 || th == 16 || th == 32; }
+bool tile_valid(int th) { return th == 8 || th == 16 || th == 32; }
 
 hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, const int* prefix, int n_ctx, int total,
                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
@@ -1097,7 +1101,6 @@ hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, const int* pr
                                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (n_ctx <= 0 || total <= 0) return hipSuccess;
   switch (th) {
-    case 4: launch_acc_multi_t<4>(descs, prefix, n_ctx, total, s, ev0, ev1); break;
     case 8: launch_acc_multi_t<8>(descs, prefix, n_ctx, total, s, ev0, ev1); break;
     case 16: launch_acc_multi_t<16>(descs, prefix, n_ctx, total, s, ev0, ev1); break;
     case 32: launch_acc_multi_t<32>(descs, prefix, n_ctx, total, s, ev0, ev1); break;
@@ -1110,7 +1113,6 @@ hipError_t launch_accumulate(const AccumArgs& a, int th, int n_tiles, hipStream_
                              hipEvent_t ev1) {
   if (n_tiles <= 0) return hipSuccess;
   switch (th) {
-    case 4: launch_accumulate_t<4>(a, n_tiles, s, ev0, ev1); break;
     case 8: launch_accumulate_t<8>(a, n_tiles, s, ev0, ev1); break;
     case 16: launch_accumulate_t<16>(a, n_tiles, s, ev0, ev1); break;
     case 32: launch_accumulate_t<32>(a, n_tiles, s, ev0, ev1); break;

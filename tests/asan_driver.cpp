@@ -105,7 +105,7 @@ int main() {
   int32_t plans[8];
   const int np_ = magpie_list_plans(m, plans, 8);
   if (np_ < 1) ++failures;
-  for (int i = 0; i < np_; ++i) expect(magpie_set_tuning(c, plans[i], 4 << (i % 3)), MAGPIE_OK, "set_tuning");
+  for (int i = 0; i < np_; ++i) expect(magpie_set_tuning(c, plans[i], 8 << (i % 3)), MAGPIE_OK, "set_tuning");
   double su = 0, au = 0;
   expect(magpie_autotune(c, 7, 1, &su, &au), MAGPIE_OK, "autotune");
   int rb = 0, th = 0;
@@ -139,6 +139,7 @@ int main() {
   std::vector<int32_t> notperm(N, 0);
   expect(magpie_run_epochs(c, 1, 4, 0, notperm.data()), MAGPIE_ERR_INVALID_ARG, "order not a permutation");
   expect(magpie_set_tuning(c, 3, 0), MAGPIE_ERR_UNSUPPORTED, "no such plan");
+  expect(magpie_set_tuning(c, 0, 4), MAGPIE_ERR_UNSUPPORTED, "no such tile height");
   magpie_ctx* e = nullptr;
   expect(magpie_create(&e, 64, 64, 24, 2, 0.5, 0, nullptr), MAGPIE_ERR_UNSUPPORTED, "m not a power of two");
   expect(magpie_create(&e, 64, 64, 16, 2, 0.5, 0, nullptr), MAGPIE_OK, "create fresh");

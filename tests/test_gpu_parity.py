@@ -413,7 +413,7 @@ def test_tile_heights_bitwise_equal_and_plan_switch_after_load():
     rng = np.random.default_rng(17)
     c = Case(rng, 200, 170, 32, 7, noise=0.05)
     outs = []
-    for th in (4, 8, 16, 32):
+    for th in (8, 16, 32, 8):
         g = c.gpu(3, 0.5)
         g.set_tuning(0, th)
         g.run_epochs(2, 12, seed=4)
