@@ -184,6 +184,8 @@ def bench_batched(args):
         ctx = Magpie(sp.n, sp.n, sp.m, sp.levels, alpha, device=0, stream=st.cuda_stream)
         ctx.set_probe(Q.astype(np.complex64))
         ctx.set_positions(offs)
+        if args.tuning:
+            ctx.set_tuning(*(int(x) for x in args.tuning.split(",")))
         dt = torch.empty((sp.n_pos, sp.m, sp.m), dtype=torch.float32, device="cuda")
         ctx.forward_model(z_true.astype(np.complex64), out=dt)                  # GPU forward model
         ctx.load_intensities(poisson_counts_device(dt, sp.peak, sp.seed), is_sqrt=False)
