@@ -72,7 +72,10 @@ const char* magpie_last_error(void);
 
 /*
  * Create a reconstruction context on HIP device `device`.
- *   n_rows, n_cols : object size (>= m each).
+ *   n_rows, n_cols : object size (>= m each); the object's n_rows * n_cols
+ *                    complex64 values must take fewer than 2^32 bytes (the
+ *                    kernels address it through 32-bit buffer ranges), else
+ *                    MAGPIE_ERR_UNSUPPORTED.
  *   m              : probe / patch side; one of 8, 16, 32, 64, 128.
  *   n_levels       : number of grids of the MAGPS V-cycle (Alg 3): the fine
  *                    grid plus n_levels-1 coarse grids, 1 <= n_levels <=
@@ -115,14 +118,23 @@ int magpie_set_regularization(magpie_ctx* ctx, double alpha, const double* u);
 int magpie_set_positions(magpie_ctx* ctx, int n_pos, const int32_t* offsets);
 
 /*
- * Measured data: float32 [n_pos][m][m], zero frequency at [0][0].
+ * Measured data d_k of the problem statement (Section 2.1: the far-field
+ * intensities |F(Q * P_k z)|^2 recorded at scan position k), float32
+ * [n_pos][m][m], zero frequency at [0][0], in the order of the positions.
+ * Host data are copied before the call returns; device data are read in
+ * stream order (see the conventions above).
  * is_sqrt = 0: intensities d_k (>= 0), the library takes square roots;
  * is_sqrt = 1: amplitudes sqrt(d_k).  Stored internally in the order the
  * kernels consume.  Errors: BAD_STATE (no positions), INVALID_ARG, HIP.
  */
 int magpie_load_intensities(magpie_ctx* ctx, const float* d, int is_sqrt, int on_device);
 
-/* Set the object z (n_rows x n_cols complex).  Errors: INVALID_ARG, HIP. */
+/*
+ * Set the object z (n_rows x n_cols complex, dtype MAGPIE_C64 or MAGPIE_C128):
+ * the initial guess z^(0) that Alg 4 (MAGPIE) takes as input, or any later
+ * iterate to resume from.  Stored as complex64.  Errors: INVALID_ARG (null,
+ * bad dtype), NUMERIC (non-finite values), HIP.
+ */
 int magpie_set_object(magpie_ctx* ctx, const void* z, int dtype, int on_device);
 
 /*
@@ -145,6 +157,18 @@ int magpie_run_epochs(magpie_ctx* ctx, int n_epochs, int batch, uint64_t seed,
                       const int32_t* order);
 
 /*
+ * One minibatch step (the inner step of magpie_run_epochs) over exactly the
+ * `count` distinct positions listed in `positions` (host int32 array of indices
+ * in [0, n_pos)): every listed position reads the same z and
+ *     z <- z + sum_k P_k^T (w0 dz_k) / sum_k P_k^T w0
+ * on the pixels they cover.  With one position this is one update of Alg 4.
+ * The epoch counter is not advanced and no graph is used.  Asynchronous.
+ * Errors: BAD_STATE, INVALID_ARG (count out of range, repeated or invalid
+ * index), OOM, HIP.
+ */
+int magpie_run_minibatch(magpie_ctx* ctx, int count, const int32_t* positions);
+
+/*
  * Objective pass over all positions at the current object (eq. 2.1, reported
  * in exit-wave form (1 / (2 m^2)) sum_k || |F(Q z_k)| - sqrt(d_k) ||^2),
  * reduced in FP64 in a fixed order.  grad_stat (nullable) receives the
@@ -161,7 +185,13 @@ int magpie_objective(magpie_ctx* ctx, double* phi, double* grad_stat);
  */
 int magpie_get_step_phi(magpie_ctx* ctx, double* phi_k);
 
-/* Copy the object / probe out (dtype C64 or C128).  Host outputs synchronise. */
+/*
+ * Copy out the current iterate z^(j) of Alg 4 (magpie_get_object; n_rows x
+ * n_cols) or the probe Q (magpie_get_probe; m x m: the one set, or the
+ * updated one with MAGPIE_UPDATE_PROBE), as dtype C64 or C128, into caller
+ * memory (host, or device with on_device = 1, written in stream order).
+ * Host outputs synchronise the stream.  Errors: INVALID_ARG, HIP.
+ */
 int magpie_get_object(magpie_ctx* ctx, void* out, int dtype, int on_device);
 int magpie_get_probe(magpie_ctx* ctx, void* out, int dtype, int on_device);
 

@@ -41,8 +41,9 @@ Pins (tests/test_oracle_*.py): brute-force DFT, Parseval, the objective
 identity, finite-difference gradients, Lemma C.1 / Prop 3.1 majorisation,
 Prop 3.2 descent, Prop 3.3 bound, Lemmas E.1-E.4, Props 4.1, 4.2, 4.4
 (as an inequality), Thm 4.3 and eq. (4.6), the rPIE special case, literal
-Alg 3 == gradient form, fixed point at the truth, recovery, and the
-splitmix64 published test vector.  The minibatch combination for L >= 2 and
+Alg 3 == gradient form, fixed point at the truth, recovery, the
+splitmix64 published test vector, and u^rPIE and the stopping statistic of
+Section 5 on hand-worked values.  The minibatch combination for L >= 2 and
 B >= 2 is "parity unpinned" beyond its two pinned special cases (B = 1 and
 L = 1); the probe update is beyond the paper and likewise unpinned except by
 its own descent property.

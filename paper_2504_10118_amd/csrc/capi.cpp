@@ -127,6 +127,9 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   if (n_levels < 1 || n_levels > ilog2(m) + 1)
     return fail(MAGPIE_ERR_UNSUPPORTED, "n_levels must be in [1, log2(m)+1]");
   if (n_rows < m || n_cols < m) return fail(MAGPIE_ERR_INVALID_ARG, "object smaller than the probe");
+  // the kernels address the object through 32-bit buffer ranges
+  if ((uint64_t)n_rows * (uint64_t)n_cols * sizeof(float2) >= (1ull << 32))
+    return fail(MAGPIE_ERR_UNSUPPORTED, "object of 2^32 bytes or more (n_rows * n_cols >= 2^29)");
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MAGPIE_ERR_INVALID_ARG, "alpha must be finite, >= 0");
   int ndev = 0;
   MG_HIP(hipGetDeviceCount(&ndev));
@@ -518,14 +521,11 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
   return MAGPIE_OK;
 }
 
-int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
-  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
-  if (n_epochs == 0 && batch >= 1) return MAGPIE_OK;
-  int rc = prepare_epochs(c, n_epochs, batch, seed, order);
-  if (rc) return rc;
+// Launches n_epochs prepared epochs of minibatch size B (the first
+// batches_per_epoch minibatches of each; the rest are not run).
+static int launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoch, bool allow_graph) {
   const int N = c->n_pos, m = c->m;
-  const int B = std::min(batch, N);
-  const int nbatch = (N + B - 1) / B;
+  const int nbatch = std::min((N + B - 1) / B, batches_per_epoch);
   const bool probe_step = (c->flags & MAGPIE_UPDATE_PROBE) != 0;
 
   mg::StepArgs sa{};
@@ -595,7 +595,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   aa.offs = c->offs;
   aa.w0f = c->w0f;
   const int n_tiles = c->tiles_x * c->tiles_y;
-  const bool use_graph = !c->timing && (c->flags & MAGPIE_GRAPH);
+  const bool use_graph = allow_graph && !c->timing && (c->flags & MAGPIE_GRAPH);
   if (use_graph) {
     const void* key[4] = {c->posrec, c->inv, c->stage, c->pnum};
     if (c->g_rb != c->rb || c->g_th != c->th) drop_graph(c);
@@ -638,7 +638,6 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
     }
     MG_HIP(mg::launch_set_counter(c->epoch_ctr, 0, c->stream));
     for (int e = 0; e < n_epochs; ++e) MG_HIP(hipGraphLaunch(c->gexec, c->stream));
-    c->epoch_index += (uint64_t)n_epochs;
     return MAGPIE_OK;
   }
   for (int e = 0; e < n_epochs; ++e) {
@@ -657,8 +656,44 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
       if (probe_step) MG_HIP(probe_tail(sa.count));
     }
   }
+  return MAGPIE_OK;
+}
+
+int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (n_epochs == 0 && batch >= 1) return MAGPIE_OK;
+  int rc = prepare_epochs(c, n_epochs, batch, seed, order);
+  if (rc) return rc;
+  const int B = std::min(batch, c->n_pos);
+  rc = launch_epochs(c, n_epochs, B, (c->n_pos + B - 1) / B, true);
+  if (rc) return rc;
   c->epoch_index += (uint64_t)n_epochs;
   return MAGPIE_OK;
+}
+
+int magpie_run_minibatch(magpie_ctx* c, int count, const int32_t* positions) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (!c->has_probe || !c->has_pos || !c->has_data)
+    return fail(MAGPIE_ERR_BAD_STATE, "set probe, positions and intensities first");
+  if (!positions || count < 1 || count > c->n_pos)
+    return fail(MAGPIE_ERR_INVALID_ARG, "positions must list 1 .. n_pos distinct positions");
+  // one epoch whose permutation starts with the given positions (the rest follow in
+  // ascending order and are not run)
+  std::vector<int32_t> order;
+  order.reserve((size_t)c->n_pos);
+  std::vector<char> seen((size_t)c->n_pos, 0);
+  for (int i = 0; i < count; ++i) {
+    const int k = positions[i];
+    if (k < 0 || k >= c->n_pos || seen[(size_t)k])
+      return fail(MAGPIE_ERR_INVALID_ARG, "positions must be distinct indices in [0, n_pos)");
+    seen[(size_t)k] = 1;
+    order.push_back(k);
+  }
+  for (int k = 0; k < c->n_pos; ++k)
+    if (!seen[(size_t)k]) order.push_back(k);
+  int rc = prepare_epochs(c, 1, count, 0, order.data());
+  if (rc) return rc;
+  return launch_epochs(c, 1, count, 1, false);
 }
 
 int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {

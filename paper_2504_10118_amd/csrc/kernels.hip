@@ -212,6 +212,36 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// Modulus replacement of one spectrum value t = F(Q z_k) with measured
+// amplitude s (Definition 2.1), kept as the difference t - s e with e = t / |t|
+// (= F(Q z_k) - F(R_k)); returns false where t counts as zero (the caller applies
+// its theta(0) rule) only where t is exactly zero.  (|t| - s)^2 is added to
+// phis.  The hardware reciprocal square root does not take single-precision
+// denormals, and |t|^2 underflows for |t| < 2^-75, so where |t|^2 < 2^-100 the
+// value is first scaled by 2^100 (exactly): every nonzero t then has a normal
+// squared magnitude in [2^-98, 2^100).
+__device__ __forceinline__ bool modulus_diff(float2 t, float s, float2& out, float2& e, double& phis) {
+  const float a2 = t.x * t.x + t.y * t.y;
+  if (a2 >= 0x1p-100f) {
+    const float ra = __builtin_amdgcn_rsqf(a2);
+    const double dlt = (double)(a2 * ra) - (double)s;
+    phis += dlt * dlt;
+    e = make_float2(t.x * ra, t.y * ra);
+    const float f = fmaf(-s, ra, 1.0f);
+    out = make_float2(t.x * f, t.y * f);
+    return true;
+  }
+  const float tx = t.x * 0x1p100f, ty = t.y * 0x1p100f;
+  const float b2 = tx * tx + ty * ty;
+  if (!(b2 > 0.0f)) return false;
+  const float rb = __builtin_amdgcn_rsqf(b2);
+  const double dlt = (double)(b2 * rb) * 0x1p-100 - (double)s;
+  phis += dlt * dlt;
+  e = make_float2(tx * rb, ty * rb);
+  out = make_float2(fmaf(-s, e.x, t.x), fmaf(-s, e.y, t.y));
+  return true;
+}
+
 // MAGPS V-cycle through LDS for hierarchies whose coarse bins span several
 // waves.  On entry g0 is in T[y][x] (pitch P) and in v (thread (x, g) holds
 // rows RB*n1 + g).  Coarse grids (FP64) overwrite the start of the LDS tile.
@@ -555,18 +585,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
       for (int j = 0; j < RA; ++j) {
         const int kx = g * CB + j / RB + RA * (j % RB);
-        const float2 t = v[j];
-        const float a2 = t.x * t.x + t.y * t.y;
         const float s = sd[j];
-        float2 e;
-        if (a2 > 0.0f) {
-          const float ra = __builtin_amdgcn_rsqf(a2);
-          const double dlt = (double)(a2 * ra) - (double)s;
-          phis += dlt * dlt;
-          e = make_float2(t.x * ra, t.y * ra);
+        float2 e, dv;
+        if (modulus_diff(v[j], s, dv, e, phis)) {
           ph[kx] = e;
-          const float f = fmaf(-s, ra, 1.0f);
-          v[j] = make_float2(t.x * f, t.y * f);
+          v[j] = dv;
         } else {
           phis += (double)s * (double)s;
           e = ph[kx];
@@ -576,15 +599,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     } else {
 #pragma unroll
     for (int j = 0; j < RA; ++j) {
-      const float2 t = v[j];
-      const float a2 = t.x * t.x + t.y * t.y;
-      const float ra = __builtin_amdgcn_rsqf(a2);
       const float s = sd[j];
-      if (a2 > 0.0f) {
-        const double dlt = (double)(a2 * ra) - (double)s;
-        phis += dlt * dlt;
-        const float f = fmaf(-s, ra, 1.0f);
-        v[j] = make_float2(t.x * f, t.y * f);
+      float2 e, dv;
+      if (modulus_diff(v[j], s, dv, e, phis)) {
+        v[j] = dv;
       } else {
         phis += (double)s * (double)s;
         v[j] = make_float2(-s, 0.0f);

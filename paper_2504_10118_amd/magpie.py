@@ -50,6 +50,7 @@ def _bind(lib):
         "magpie_load_intensities": (i, [vp, vp, i, i]),
         "magpie_set_object": (i, [vp, vp, i, i]),
         "magpie_run_epochs": (i, [vp, i, i, u64, vp]),
+        "magpie_run_minibatch": (i, [vp, i, vp]),
         "magpie_objective": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(d)]),
         "magpie_get_step_phi": (i, [vp, vp]),
         "magpie_get_object": (i, [vp, vp, i, i]),
@@ -244,6 +245,11 @@ class Magpie:
         else:
             o = np.ascontiguousarray(order, dtype=np.int32).reshape(n_epochs, self.n_pos)
             _check(self.lib.magpie_run_epochs(self._h, n_epochs, batch, seed, o.ctypes.data_as(ctypes.c_void_p)))
+
+    def run_minibatch(self, positions):
+        """One minibatch step over exactly these (distinct) positions; the epoch counter is kept."""
+        a = np.ascontiguousarray(positions, dtype=np.int32).ravel()
+        _check(self.lib.magpie_run_minibatch(self._h, int(a.size), a.ctypes.data_as(ctypes.c_void_p)))
 
     def objective(self):
         phi, st = ctypes.c_double(), ctypes.c_double()

@@ -3,6 +3,7 @@
 // goes through every entry point once, with several flag combinations and the
 // error paths, on a small reconstruction.  Exit status 0 when every call
 // returned what it should; a memory error aborts the run with ASan's report.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -116,6 +117,13 @@ int main() {
   std::vector<int32_t> order(N);
   expect(magpie_permutation(5, 0, N, order.data()), MAGPIE_OK, "permutation");
   expect(magpie_run_epochs(c, 1, N, 0, order.data()), MAGPIE_OK, "run_epochs order");
+  expect(magpie_run_minibatch(c, std::min(N, 5), order.data()), MAGPIE_OK, "run_minibatch");
+  expect(magpie_run_minibatch(c, N, order.data()), MAGPIE_OK, "run_minibatch all");
+  {
+    std::vector<int32_t> twice = {order[0], order[0]};
+    expect(magpie_run_minibatch(c, 2, twice.data()), MAGPIE_ERR_INVALID_ARG, "run_minibatch repeated");
+    expect(magpie_run_minibatch(c, N + 1, order.data()), MAGPIE_ERR_INVALID_ARG, "run_minibatch too many");
+  }
   std::vector<double> u((size_t)m * m, 0.1);
   expect(magpie_set_regularization(c, 0.0, u.data()), MAGPIE_OK, "set_regularization u");
   expect(magpie_set_regularization(c, 0.5, nullptr), MAGPIE_OK, "set_regularization alpha");

@@ -60,6 +60,7 @@ class Case:
         self.z0 = self.z0_32.astype(np.complex128)
         ill = oracle.illumination((n_rows, n_cols), self.Q, self.offs)
         self.mask = ill >= 0.1 * ill.max()
+        self.covered = covered_pixels((n_rows, n_cols), m, self.offs)
 
     @property
     def n_pos(self):
@@ -81,3 +82,21 @@ class Case:
 
     def rel(self, a, b):
         return float(np.linalg.norm((a - b)[self.mask]) / np.linalg.norm(b[self.mask]))
+
+    def rel_max(self, a, b):
+        """Element-wise bound, unmasked: max |a - b| over every pixel any window covers
+        (where the update's denominator is positive), relative to max |b| there."""
+        return elementwise_rel(a, b, self.covered)
+
+
+def covered_pixels(shape, m, offs):
+    """Pixels inside at least one m x m window."""
+    cov = np.zeros(shape, dtype=bool)
+    for r, c in offs:
+        cov[r:r + m, c:c + m] = True
+    return cov
+
+
+def elementwise_rel(a, b, covered):
+    d = np.abs(np.asarray(a) - np.asarray(b))[covered]
+    return float(d.max() / np.abs(np.asarray(b)[covered]).max())

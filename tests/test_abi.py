@@ -52,8 +52,14 @@ def test_create_rejects_bad_arguments_before_touching_a_device():
     assert lib.magpie_create(ctypes.byref(h), 16, 64, 32, 2, 0.5, 0, None) == -1   # object < probe
     assert lib.magpie_create(ctypes.byref(h), 64, 64, 32, 2, -1.0, 0, None) == -1  # alpha < 0
     assert lib.magpie_create(None, 64, 64, 32, 2, 0.5, 0, None) == -1
+    # objects of 2^32 bytes or more (complex64) do not fit the kernels' 32-bit buffer ranges
+    assert lib.magpie_create(ctypes.byref(h), 1 << 14, 1 << 15, 64, 3, 0.5, 0, None) == -6   # exactly 2^32 B
+    assert b"2^32" in lib.magpie_last_error()
+    assert lib.magpie_create(ctypes.byref(h), 23171, 23171, 128, 4, 0.5, 0, None) == -6      # just above
+    assert not h.value
     # NULL context is rejected by every entry point that takes one
     assert lib.magpie_run_epochs(None, 1, 1, 0, None) == -1
+    assert lib.magpie_run_minibatch(None, 1, None) == -1
     assert lib.magpie_destroy(None) == 0
 
 

@@ -6,15 +6,20 @@ The plan and tile height are the autotuner's, as in the benchmark.
 Intensities come from the oracle's forward model of the true object, with
 Poisson noise, rounded to FP32.
 
-Per step (the gated tolerance, 1e-5 relative): minibatch t of the epoch's
-order is run on the GPU from the oracle's own object after t minibatches
-(rounded to complex64) -- a context holding exactly that minibatch's 256
-positions, so one epoch is that one minibatch -- and compared with the
-oracle's step from the same object.  The 1024 x 1024 flat-start step is
-bounded by the FP32 floor of an independent single-precision computation
-instead (it lies above 1e-5 on these data).  Whole epoch (512 x 512, 7 minibatches,
-flat start): FP32 rounding accumulates through 7 dependent steps, bounded at
-2e-4; the objective of the oracle's object is compared at 1e-5.
+Per step (the gated tolerance, 1e-5 relative in the masked norm; element-wise over
+every covered pixel, 1e-5 of the largest value or twice the element-wise FP32 floor of
+the same step, whichever is larger):
+minibatch t of the epoch's order is run on the GPU (magpie_run_minibatch, in the
+context holding all 1600 or 6400 positions, so the accumulation screens every
+position overlapping each tile as in production) from the oracle's own object
+after t minibatches (rounded to complex64), and compared with the oracle's step
+from the same object.  The 1024 x 1024 flat-start step is bounded by the FP32
+floor of an independent single-precision computation instead (it lies above 1e-5
+on these data): a tolerance the FP32 pipeline does not meet there.  Whole epoch
+(512 x 512, 7 minibatches, flat start): FP32 rounding accumulates through 7
+dependent steps, bounded at 2e-4; the objective of the oracle's object is compared
+at 1e-5.  Fifty epochs from the flat start with identical permutations: the
+objective (eq. 2.1) of the two trajectories agrees to 1e-4.
 """
 
 import numpy as np
@@ -52,15 +57,20 @@ def _rel(a, b, mask):
     return float(np.linalg.norm((a - b)[mask]) / np.linalg.norm(b[mask]))
 
 
-def _fp32_fft_step_error(cfg, Q32, offs, sd32, chunk, mask):
-    """Relative error of a one-level step whose FFTs run in single precision (SciPy's
-    complex64 transforms, an implementation independent of the HIP path) against the FP64
-    oracle, from the flat object: the FP32 floor of that step on these data."""
+def _relx(a, b, cfg, offs):
+    from gpu_cases import covered_pixels, elementwise_rel
+    return elementwise_rel(a, b, covered_pixels((cfg.n, cfg.n), cfg.m, offs))
+
+
+def _fp32_fft_step_errors(cfg, Q32, offs, sd32, chunk, z0, mask):
+    """Relative errors (masked norm, element-wise over covered pixels) of a one-level
+    step whose FFTs run in single precision (SciPy's complex64 transforms, an
+    implementation independent of the HIP path) against the FP64 oracle's step from the
+    same object z0: the FP32 floor of that step on these data."""
     import scipy.fft as sf
     m = cfg.m
     Q = Q32.astype(np.complex128)
     u = oracle.u_rpie(Q, cfg.alpha)
-    z0 = np.ones((cfg.n, cfg.n), dtype=np.complex128)
     zo = oracle.minibatch_step(z0, Q, offs, sd32.astype(np.float64), u, 1, chunk)
     w0 = u + np.abs(Q) ** 2
     num = np.zeros(z0.shape, dtype=np.complex128)
@@ -77,38 +87,46 @@ def _fp32_fft_step_error(cfg, Q32, offs, sd32, chunk, mask):
     zf = z0.copy()
     pos = den > 0
     zf[pos] += num[pos] / den[pos]
-    return _rel(zf, zo, mask)
+    return _rel(zf, zo, mask), _relx(zf, zo, cfg, offs)
 
 
-def test_full_size_flat_start_step_within_fp32_floor():
+@pytest.mark.parametrize("levels", [1, 4])
+def test_full_size_flat_start_step_within_fp32_floor(levels):
     """1024 x 1024, 128 x 128 probe, 1e5 photons, first step from the flat object: many
     far-field pixels carry a model amplitude ~1e-6 of the peak, whose phase any FP32 FFT
-    gets from rounding, so the step's FP32 floor lies above 1e-5.  The GPU's one-level step
-    must stay within 1.5x the floor of an independent single-precision computation."""
+    gets from rounding, so the step's FP32 floor lies above 1e-5.  The GPU's step (one
+    grid, and the workload's four) must stay within 1.5x the floor of an independent
+    single-precision computation of the one-grid step (the rounding sits in the
+    transforms, which every depth shares)."""
     cfg, Q32, offs, sd32, order, mask = _problem(3)
     chunk = order[:cfg.batch]
-    floor = _fp32_fft_step_error(cfg, Q32, offs, sd32, chunk, mask)
     Q = Q32.astype(np.complex128)
     u = oracle.u_rpie(Q, cfg.alpha)
     z0 = np.ones((cfg.n, cfg.n), dtype=np.complex128)
-    zo = oracle.minibatch_step(z0, Q, offs, sd32.astype(np.float64), u, 1, chunk)
+    floor, floor_x = _fp32_fft_step_errors(cfg, Q32, offs, sd32, chunk, z0, mask)
+    zo = oracle.minibatch_step(z0, Q, offs, sd32.astype(np.float64), u, levels, chunk)
     from paper_2504_10118_amd import Magpie
-    g = Magpie(cfg.n, cfg.n, cfg.m, 1, cfg.alpha)
+    g = Magpie(cfg.n, cfg.n, cfg.m, levels, cfg.alpha)
     g.set_probe(Q32)
-    g.set_positions(offs[chunk])
-    g.load_intensities(sd32[chunk], is_sqrt=True)
+    g.set_positions(offs)
+    g.load_intensities(sd32, is_sqrt=True)
     g.set_object(z0.astype(np.complex64))
-    g.run_epochs(1, cfg.batch, order=np.arange(len(chunk), dtype=np.int32)[None, :])
-    rel = _rel(g.get_object().astype(np.complex128), zo, mask)
+    g.run_minibatch(chunk)
+    zg = g.get_object().astype(np.complex128)
     g.close()
-    print(f"flat-start step: GPU rel {rel:.2e}, FP32 floor {floor:.2e}", flush=True)
+    rel = _rel(zg, zo, mask)
+    relx = _relx(zg, zo, cfg, offs)
+    print(f"flat-start step L={levels}: GPU rel {rel:.2e} (element-wise {relx:.2e}), FP32 floor {floor:.2e} "
+          f"(element-wise {floor_x:.2e})", flush=True)
     assert rel <= max(1e-5, 1.5 * floor)
+    assert relx <= max(1e-5, 2.0 * floor_x)
 
 
 @pytest.mark.parametrize("cfg_id,first,steps", [(2, 0, 3), (3, 1, 3)])
 def test_full_size_steps_match_oracle(cfg_id, first, steps):
     """Steps t = first .. steps-1 of the epoch, each from the oracle's object after t steps
-    (the 1024 x 1024 case starts after its flat-start step, which the FP32 floor test covers)."""
+    (the 1024 x 1024 case starts after its flat-start step, which the FP32 floor test covers),
+    one minibatch at a time in the context of all positions."""
     cfg, Q32, offs, sd32, order, mask = _problem(cfg_id)
     Q = Q32.astype(np.complex128)
     u = oracle.u_rpie(Q, cfg.alpha)
@@ -117,19 +135,24 @@ def test_full_size_steps_match_oracle(cfg_id, first, steps):
     for t in range(first):
         z = oracle.minibatch_step(z.astype(np.complex64).astype(np.complex128), Q, offs, sd, u, cfg.levels,
                                   order[t * cfg.batch:(t + 1) * cfg.batch])
+    g = _gpu(cfg, Q32, offs, sd32, z)
+    tuning = g.get_tuning()
     for t in range(first, steps):
         chunk = order[t * cfg.batch:(t + 1) * cfg.batch]
         z_in = z.astype(np.complex64).astype(np.complex128)
         zo = oracle.minibatch_step(z_in, Q, offs, sd, u, cfg.levels, chunk)
-        g = _gpu(cfg, Q32, offs[chunk], sd32[chunk], z_in)
-        g.run_epochs(1, cfg.batch, order=np.arange(len(chunk), dtype=np.int32)[None, :])
+        g.set_object(z_in.astype(np.complex64))
+        g.run_minibatch(chunk)
         zg = g.get_object().astype(np.complex128)
-        tuning = g.get_tuning()
-        g.close()
         rel = _rel(zg, zo, mask)
-        print(f"cfg {cfg_id} minibatch {t}: plan {tuning}, rel {rel:.2e}", flush=True)
+        relx = _relx(zg, zo, cfg, offs)
+        _, floor_x = _fp32_fft_step_errors(cfg, Q32, offs, sd32, chunk, z_in, mask)
+        print(f"cfg {cfg_id} minibatch {t}: plan {tuning}, rel {rel:.2e}, element-wise {relx:.2e} "
+              f"(FP32 floor {floor_x:.2e})", flush=True)
         assert rel <= 1e-5
+        assert relx <= max(1e-5, 2.0 * floor_x)
         z = zo
+    g.close()
 
 
 def test_full_size_epoch_and_objective():
@@ -151,3 +174,27 @@ def test_full_size_epoch_and_objective():
     print(f"objective {phi_g:.6e} vs {phi_o:.6e}", flush=True)
     assert abs(phi_g - phi_o) <= 1e-5 * phi_o
     g.close()
+
+
+def test_full_size_objective_after_50_epochs():
+    """512 x 512, 64 x 64 probe, 3 levels, minibatch 256, 1e4 photons: 50 epochs from the
+    flat start with the same explicit permutations on both sides; the objective (eq. 2.1,
+    FP64 reduction) of the GPU's object and of the oracle's object agree to 1e-4."""
+    cfg, Q32, offs, sd32, _, mask = _problem(2)
+    epochs = 50
+    orders = np.stack([oracle.library_permutation(41, e, cfg.n_pos) for e in range(epochs)])
+    g = _gpu(cfg, Q32, offs, sd32, np.ones((cfg.n, cfg.n)))
+    g.run_epochs(epochs, cfg.batch, order=orders)
+    phi_g, stat_g = g.objective()
+    zg = g.get_object().astype(np.complex128)
+    g.close()
+    Q = Q32.astype(np.complex128)
+    sd = sd32.astype(np.float64)
+    u = oracle.u_rpie(Q, cfg.alpha)
+    zo = oracle.run_epochs(np.ones((cfg.n, cfg.n)), Q, offs, sd, u, cfg.levels, orders, cfg.batch)
+    phi_o = oracle.objective(zo, Q, offs, sd)
+    phi_0 = oracle.objective(np.ones((cfg.n, cfg.n)), Q, offs, sd)
+    drift = _rel(zg, zo, mask)
+    print(f"50 epochs: phi gpu {phi_g:.8e} oracle {phi_o:.8e} (start {phi_0:.4e}), rel {abs(phi_g - phi_o) / phi_o:.2e}, "
+          f"object drift {drift:.2e}", flush=True)
+    assert abs(phi_g - phi_o) <= 1e-4 * phi_o
