@@ -169,6 +169,26 @@ int magpie_run_epochs(magpie_ctx* ctx, int n_epochs, int batch, uint64_t seed,
 int magpie_run_minibatch(magpie_ctx* ctx, int count, const int32_t* positions);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the epochs of
+ * magpie_run_epochs with order = NULL (the library's seeded permutations, seed
+ * XOR epoch counter), with the same results bit for bit, without any device or
+ * pinned-host allocation.  The per-call buffers (the minibatch staging, 8 m^2
+ * bytes per position of a minibatch, and each epoch's position records and
+ * inverse permutation, 20 bytes per position) live in a 16 MiB device array of
+ * the library, one per GPU, held until the process ends; its address is resolved
+ * when a context is created on that GPU.  Epochs are processed in chunks whose
+ * records fit beside the staging; their permutations are drawn on the device.
+ * Nothing in the array needs to start cleared, and it keeps the last call's
+ * contents: calls that overlap on one GPU (contexts on different streams) race
+ * and must be serialised by the caller.  MAGPIE_GRAPH is ignored (kernels are
+ * launched directly) and timing is not recorded.  Asynchronous.
+ * Errors: INVALID_ARG, BAD_STATE, UNSUPPORTED (MAGPIE_UPDATE_PROBE set; more
+ * than 16384 positions; staging plus one epoch's records above 16 MiB), HIP.
+ */
+int magpie_run_epochs_noalloc(magpie_ctx* ctx, int n_epochs, int batch, uint64_t seed);
+
+/*
  * Objective pass over all positions at the current object (eq. 2.1, reported
  * in exit-wave form (1 / (2 m^2)) sum_k || |F(Q z_k)| - sqrt(d_k) ||^2),
  * reduced in FP64 in a fixed order.  grad_stat (nullable) receives the

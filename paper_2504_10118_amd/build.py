@@ -27,7 +27,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libmagpie.so")
 ASAN_DRIVER = os.path.join(LIBDIR, "magpie_asan_driver")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["kernels.hip", "cnn.hip", "capi.cpp", "learned.cpp"]
+SOURCES = ["kernels.hip", "cnn.hip", "capi.cpp", "learned.cpp", "noalloc.hip"]
 ARCH = os.environ.get("MAGPIE_OFFLOAD_ARCH", "gfx950")
 ASAN_FLAGS = ["-gline-tables-only", "-Xarch_host", "-fsanitize=address",
               "-Xarch_host", "-fno-omit-frame-pointer"]

@@ -144,6 +144,7 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   c->alpha = alpha;
   c->rb = mg::default_plan(m);
   int rc = set_dev(c);
+  if (!rc) rc = noalloc_init_device(device);
   if (rc) { delete c; return rc; }
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
     c->n_cu = 256;
@@ -521,9 +522,14 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
   return MAGPIE_OK;
 }
 
+}  // extern "C"
+
 // Launches n_epochs prepared epochs of minibatch size B (the first
-// batches_per_epoch minibatches of each; the rest are not run).
-static int launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoch, bool allow_graph) {
+// batches_per_epoch minibatches of each; the rest are not run) on the buffers
+// `buf` (the context's own, or the caller-free scratch of the no-allocation entry
+// point, which passes allow_graph = false and has timing off).
+int mgrt::launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoch, bool allow_graph,
+                        const EpochBuffers& buf) {
   const int N = c->n_pos, m = c->m;
   const int nbatch = std::min((N + B - 1) / B, batches_per_epoch);
   const bool probe_step = (c->flags & MAGPIE_UPDATE_PROBE) != 0;
@@ -536,7 +542,7 @@ static int launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epo
   sa.qtab = c->qtab;
   sa.sqrtd = c->sqrtd;
   sa.offs = c->offs;
-  sa.stage = c->stage;
+  sa.stage = buf.stage;
   sa.u0f = c->u0f;
   sa.lvl = c->lvl;
   sa.levels = c->L;
@@ -591,13 +597,13 @@ static int launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epo
   aa.tile_ptr = c->tile_ptr;
   aa.tile_ent = c->tile_ent;
   aa.batch = B;
-  aa.stage = c->stage;
+  aa.stage = buf.stage;
   aa.offs = c->offs;
   aa.w0f = c->w0f;
   const int n_tiles = c->tiles_x * c->tiles_y;
   const bool use_graph = allow_graph && !c->timing && (c->flags & MAGPIE_GRAPH);
   if (use_graph) {
-    const void* key[4] = {c->posrec, c->inv, c->stage, c->pnum};
+    const void* key[4] = {buf.posrec, buf.inv, buf.stage, c->pnum};
     if (c->g_rb != c->rb || c->g_th != c->th) drop_graph(c);
     if (!c->gexec || c->g_batch != B || std::memcmp(key, c->g_key, sizeof(key)) != 0) {
       drop_graph(c);
@@ -608,9 +614,9 @@ static int launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epo
       sa.epoch_stride = N;
       aa.epoch = c->epoch_ctr;
       aa.epoch_stride = N;
-      aa.inv = c->inv;
+      aa.inv = buf.inv;
       for (int t = 0; t < nbatch && ce == hipSuccess; ++t) {
-        sa.pos = c->posrec + (size_t)t * B;
+        sa.pos = buf.posrec + (size_t)t * B;
         sa.count = std::min(B, N - t * B);
         ce = mg::launch_step(m, c->rb, mg::MODE_STEP, sa, c->stream);
         aa.batch_index = t;
@@ -642,12 +648,12 @@ static int launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epo
   }
   for (int e = 0; e < n_epochs; ++e) {
     for (int t = 0; t < nbatch; ++t) {
-      sa.pos = c->posrec + (size_t)e * N + (size_t)t * B;
+      sa.pos = buf.posrec + (size_t)e * N + (size_t)t * B;
       sa.count = std::min(B, N - t * B);
       int ti = timed_slot(c, 0, sa.count);
       MG_HIP(mg::launch_step(m, c->rb, mg::MODE_STEP, sa, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
                              ti >= 0 ? c->timed[ti].b : nullptr));
-      aa.inv = c->inv + (size_t)e * N;
+      aa.inv = buf.inv + (size_t)e * N;
       aa.batch_index = t;
       ti = timed_slot(c, 1, 0);
       MG_HIP(mg::launch_accumulate(aa, c->th, n_tiles, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
@@ -659,13 +665,15 @@ static int launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epo
   return MAGPIE_OK;
 }
 
+extern "C" {
+
 int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
   if (n_epochs == 0 && batch >= 1) return MAGPIE_OK;
   int rc = prepare_epochs(c, n_epochs, batch, seed, order);
   if (rc) return rc;
   const int B = std::min(batch, c->n_pos);
-  rc = launch_epochs(c, n_epochs, B, (c->n_pos + B - 1) / B, true);
+  rc = launch_epochs(c, n_epochs, B, (c->n_pos + B - 1) / B, true, EpochBuffers{c->stage, c->posrec, c->inv});
   if (rc) return rc;
   c->epoch_index += (uint64_t)n_epochs;
   return MAGPIE_OK;
@@ -693,7 +701,7 @@ int magpie_run_minibatch(magpie_ctx* c, int count, const int32_t* positions) {
     if (!seen[(size_t)k]) order.push_back(k);
   int rc = prepare_epochs(c, 1, count, 0, order.data());
   if (rc) return rc;
-  return launch_epochs(c, 1, count, 1, false);
+  return launch_epochs(c, 1, count, 1, false, EpochBuffers{c->stage, c->posrec, c->inv});
 }
 
 int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {

@@ -177,6 +177,22 @@ inline int set_dev(magpie_ctx* c) {
   return MAGPIE_OK;
 }
 
+// Per-epoch device buffers of the launch loop: staging [B][m][m], position
+// records (k, row, col, 0) [E][N] in processing order, inverse permutations [E][N].
+struct EpochBuffers {
+  float2* stage;
+  const int4* posrec;
+  const int* inv;
+};
+
+// noalloc.hip: resolves the device address of the no-allocation entry point's
+// scratch array on `device` (current), once per device.
+int noalloc_init_device(int device);
+
+// capi.cpp: launches prepared epochs on the given buffers (see there).
+int launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoch, bool allow_graph,
+                  const EpochBuffers& buf);
+
 inline int read_flag(magpie_ctx* c, int* out) {
   int h = 0;
   MG_HIP(hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));

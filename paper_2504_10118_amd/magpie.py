@@ -51,6 +51,7 @@ def _bind(lib):
         "magpie_set_object": (i, [vp, vp, i, i]),
         "magpie_run_epochs": (i, [vp, i, i, u64, vp]),
         "magpie_run_minibatch": (i, [vp, i, vp]),
+        "magpie_run_epochs_noalloc": (i, [vp, i, i, u64]),
         "magpie_objective": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(d)]),
         "magpie_get_step_phi": (i, [vp, vp]),
         "magpie_get_object": (i, [vp, vp, i, i]),
@@ -245,6 +246,10 @@ class Magpie:
         else:
             o = np.ascontiguousarray(order, dtype=np.int32).reshape(n_epochs, self.n_pos)
             _check(self.lib.magpie_run_epochs(self._h, n_epochs, batch, seed, o.ctypes.data_as(ctypes.c_void_p)))
+
+    def run_epochs_noalloc(self, n_epochs: int, batch: int, seed: int = 0):
+        """run_epochs with the library's permutations, taking no device allocation (fixed scratch)."""
+        _check(self.lib.magpie_run_epochs_noalloc(self._h, n_epochs, batch, seed))
 
     def run_minibatch(self, positions):
         """One minibatch step over exactly these (distinct) positions; the epoch counter is kept."""

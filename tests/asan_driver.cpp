@@ -117,6 +117,7 @@ int main() {
   std::vector<int32_t> order(N);
   expect(magpie_permutation(5, 0, N, order.data()), MAGPIE_OK, "permutation");
   expect(magpie_run_epochs(c, 1, N, 0, order.data()), MAGPIE_OK, "run_epochs order");
+  expect(magpie_run_epochs_noalloc(c, 2, 7, 11), MAGPIE_OK, "run_epochs_noalloc");
   expect(magpie_run_minibatch(c, std::min(N, 5), order.data()), MAGPIE_OK, "run_minibatch");
   expect(magpie_run_minibatch(c, N, order.data()), MAGPIE_OK, "run_minibatch all");
   {
@@ -134,6 +135,7 @@ int main() {
   expect(magpie_run_epochs(c, 2, 5, 3, nullptr), MAGPIE_OK, "run_epochs all flags");
   expect(magpie_run_epochs(c, 3, 40, 3, nullptr), MAGPIE_OK, "run_epochs larger batch");
   expect(magpie_set_flags(c, MAGPIE_UPDATE_PROBE, 0.3), MAGPIE_OK, "set_flags probe");
+  expect(magpie_run_epochs_noalloc(c, 1, 5, 3), MAGPIE_ERR_UNSUPPORTED, "run_epochs_noalloc with probe step");
   expect(magpie_run_epochs(c, 1, 5, 3, nullptr), MAGPIE_OK, "run_epochs probe");
   expect(magpie_set_flags(c, 0, 0.0), MAGPIE_OK, "set_flags none");
   expect(magpie_sync(c), MAGPIE_OK, "sync");
