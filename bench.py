@@ -11,9 +11,13 @@ Prints one JSON line.  ``value`` is from the timed region, which runs the
 production path.  ``roofline`` covers the per-position step kernel (the
 dominant kernel): the same epochs are run a second time with HIP events
 recorded by each launch's own dispatch on the context's stream, and the
-algorithmic bytes per launch are divided by the mean event duration.
-``cpu_baseline`` times the FP64 oracle on a bounded sample of the same
-workload on the host cores.
+algorithmic bytes of a full launch (one whole minibatch) are divided by the
+mean duration of the full launches; ``roofline.pipeline`` divides the whole
+epoch's algorithmic bytes (patterns, staging and object updates) by the timed
+wall time.  The default run (the 512 x 512 workload) also reports the
+1024 x 1024 workload and the 64-reconstruction workload as extra keys, and
+``cpu_baseline`` times the FP64 oracle on bounded samples of the same workloads
+on the host cores (all usable cores, and one).
 """
 
 from __future__ import annotations
@@ -30,6 +34,7 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
+ACC_TILE_W = 32           # accumulation tile width of the library (columns)
 
 
 def kernel_source_hash() -> str:
@@ -96,36 +101,98 @@ def host_cpu_name() -> str:
     return cpu
 
 
-def oracle_intensities(z_true, Q, offs, peak, rng):
-    """sqrt of Poisson counts of the oracle's own forward model (inputs of the CPU baseline)."""
+def usable_cores() -> int:
+    """Host cores this process may use, capped at 16 (a one-GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def coverage_per_batch(offs, n: int, m: int, batch: int, seed: int, epochs: int):
+    """(mean, list) of the number of distinct object pixels a minibatch covers (cov(B)),
+    over the minibatches of the first `epochs` epochs of the library's permutations."""
     import oracle
-    from synth import poisson_counts
-    dt = oracle.forward_model(np.asarray(z_true, dtype=np.complex128), np.asarray(Q, dtype=np.complex128), offs)
-    return np.sqrt(poisson_counts(dt, peak, rng))
+    covs = []
+    for e in range(epochs):
+        order = oracle.library_permutation(seed, e, len(offs))
+        for b in oracle.batches(order, batch):
+            mask = np.zeros((n, n), dtype=bool)
+            for k in b:
+                r, c = offs[k]
+                mask[r:r + m, c:c + m] = True
+            covs.append(int(mask.sum()))
+    return float(np.mean(covs)), covs
 
 
-def cpu_baseline(n, Q, offs, sqrt_d, levels, batch, alpha, seed, seconds):
-    """The oracle (literal Alg 3, minibatch combination) on whole minibatches of epoch 0 until `seconds` pass.
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle, unchanged, on whole minibatches of epoch 0
+# ---------------------------------------------------------------------------
+_CPU = {}
+
+
+def _cpu_minibatch(args):
+    import oracle
+    i, = args
+    d = _CPU
+    chunk = d["chunks"][i % len(d["chunks"])]
+    oracle.minibatch_step(d["z"], d["Q"], d["offs"], d["sqrt_d"], d["u"], d["levels"], chunk)
+    return len(chunk)
+
+
+def cpu_baseline(n, Q, offs, sqrt_d, levels, batch, alpha, seed, seconds, workers=1):
+    """The oracle (literal Alg 3, minibatch combination) on whole minibatches of epoch 0
+    from the flat object, for about `seconds` of wall time, on `workers` processes each
+    running the unchanged oracle on its own minibatches.
 
     Returns (patterns, seconds, minibatches)."""
     import oracle
-    Q = np.asarray(Q, dtype=np.complex128)
-    u = oracle.u_rpie(Q, alpha)
-    z = np.ones((n, n), dtype=np.complex128)
+    Qd = np.asarray(Q, dtype=np.complex128)
     order = oracle.library_permutation(seed, 0, len(offs))
-    done = 0
-    nb = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        for chunk in oracle.batches(order, batch):
-            z = oracle.minibatch_step(z, Q, offs, sqrt_d, u, levels, chunk)
-            done += len(chunk)
+    _CPU.update(z=np.ones((n, n), dtype=np.complex128), Q=Qd, offs=offs, sqrt_d=sqrt_d,
+                u=oracle.u_rpie(Qd, alpha), levels=levels, chunks=oracle.batches(order, batch))
+    if workers <= 1:
+        done = nb = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            done += _cpu_minibatch((nb,))
             nb += 1
-            if time.perf_counter() - t0 >= seconds:
-                break
-    return done, time.perf_counter() - t0, nb
+        return done, time.perf_counter() - t0, nb
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(_cpu_minibatch, [(i,) for i in range(workers)])       # warm the workers
+        # size the sample from a timed round: one minibatch per worker
+        t0 = time.perf_counter()
+        done = sum(pool.map(_cpu_minibatch, [(i,) for i in range(workers)]))
+        t_round = time.perf_counter() - t0
+        rounds = max(1, int(seconds / max(t_round, 1e-3)) - 1)
+        nb = workers * (rounds + 1)
+        done += sum(pool.map(_cpu_minibatch, [(i,) for i in range(workers, workers * (rounds + 1))]))
+        dt = time.perf_counter() - t0
+    return done, dt, nb
 
 
+def cpu_baselines(cfg_id, seconds_multi, seconds_single, seed):
+    """Oracle patterns/s on a workload: all usable cores and one core."""
+    import oracle
+    from synth import CONFIGS, make_problem_inputs, poisson_counts
+    cfg = CONFIGS[cfg_id]
+    z, Q, offs, r_noise, _ = make_problem_inputs(cfg)
+    Q32 = Q.astype(np.complex64)
+    d = oracle.forward_model(z.astype(np.complex64).astype(np.complex128), Q32.astype(np.complex128), offs)
+    sd = np.sqrt(poisson_counts(d, cfg.peak, r_noise) if cfg.peak else d).astype(np.float32).astype(np.float64)
+    out = {}
+    for key, workers, secs in (("all_cores", usable_cores(), seconds_multi), ("one_core", 1, seconds_single)):
+        done, dt, nb = cpu_baseline(cfg.n, Q32, offs, sd, cfg.levels, cfg.batch, cfg.alpha, seed, secs, workers)
+        out[key] = {"value": done / dt, "cores": workers, "patterns": done, "minibatches": nb, "seconds": dt}
+    return cfg, out
+
+
+# ---------------------------------------------------------------------------
+# GPU runs
+# ---------------------------------------------------------------------------
 def learned_race(n_objects: int):
     """Wall time to 1e-3 relative object error, flat vs learned start (noiseless data)."""
     import torch
@@ -166,16 +233,136 @@ def learned_race(n_objects: int):
     }
 
 
-def bench_batched(args):
+def run_single(cfg_id, steps, warmup, seed, batch=None, levels=None, alpha=None, tuning="", autotune=True,
+               device_noise=False):
+    """One reconstruction of workload cfg_id: timed epochs (production path), then the
+    same epochs with per-launch events.  Returns a dict of figures."""
+    import torch
+    from paper_2504_10118_amd import Magpie
+    from synth import poisson_counts, poisson_counts_device
+
+    cfg, z_true, Q32, offs, r_noise = workload_inputs(cfg_id)
+    batch = batch or cfg.batch
+    levels = levels or cfg.levels
+    alpha = cfg.alpha if alpha is None else alpha
+    m, N, n = cfg.m, cfg.n_pos, cfg.n
+    B = min(batch, N)
+
+    ctx = Magpie(n, n, m, levels, alpha, device=0)
+    ctx.set_probe(Q32)
+    ctx.set_positions(offs)
+    if device_noise:
+        dt = torch.empty((N, m, m), dtype=torch.float32, device="cuda")
+        ctx.forward_model(z_true, out=dt)                    # GPU forward model
+        torch.cuda.synchronize()
+        d = poisson_counts_device(dt, cfg.peak, 1000 + cfg_id) if cfg.peak else dt
+        torch.cuda.synchronize()
+        tl0 = time.perf_counter()
+        ctx.load_intensities(d, is_sqrt=False)
+        ctx.sync()
+        load_s = time.perf_counter() - tl0
+        ctx._keep_d = None
+        del dt, d
+    else:
+        dtilde = ctx.forward_model(z_true)                   # GPU forward model
+        d = (poisson_counts(dtilde, cfg.peak, r_noise) if cfg.peak else dtilde).astype(np.float32)
+        torch.cuda.synchronize()
+        tl0 = time.perf_counter()
+        ctx.load_intensities(d, is_sqrt=False)               # host -> device, checked (synchronises)
+        load_s = time.perf_counter() - tl0
+    ctx.set_object(np.ones((n, n), dtype=np.complex64))
+    tune = None
+    if tuning:
+        rb, th = (int(x) for x in tuning.split(","))
+        ctx.set_tuning(rb, th)
+        tune = {"threads_per_transform": rb, "tile_rows": th, "source": "--tuning"}
+    elif autotune:
+        rb, th, su, au = ctx.autotune(batch)             # the library's own autotuner, on this data
+        tune = {"threads_per_transform": rb, "tile_rows": th, "trial_step_us": su, "trial_accumulate_us": au}
+    if warmup:
+        ctx.run_epochs(warmup, batch, seed=seed + 1)
+    ctx.sync()
+    # timed region: the production path (no per-kernel events)
+    ctx.set_object(np.ones((n, n), dtype=np.complex64))
+    ctx.epoch_index = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run_epochs(steps, batch, seed=seed)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phi, stat = ctx.objective()
+    tr0 = time.perf_counter()
+    ctx.get_object()                                         # device -> host read-back of the object
+    readback_s = time.perf_counter() - tr0
+
+    # kernel timing: the same epochs again, every launch bracketed by HIP events
+    # that its own dispatch records on the context's stream
+    ctx.set_object(np.ones((n, n), dtype=np.complex64))
+    ctx.epoch_index = 0
+    ctx.set_timing(True)
+    ctx.get_timing()                                         # reset
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.run_epochs(steps, batch, seed=seed)
+    step_us, step_pos = ctx.launch_times(0)                  # synchronises
+    acc_us, _ = ctx.launch_times(1)
+    tm = ctx.get_timing()                                    # sums; resets
+    t3 = time.perf_counter()
+    rb_used, th_used = ctx.get_tuning()
+    ctx.close()
+
+    wall = t1 - t0
+    patterns = steps * N
+    nb = (N + B - 1) // B
+    full = step_pos == B
+    step_full_us = float(step_us[full].mean())
+    bytes_per_pattern = 20 * m * m          # sqrt(d) 4 m^2 + patch read 8 m^2 + staged update 8 m^2
+    achieved = bytes_per_pattern * B / (step_full_us * 1e-6) / 1e9
+    cov_mean, covs = coverage_per_batch(offs, n, m, B, seed, min(steps, 4))
+    # accumulation: full launches are every minibatch of B positions (all but a short last one)
+    acc_full = np.array([(i % nb) < N // B for i in range(len(acc_us))])
+    cov_full = float(np.mean([c for i, c in enumerate(covs) if (i % nb) < N // B]))
+    acc_full_us = float(acc_us[acc_full].mean())
+    acc_bytes = B * 8 * m * m + 16 * cov_full
+    epoch_bytes = N * bytes_per_pattern + 16 * cov_mean * nb
+    n_tiles = ((n + ACC_TILE_W - 1) // ACC_TILE_W) * ((n + th_used - 1) // th_used)
+    return {
+        "cfg": cfg, "batch": batch, "levels": levels, "alpha": alpha, "N": N, "m": m, "n": n, "B": B,
+        "tuning": tune, "rb": rb_used, "th": th_used,
+        "value": patterns / wall, "wall": wall, "ms_per_step": wall * 1e3 / steps,
+        "step_full_us": step_full_us, "step_mean_us": float(step_us.mean()), "step_launches": len(step_us),
+        "achieved": achieved, "bytes_per_pattern": bytes_per_pattern,
+        "acc_full_us": acc_full_us, "acc_launches": len(acc_us), "acc_bytes": acc_bytes, "n_tiles": n_tiles,
+        "cov_mean": cov_mean, "epoch_bytes": epoch_bytes,
+        "event_wall": t3 - t2, "step_ms_sum": tm["step_ms"], "acc_ms_sum": tm["accum_ms"],
+        "load_s": load_s, "readback_s": readback_s, "phi": phi, "stat": stat,
+    }
+
+
+def single_summary(r, steps):
+    """The compact figures of a single-reconstruction run (extra keys)."""
+    pipe = r["epoch_bytes"] * steps / r["wall"] / 1e9
+    return {
+        "workload": describe(r["cfg"], r["batch"], r["levels"], r["alpha"]),
+        "value": r["value"], "unit": "patterns/s", "ms_per_step": r["ms_per_step"], "steps": steps,
+        "step_kernel_full_launch_us": r["step_full_us"], "step_kernel_frac": r["achieved"] / HBM_PEAK_GBS,
+        "accumulate_full_launch_us": r["acc_full_us"],
+        "accumulate_frac": r["acc_bytes"] / (r["acc_full_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "pipeline_frac": pipe / HBM_PEAK_GBS, "tuning": [r["rb"], r["th"]],
+    }
+
+
+def bench_batched(steps, warmup, seed, batch=None, alpha=None, tuning=""):
     """64 independent reconstructions of uneven size advanced together by the
     multi-context entry point (one launch per FFT plan / tile group per round)."""
     import torch
     from paper_2504_10118_amd import Magpie, run_epochs_multi
     from synth import batched_workload, make_batched_inputs, poisson_counts_device
 
-    alpha = 0.5 if args.alpha is None else args.alpha
+    alpha = 0.5 if alpha is None else alpha
     specs = batched_workload()
-    ctxs, batches, first = [], [], None
+    ctxs, batches = [], []
     # torch (noise) and the contexts (forward model, loads) share one stream
     st = torch.cuda.Stream()
     torch.cuda.set_stream(st)
@@ -184,8 +371,8 @@ def bench_batched(args):
         ctx = Magpie(sp.n, sp.n, sp.m, sp.levels, alpha, device=0, stream=st.cuda_stream)
         ctx.set_probe(Q.astype(np.complex64))
         ctx.set_positions(offs)
-        if args.tuning:
-            ctx.set_tuning(*(int(x) for x in args.tuning.split(",")))
+        if tuning:
+            ctx.set_tuning(*(int(x) for x in tuning.split(",")))
         dt = torch.empty((sp.n_pos, sp.m, sp.m), dtype=torch.float32, device="cuda")
         ctx.forward_model(z_true.astype(np.complex64), out=dt)                  # GPU forward model
         ctx.load_intensities(poisson_counts_device(dt, sp.peak, sp.seed), is_sqrt=False)
@@ -194,9 +381,7 @@ def bench_batched(args):
         del dt
         ctx.set_object(np.ones((sp.n, sp.n), dtype=np.complex64))
         ctxs.append(ctx)
-        batches.append(args.batch or sp.batch)
-        if first is None:
-            first = (sp, z_true, Q, offs)
+        batches.append(batch or sp.batch)
     torch.cuda.synchronize()
     total_pos = sum(sp.n_pos for sp in specs)
     bytes_per_epoch = sum(20 * sp.m * sp.m * sp.n_pos for sp in specs)
@@ -207,11 +392,11 @@ def bench_batched(args):
             c.epoch_index = 0
         torch.cuda.synchronize()
 
-    if args.warmup:
-        run_epochs_multi(ctxs, args.warmup, batches, seed=args.seed + 1)
+    if warmup:
+        run_epochs_multi(ctxs, warmup, batches, seed=seed + 1)
     reset()
     t0 = time.perf_counter()
-    run_epochs_multi(ctxs, args.steps, batches, seed=args.seed)
+    run_epochs_multi(ctxs, steps, batches, seed=seed)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # kernel timing pass: dispatch-recorded events on every multi launch
@@ -219,71 +404,67 @@ def bench_batched(args):
     ctxs[0].set_timing(True)
     ctxs[0].get_timing()
     t2 = time.perf_counter()
-    run_epochs_multi(ctxs, args.steps, batches, seed=args.seed)
+    run_epochs_multi(ctxs, steps, batches, seed=seed)
     tm = ctxs[0].get_timing()
     t3 = time.perf_counter()
     ctxs[0].set_timing(False)
     phis = [c.objective()[0] for c in ctxs]
     for c in ctxs:
         c.close()
-
+    torch.cuda.set_stream(torch.cuda.default_stream())
     wall = t1 - t0
     step_s = tm["step_ms"] * 1e-3
-    achieved = args.steps * bytes_per_epoch / step_s / 1e9 if step_s > 0 else None
+    achieved = steps * bytes_per_epoch / step_s / 1e9 if step_s > 0 else None
     ms = [sp.m for sp in specs]
-    out = {
+    return {
+        "specs": specs, "total_pos": total_pos, "value": steps * total_pos / wall, "wall": wall,
+        "ms_per_step": wall * 1e3 / steps, "achieved": achieved,
+        "step_launch_us": tm["step_ms"] * 1e3 / max(1, tm["step_launches"]), "step_launches": tm["step_launches"],
+        "acc_launch_us": tm["accum_ms"] * 1e3 / max(1, tm["accum_launches"]), "acc_launches": tm["accum_launches"],
+        "event_wall": t3 - t2, "step_ms_sum": tm["step_ms"], "acc_ms_sum": tm["accum_ms"],
+        "phi_median": float(np.median(phis)), "alpha": alpha,
+        "workload": (f"cfg4: {len(specs)} independent reconstructions, objects "
+                     f"{min(sp.n for sp in specs)}..{max(sp.n for sp in specs)} px, probes 64 ({ms.count(64)}) "
+                     f"and 128 ({ms.count(128)}), {min(sp.n_pos for sp in specs)}..{max(sp.n_pos for sp in specs)} "
+                     f"positions each ({total_pos} total), Poisson 1e4..1e5 peak photons, L = 3 (m 64) / 4 "
+                     f"(m 128), minibatch min(256, N), alpha {alpha}"),
+    }
+
+
+def batched_summary(r, steps):
+    return {"workload": r["workload"], "value": r["value"], "unit": "patterns/s", "ms_per_step": r["ms_per_step"],
+            "steps": steps, "step_kernel_frac": (r["achieved"] / HBM_PEAK_GBS) if r["achieved"] else None,
+            "step_launch_us": r["step_launch_us"], "accumulate_launch_us": r["acc_launch_us"]}
+
+
+def base_line(metric_value, steps, warmup, ms_per_step):
+    return {
         "metric": "diffraction patterns/s (fused step)",
-        "value": args.steps * total_pos / wall,
+        "value": metric_value,
         "unit": "patterns/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": (f"cfg4: {len(specs)} independent reconstructions, objects "
-                         f"{min(sp.n for sp in specs)}..{max(sp.n for sp in specs)} px, probes 64 ({ms.count(64)}) "
-                         f"and 128 ({ms.count(128)}), {min(sp.n_pos for sp in specs)}..{max(sp.n_pos for sp in specs)} "
-                         f"positions each ({total_pos} total), Poisson 1e4..1e5 peak photons, L = 3 (m 64) / 4 (m 128), "
-                         f"minibatch min(256, N), alpha {alpha}"),
-            "reconstructions": len(specs), "positions": total_pos,
-            "step": f"one epoch of every reconstruction = {total_pos} patterns",
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "step_multi_kernel<64|128, MODE_STEP>",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
-            "bytes_per_pattern": "20 m^2",
-            "avg_launch_us": tm["step_ms"] * 1e3 / max(1, tm["step_launches"]),
-            "launches": tm["step_launches"],
-        },
-        "accumulate_kernel": {
-            "avg_launch_us": tm["accum_ms"] * 1e3 / max(1, tm["accum_launches"]),
-            "launches": tm["accum_launches"],
-        },
-        "event_pass": {"ms_per_step": (t3 - t2) * 1e3 / args.steps,
-                       "step_share": step_s / (t3 - t2), "accumulate_share": tm["accum_ms"] * 1e-3 / (t3 - t2)},
-        "objective_after_median": float(np.median(phis)),
     }
-    if not args.no_cpu_baseline:
-        sp, z_true, Q, offs = first
-        sqrt_d = oracle_intensities(z_true, Q, offs, sp.peak, np.random.default_rng(sp.seed))
-        done, dt, nb = cpu_baseline(sp.n, Q, offs, sqrt_d, sp.levels, args.batch or sp.batch, alpha, args.seed,
-                                    args.cpu_seconds)
-        out["cpu_baseline"] = {
-            "value": done / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
-            "sample": f"reconstruction 0 (object {sp.n}, probe {sp.m}, {sp.n_pos} positions): {nb} minibatches "
-                      f"({done} patterns) of epoch 0, FP64 NumPy single thread, {dt:.1f} s on {host_cpu_name()} "
-                      f"({os.cpu_count()} host cores visible)"}
-    print(json.dumps(out), flush=True)
+
+
+def cpu_line(args, cfg_id):
+    cfg, res = cpu_baselines(cfg_id, args.cpu_seconds, args.cpu_seconds_single, args.seed)
+    a, o = res["all_cores"], res["one_core"]
+    return cfg, {
+        "value": a["value"], "unit": "patterns/s", "cores": a["cores"], "kind": "oracle",
+        "sample": (f"{a['minibatches']} minibatches of {cfg.batch} ({a['patterns']} patterns) of epoch 0 of the "
+                   f"{cfg.n}x{cfg.n} workload from the flat object, the unchanged FP64 NumPy oracle (literal Alg 3) "
+                   f"in {a['cores']} processes (one minibatch each at a time), {a['seconds']:.1f} s on "
+                   f"{host_cpu_name()} ({os.cpu_count()} host cores visible)"),
+        "one_core": {"value": o["value"], "cores": 1, "patterns": o["patterns"], "seconds": o["seconds"]},
+    }
 
 
 def main():
@@ -297,8 +478,11 @@ def main():
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--seed", type=int, default=2504)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="all-core oracle sample (per workload)")
+    ap.add_argument("--cpu-seconds-single", type=float, default=6.0, help="one-core oracle sample (per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-workloads", action="store_true",
+                    help="default run: skip the 1024x1024 and 64-reconstruction extra keys")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT plan and tile height")
     ap.add_argument("--tuning", type=str, default="",
                     help="RB,TH: use this FFT plan (threads per transform) and tile height instead of the autotuner")
@@ -314,10 +498,20 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2504_10118_amd import Magpie
-    from synth import poisson_counts
+    # The oracle's CPU baselines run first, before anything initialises the GPU or
+    # loads the HIP library: their worker processes are forked and must not inherit
+    # GPU state.
+    default_run = args.config == 2 and not args.batch and not args.levels and args.alpha is None
+    cpu = {}
+    if not args.no_cpu_baseline and args.config != 4:
+        _, cpu["main"] = cpu_line(args, args.config)
+        if default_run:
+            for cid in (1, 3):
+                c, line = cpu_line(args, cid)
+                cpu[cid] = {"value": line["value"], "cores": line["cores"], "one_core": line["one_core"]["value"],
+                            "workload": describe(c, c.batch, c.levels, c.alpha)}
 
+    import torch
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
@@ -331,134 +525,91 @@ def main():
         del src, dst
 
     if args.config == 4:
-        return bench_batched(args)
+        r = bench_batched(args.steps, args.warmup, args.seed, args.batch, args.alpha, args.tuning)
+        out = base_line(r["value"], args.steps, args.warmup, r["ms_per_step"])
+        out["config"] = {"workload": r["workload"], "reconstructions": len(r["specs"]), "positions": r["total_pos"],
+                         "step": f"one epoch of every reconstruction = {r['total_pos']} patterns"}
+        out["roofline"] = {
+            "bound": "hbm", "kernel": "step_multi_kernel<64|128, MODE_STEP>", "achieved": r["achieved"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (r["achieved"] / HBM_PEAK_GBS) if r["achieved"] else None, "traffic": None,
+            "bytes_per_pattern": "20 m^2", "avg_launch_us": r["step_launch_us"], "launches": r["step_launches"]}
+        out["accumulate_kernel"] = {"avg_launch_us": r["acc_launch_us"], "launches": r["acc_launches"]}
+        out["event_pass"] = {"ms_per_step": r["event_wall"] * 1e3 / args.steps,
+                             "step_share": r["step_ms_sum"] * 1e-3 / r["event_wall"],
+                             "accumulate_share": r["acc_ms_sum"] * 1e-3 / r["event_wall"]}
+        out["objective_after_median"] = r["phi_median"]
+        print(json.dumps(out), flush=True)
+        return
 
-    cfg, z_true, Q32, offs, r_noise = workload_inputs(args.config)
-    batch = args.batch or cfg.batch
-    levels = args.levels or cfg.levels
-    alpha = cfg.alpha if args.alpha is None else args.alpha
-    m, N = cfg.m, cfg.n_pos
-
-    ctx = Magpie(cfg.n, cfg.n, m, levels, alpha, device=0)
-    ctx.set_probe(Q32)
-    ctx.set_positions(offs)
-    dtilde = ctx.forward_model(z_true)                       # GPU forward model
-    d = poisson_counts(dtilde, cfg.peak, r_noise).astype(np.float32)
-    torch.cuda.synchronize()
-    tl0 = time.perf_counter()
-    ctx.load_intensities(d, is_sqrt=False)                   # host -> device, checked (synchronises)
-    load_s = time.perf_counter() - tl0
-    ctx.set_object(np.ones((cfg.n, cfg.n), dtype=np.complex64))
-    tuning = None
-    if args.tuning:
-        rb, th = (int(x) for x in args.tuning.split(","))
-        ctx.set_tuning(rb, th)
-        tuning = {"threads_per_transform": rb, "tile_rows": th, "source": "--tuning"}
-    elif not args.no_autotune:
-        rb, th, su, au = ctx.autotune(batch)             # the library's own autotuner, on this data
-        tuning = {"threads_per_transform": rb, "tile_rows": th, "trial_step_us": su, "trial_accumulate_us": au}
-    if args.warmup:
-        ctx.run_epochs(args.warmup, batch, seed=args.seed + 1)
-    ctx.sync()
-    # timed region: the production path (no per-kernel events)
-    ctx.set_object(np.ones((cfg.n, cfg.n), dtype=np.complex64))
-    ctx.epoch_index = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.run_epochs(args.steps, batch, seed=args.seed)
-    ctx.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    phi, stat = ctx.objective()
-    tr0 = time.perf_counter()
-    ctx.get_object()                                         # device -> host read-back of the object
-    readback_s = time.perf_counter() - tr0
-
-    # kernel timing: the same epochs again, every launch bracketed by HIP events
-    # that its own dispatch records on the context's stream
-    ctx.set_object(np.ones((cfg.n, cfg.n), dtype=np.complex64))
-    ctx.epoch_index = 0
-    ctx.set_timing(True)
-    ctx.get_timing()                                         # reset
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ctx.run_epochs(args.steps, batch, seed=args.seed)
-    tm = ctx.get_timing()                                    # synchronises
-    t3 = time.perf_counter()
-    ctx_rb, ctx_tile_rows = ctx.get_tuning()
-    ctx.close()
-
-    wall = t1 - t0
-    patterns = args.steps * N
-    value = patterns / wall
-    bytes_per_pattern = 20 * m * m          # sqrt(d) 4 m^2 + patch read 8 m^2 + staged update 8 m^2
-    step_s = tm["step_ms"] * 1e-3
-    achieved = tm["positions"] * bytes_per_pattern / step_s / 1e9 if step_s > 0 else None
-    th_used = ctx_tile_rows
-    n_tiles = ((cfg.n + 63) // 64) * ((cfg.n + th_used - 1) // th_used)
-    traffic = stored_traffic(args.config, m, ctx_rb) if batch == cfg.batch and levels == cfg.levels else None
-    out = {
-        "metric": "diffraction patterns/s (fused step)",
-        "value": value,
-        "unit": "patterns/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": describe(cfg, batch, levels, alpha),
-            "object": cfg.n, "probe": m, "positions": N, "levels": levels, "batch": batch,
-            "step": f"one epoch = {N} patterns in {(N + batch - 1) // batch} minibatches",
-            "tuning": tuning,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": f"step_kernel<{m}, {ctx_rb}, MODE_STEP>",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None if traffic is None else traffic["bytes_per_full_launch"],
-            "traffic_detail": traffic,
-            "algorithmic_bytes_per_full_launch": bytes_per_pattern * min(batch, N),
-            "bytes_per_pattern": bytes_per_pattern,
-            "avg_launch_us": tm["step_ms"] * 1e3 / max(1, tm["step_launches"]),
-            "launches": tm["step_launches"],
-        },
-        "accumulate_kernel": {
-            "avg_launch_us": tm["accum_ms"] * 1e3 / max(1, tm["accum_launches"]),
-            "launches": tm["accum_launches"], "tiles_per_launch": n_tiles,
-        },
-        "event_pass": {
-            "note": "second pass over the same epochs with per-launch HIP events (slower: events serialise dispatch)",
-            "ms_per_step": (t3 - t2) * 1e3 / args.steps,
-            "step_share": step_s / (t3 - t2),
-            "accumulate_share": tm["accum_ms"] * 1e-3 / (t3 - t2),
-        },
-        "pcie_inclusive": {
-            "note": "the same job with the host-buffer boundary crossings added: the measured intensities "
-                    "uploaded (and square-rooted, re-laid out, checked) by magpie_load_intensities, and the "
-                    "object read back; not the value",
-            "value": patterns / (wall + load_s + readback_s),
-            "load_ms": load_s * 1e3, "readback_ms": readback_s * 1e3},
-        "objective_after": phi,
-        "stopping_statistic_after": stat,
+    r = run_single(args.config, args.steps, args.warmup, args.seed, args.batch, args.levels, args.alpha,
+                   args.tuning, not args.no_autotune)
+    cfg, m, B = r["cfg"], r["m"], r["B"]
+    traffic = stored_traffic(args.config, m, r["rb"]) if r["batch"] == cfg.batch and r["levels"] == cfg.levels \
+        else None
+    pipe_achieved = r["epoch_bytes"] * args.steps / r["wall"] / 1e9
+    out = base_line(r["value"], args.steps, args.warmup, r["ms_per_step"])
+    out["config"] = {
+        "workload": describe(cfg, r["batch"], r["levels"], r["alpha"]),
+        "object": cfg.n, "probe": m, "positions": r["N"], "levels": r["levels"], "batch": r["batch"],
+        "step": f"one epoch = {r['N']} patterns in {(r['N'] + B - 1) // B} minibatches",
+        "tuning": r["tuning"],
     }
+    out["roofline"] = {
+        "bound": "hbm",
+        "kernel": f"step_kernel<{m}, {r['rb']}, MODE_STEP>",
+        "achieved": r["achieved"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": r["achieved"] / HBM_PEAK_GBS,
+        "traffic": None if traffic is None else traffic["bytes_per_full_launch"],
+        "traffic_detail": traffic,
+        "algorithmic_bytes_per_full_launch": r["bytes_per_pattern"] * B,
+        "bytes_per_pattern": r["bytes_per_pattern"],
+        "avg_launch_us": r["step_full_us"],
+        "avg_launch_us_note": f"mean over the full launches ({B} patterns); all launches incl. the short last "
+                              f"minibatch: {r['step_mean_us']:.3f} us",
+        "launches": r["step_launches"],
+        "pipeline": {
+            "note": "whole epoch: N * 20 m^2 (sqrt(d), patch, staged update) + 16 B per covered pixel per "
+                    "minibatch (object read + write), measured coverage, over the timed wall time",
+            "bytes_per_epoch": r["epoch_bytes"], "achieved": pipe_achieved, "frac": pipe_achieved / HBM_PEAK_GBS,
+            "bytes_per_pattern": r["epoch_bytes"] / r["N"], "covered_pixels_per_minibatch": r["cov_mean"]},
+    }
+    out["accumulate_kernel"] = {
+        "avg_launch_us": r["acc_full_us"], "launches": r["acc_launches"], "tiles_per_launch": r["n_tiles"],
+        "tile": f"{ACC_TILE_W}x{r['th']}",
+        "algorithmic_bytes_per_full_launch": r["acc_bytes"],
+        "frac": r["acc_bytes"] / (r["acc_full_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "bytes_note": "B * 8 m^2 staged reads + 16 B per covered pixel (object read + write)"}
+    out["event_pass"] = {
+        "note": "second pass over the same epochs with per-launch HIP events (slower: events serialise dispatch)",
+        "ms_per_step": r["event_wall"] * 1e3 / args.steps,
+        "step_share": r["step_ms_sum"] * 1e-3 / r["event_wall"],
+        "accumulate_share": r["acc_ms_sum"] * 1e-3 / r["event_wall"],
+    }
+    out["pcie_inclusive"] = {
+        "note": "the same job with the host-buffer boundary crossings added: the measured intensities "
+                "uploaded (and square-rooted, re-laid out, checked) by magpie_load_intensities, and the "
+                "object read back; not the value",
+        "value": args.steps * r["N"] / (r["wall"] + r["load_s"] + r["readback_s"]),
+        "load_ms": r["load_s"] * 1e3, "readback_ms": r["readback_s"] * 1e3}
+    out["objective_after"] = r["phi"]
+    out["stopping_statistic_after"] = r["stat"]
+    if default_run and not args.no_extra_workloads:
+        r3 = run_single(3, 20, 5, args.seed, device_noise=True)
+        out["cfg3"] = single_summary(r3, 20)
+        out["cfg3"]["noise"] = "Poisson counts drawn on the device (same model)"
+        r4 = bench_batched(3, 1, args.seed)
+        out["cfg4"] = batched_summary(r4, 3)
+        torch.cuda.synchronize()
     if args.race_objects > 0 and args.config == 2:
         out["learned_race"] = learned_race(args.race_objects)
-    if not args.no_cpu_baseline:
-        sqrt_d = oracle_intensities(z_true, Q32, offs, cfg.peak, np.random.default_rng(args.seed))
-        done, dt, nb = cpu_baseline(cfg.n, Q32, offs, sqrt_d, levels, batch, alpha, args.seed, args.cpu_seconds)
-        out["cpu_baseline"] = {
-            "value": done / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nb} minibatches of {batch} ({done} patterns; passes over the minibatches of epoch 0) of "
-                      f"the same workload, FP64 NumPy single thread, {dt:.1f} s on {host_cpu_name()} "
-                      f"({os.cpu_count()} host cores visible)"}
+    if "main" in cpu:
+        out["cpu_baseline"] = cpu["main"]
+        others = {f"cfg{cid}": v for cid, v in cpu.items() if cid != "main"}
+        if others:
+            out["cpu_baseline"]["other_workloads"] = others
     print(json.dumps(out), flush=True)
 
 

@@ -274,6 +274,16 @@ int magpie_get_timing(magpie_ctx* ctx, double* step_ms, double* accum_ms, int64_
                       int64_t* accum_launches, int64_t* positions);
 
 /*
+ * The recorded launches of one kernel (kind 0: step kernel, 1: accumulation
+ * kernel) since timing was last read or enabled, without resetting them:
+ * per-launch durations in microseconds (us) and the positions of each step
+ * launch (positions; 0 for the accumulation), at most cap entries each, in launch
+ * order.  Synchronises.  Returns the number of recorded launches of that kind
+ * (which may exceed cap) or a negative error code.  Errors: INVALID_ARG, HIP.
+ */
+int magpie_get_launch_times(magpie_ctx* ctx, int kind, double* us, int32_t* positions, int cap);
+
+/*
  * Kernel variants (no effect on the mathematics; results agree to FP32
  * rounding).  The step kernel's FFT plan is the number of threads per 1-D
  * transform (each thread then holds m / threads points); the accumulation

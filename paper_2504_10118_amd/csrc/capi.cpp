@@ -180,7 +180,8 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   if (!rc) rc = dev_alloc(&c->flag, 1);
   if (!rc) rc = dev_alloc(&c->red, 4);
   if (!rc) rc = dev_alloc(&c->epoch_ctr, 1);
-  if (!rc && hipEventCreateWithFlags(&c->pin_done, hipEventDisableTiming) != hipSuccess)
+  if (!rc && (hipEventCreateWithFlags(&c->pin_done[0], hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&c->pin_done[1], hipEventDisableTiming) != hipSuccess))
     rc = fail(MAGPIE_ERR_HIP, "hipEventCreate failed");
   if (rc) {
     magpie_destroy(c);
@@ -226,7 +227,6 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->pden);
   dev_free(c->pmax);
   dev_free(c->pacc);
-  dev_free(c->perm);
   dev_free(c->posrec);
   dev_free(c->inv);
   dev_free(c->lrn_sd);
@@ -236,7 +236,8 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->lrn_q);
   dev_free(c->lrn_one);
   if (c->h_pin) hipHostFree(c->h_pin);
-  if (c->pin_done) hipEventDestroy(c->pin_done);
+  for (hipEvent_t ev : c->pin_done)
+    if (ev) hipEventDestroy(ev);
   for (auto& t : c->timed) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);
@@ -410,9 +411,10 @@ int magpie_set_object(magpie_ctx* c, const void* z, int dtype, int on_device) {
   return MAGPIE_OK;
 }
 
-// Checks, staging capacity, and uploads of the epochs' permutations, inverse
-// permutations and position records (k, row, col) in processing order.
-static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
+// Checks and device buffers for minibatches of B positions and the records of
+// rec_epochs epochs (staging, probe-step partials with the flag, position records
+// and inverse permutations), grown as needed.
+static int ensure_epoch_buffers(magpie_ctx* c, int n_epochs, int batch, size_t rec_epochs) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
   if (!c->has_probe || !c->has_pos || !c->has_data)
     return fail(MAGPIE_ERR_BAD_STATE, "set probe, positions and intensities first");
@@ -457,56 +459,93 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
     }
     c->pcap = need_stage;
   }
-  const size_t nperm = (size_t)n_epochs * N;
-  if (nperm > c->perm_cap) {
+  const size_t nrec = rec_epochs * (size_t)N;
+  if (nrec > c->perm_cap) {
     MG_HIP(hipStreamSynchronize(c->stream));
     drop_graph(c);
-    dev_free(c->perm);
     dev_free(c->posrec);
     dev_free(c->inv);
-    rc = dev_alloc(&c->perm, nperm);
-    if (!rc) rc = dev_alloc(&c->inv, nperm);
-    if (!rc) rc = dev_alloc(&c->posrec, nperm);
+    rc = dev_alloc(&c->inv, nrec);
+    if (!rc) rc = dev_alloc(&c->posrec, nrec);
     if (rc) {
-      dev_free(c->perm);
       dev_free(c->inv);
       dev_free(c->posrec);
       c->perm_cap = 0;
       return rc;
     }
-    c->perm_cap = nperm;
+    c->perm_cap = nrec;
   }
-  if (c->pin_pending) {
-    MG_HIP(hipEventSynchronize(c->pin_done));
-    c->pin_pending = false;
-  }
-  if (6 * nperm > c->h_pin_cap) {   // perm, inv, then 4 ints per position record
-    if (c->h_pin) hipHostFree(c->h_pin);
+  return MAGPIE_OK;
+}
+
+// Pinned host area for the records of `epochs` epochs in each of the two slots
+// (inverse permutation, then 4 ints per position record), grown as needed once
+// both slots' uploads are done.
+static int ensure_pinned(magpie_ctx* c, size_t epochs) {
+  const size_t need = 2 * epochs * (size_t)c->n_pos * 5;
+  if (need <= c->h_pin_cap) return MAGPIE_OK;
+  for (int s = 0; s < 2; ++s)
+    if (c->pin_pending[s]) {
+      MG_HIP(hipEventSynchronize(c->pin_done[s]));
+      c->pin_pending[s] = false;
+    }
+  if (c->h_pin) hipHostFree(c->h_pin);
+  c->h_pin = nullptr;
+  c->h_pin_cap = 0;
+  if (hipHostMalloc((void**)&c->h_pin, need * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
     c->h_pin = nullptr;
-    c->h_pin_cap = 0;
-    if (hipHostMalloc((void**)&c->h_pin, 6 * nperm * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
-      c->h_pin = nullptr;
-      return fail(MAGPIE_ERR_OOM, "pinned host allocation failed");
-    }
-    c->h_pin_cap = 6 * nperm;
+    return fail(MAGPIE_ERR_OOM, "pinned host allocation failed");
   }
-  int32_t* hp = c->h_pin;
-  int32_t* hi = c->h_pin + nperm;
-  int32_t* hr = c->h_pin + 2 * nperm;
+  c->h_pin_cap = need;
+  return MAGPIE_OK;
+}
+
+// An explicit order [n_epochs][N] must hold a permutation of 0..N-1 per row.
+static int check_orders(magpie_ctx* c, int n_epochs, const int32_t* order) {
+  const int N = c->n_pos;
+  c->h_seen.assign((size_t)N, 0);
   for (int e = 0; e < n_epochs; ++e) {
-    int32_t* p = hp + (size_t)e * N;
-    int32_t* q = hi + (size_t)e * N;
-    if (order) {
-      std::memcpy(p, order + (size_t)e * N, (size_t)N * sizeof(int32_t));
-    } else {
-      fisher_yates(seed, c->epoch_index + (uint64_t)e, N, p);
+    const int32_t* p = order + (size_t)e * N;
+    for (int i = 0; i < N; ++i) {
+      const int k = p[i];
+      if (k < 0 || k >= N || c->h_seen[(size_t)k] == e + 1)
+        return fail(MAGPIE_ERR_INVALID_ARG, "order row " + std::to_string(e) + " is not a permutation");
+      c->h_seen[(size_t)k] = e + 1;
     }
-    for (int i = 0; i < N; ++i) q[i] = -1;
+  }
+  return MAGPIE_OK;
+}
+
+// Inverse permutations and position records (k, row, col) in processing order of
+// epochs e0 .. e0+ne-1 (permutations from `order`, already checked, or the
+// library's seeded ones for epoch counter c->epoch_index + e), built in pinned
+// slot `slot` (slot_epochs epochs wide) and uploaded to the device records from
+// epoch offset dev_epoch; the slot's event marks the end of its upload.
+static int fill_records(magpie_ctx* c, int e0, int ne, uint64_t seed, const int32_t* order, int slot,
+                        size_t slot_epochs, size_t dev_epoch) {
+  const int N = c->n_pos;
+  // a slot's region moves with its width: then both slots' uploads must be done
+  for (int s = 0; s < 2; ++s)
+    if (c->pin_pending[s] && (s == slot || slot_epochs != c->pin_width)) {
+      MG_HIP(hipEventSynchronize(c->pin_done[s]));
+      c->pin_pending[s] = false;
+    }
+  c->pin_width = slot_epochs;
+  int32_t* hi = c->h_pin + (size_t)slot * slot_epochs * N * 5;
+  int32_t* hr = hi + slot_epochs * N;
+  c->h_perm.resize((size_t)N);
+  for (int e = 0; e < ne; ++e) {
+    const int32_t* p;
+    if (order) {
+      p = order + (size_t)(e0 + e) * N;
+    } else {
+      fisher_yates(seed, c->epoch_index + (uint64_t)(e0 + e), N, c->h_perm.data());
+      p = c->h_perm.data();
+    }
+    int32_t* q = hi + (size_t)e * N;
     int32_t* r = hr + (size_t)e * N * 4;
     for (int i = 0; i < N; ++i) {
       const int k = p[i];
-      if (k < 0 || k >= N || q[k] != -1)
-        return fail(MAGPIE_ERR_INVALID_ARG, "order row " + std::to_string(e) + " is not a permutation");
       q[k] = i;
       r[4 * i] = k;
       r[4 * i + 1] = c->h_offs[2 * (size_t)k];
@@ -514,12 +553,22 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
       r[4 * i + 3] = 0;
     }
   }
-  MG_HIP(hipMemcpyAsync(c->perm, hp, nperm * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-  MG_HIP(hipMemcpyAsync(c->inv, hi, nperm * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-  MG_HIP(hipMemcpyAsync(c->posrec, hr, nperm * sizeof(int4), hipMemcpyHostToDevice, c->stream));
-  MG_HIP(hipEventRecord(c->pin_done, c->stream));
-  c->pin_pending = true;
+  const size_t n = (size_t)ne * N;
+  MG_HIP(hipMemcpyAsync(c->inv + dev_epoch * N, hi, n * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipMemcpyAsync(c->posrec + dev_epoch * N, hr, n * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+  MG_HIP(hipEventRecord(c->pin_done[slot], c->stream));
+  c->pin_pending[slot] = true;
   return MAGPIE_OK;
+}
+
+// Buffers, checks and the records of all n_epochs epochs at once (graph
+// capture, multi-context rounds and single minibatches read them by epoch).
+static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
+  int rc = ensure_epoch_buffers(c, n_epochs, batch, (size_t)n_epochs);
+  if (!rc && order) rc = check_orders(c, n_epochs, order);
+  if (!rc) rc = ensure_pinned(c, (size_t)n_epochs);
+  if (!rc) rc = fill_records(c, 0, n_epochs, seed, order, 0, (size_t)n_epochs, 0);
+  return rc;
 }
 
 }  // extern "C"
@@ -670,11 +719,40 @@ extern "C" {
 int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
   if (n_epochs == 0 && batch >= 1) return MAGPIE_OK;
-  int rc = prepare_epochs(c, n_epochs, batch, seed, order);
+  const bool use_graph = !c->timing && (c->flags & MAGPIE_GRAPH);
+  int rc;
+  if (use_graph) {
+    rc = prepare_epochs(c, n_epochs, batch, seed, order);
+    if (rc) return rc;
+    const int B = std::min(batch, c->n_pos);
+    rc = launch_epochs(c, n_epochs, B, (c->n_pos + B - 1) / B, true, EpochBuffers{c->stage, c->posrec, c->inv});
+    if (rc) return rc;
+    c->epoch_index += (uint64_t)n_epochs;
+    return MAGPIE_OK;
+  }
+  // Direct launches, with the host's part pipelined: the records of the next chunk
+  // of epochs are drawn and uploaded (two pinned slots, two device halves) while
+  // the GPU runs the current chunk.  The first chunk is one epoch, so the first
+  // launch waits for one epoch's records only.
+  constexpr int CH = 8;
+  const size_t ch = (size_t)std::min(CH, n_epochs);
+  rc = ensure_epoch_buffers(c, n_epochs, batch, 2 * ch);
+  if (!rc && order) rc = check_orders(c, n_epochs, order);
+  if (!rc) rc = ensure_pinned(c, ch);
   if (rc) return rc;
-  const int B = std::min(batch, c->n_pos);
-  rc = launch_epochs(c, n_epochs, B, (c->n_pos + B - 1) / B, true, EpochBuffers{c->stage, c->posrec, c->inv});
-  if (rc) return rc;
+  const int N = c->n_pos;
+  const int B = std::min(batch, N);
+  int chunk = 0;
+  for (int e0 = 0; e0 < n_epochs; ++chunk) {
+    const int ne = chunk == 0 ? 1 : std::min(CH, n_epochs - e0);
+    const int slot = chunk & 1;
+    rc = fill_records(c, e0, ne, seed, order, slot, ch, (size_t)slot * ch);
+    if (rc) return rc;
+    const size_t off = (size_t)slot * ch * N;
+    rc = launch_epochs(c, ne, B, (N + B - 1) / B, false, EpochBuffers{c->stage, c->posrec + off, c->inv + off});
+    if (rc) return rc;
+    e0 += ne;
+  }
   c->epoch_index += (uint64_t)n_epochs;
   return MAGPIE_OK;
 }
@@ -895,6 +973,26 @@ int magpie_get_timing(magpie_ctx* c, double* step_ms, double* accum_ms, int64_t*
   *accum_launches = nl[1];
   *positions = pos;
   return MAGPIE_OK;
+}
+
+int magpie_get_launch_times(magpie_ctx* c, int kind, double* us, int32_t* positions, int cap) {
+  if (!c || kind < 0 || kind > 1 || cap < 0 || (cap > 0 && (!us || !positions)))
+    return fail(MAGPIE_ERR_INVALID_ARG, "bad argument");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  MG_HIP(hipStreamSynchronize(c->stream));
+  int n = 0;
+  for (auto& t : c->timed) {
+    if (t.kind != kind) continue;
+    if (n < cap) {
+      float f = 0.0f;
+      MG_HIP(hipEventElapsedTime(&f, t.a, t.b));
+      us[n] = 1e3 * (double)f;
+      positions[n] = t.count;
+    }
+    ++n;
+  }
+  return n;
 }
 
 int magpie_list_plans(int m, int32_t* threads_per_transform, int cap) {

@@ -130,14 +130,17 @@ struct magpie_ctx {
   float* pmax = nullptr;
   double* pacc = nullptr;   // probe step: per-chunk partial sums (mg::probe_scratch_doubles)
   size_t pcap = 0;
-  int* perm = nullptr;   // [E][N]
   int4* posrec = nullptr;  // [E][N] (k, row, col, 0) in processing order
-  int* inv = nullptr;    // [E][N]
-  size_t perm_cap = 0;   // ints per array
+  int* inv = nullptr;    // [E][N] position -> index in its epoch's permutation
+  size_t perm_cap = 0;   // entries per array
+  // pinned host records in two slots (filled while the GPU runs the other one)
   int32_t* h_pin = nullptr;
   size_t h_pin_cap = 0;  // ints
-  hipEvent_t pin_done = nullptr;
-  bool pin_pending = false;
+  size_t pin_width = 0;  // epochs per slot of the last fill
+  hipEvent_t pin_done[2] = {nullptr, nullptr};
+  bool pin_pending[2] = {false, false};
+  std::vector<int32_t> h_perm;   // host scratch: one epoch's permutation
+  std::vector<int> h_seen;       // host scratch: permutation check
 
   // optional per-launch timing
   bool timing = false;

@@ -64,6 +64,7 @@ def _bind(lib):
         "magpie_set_epoch_index": (i, [vp, u64]),
         "magpie_set_timing": (i, [vp, i]),
         "magpie_list_plans": (i, [i, vp, i]),
+        "magpie_get_launch_times": (i, [vp, i, vp, vp, i]),
         "magpie_set_tuning": (i, [vp, i, i]),
         "magpie_get_tuning": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "magpie_autotune": (i, [vp, i, i, ctypes.POINTER(d), ctypes.POINTER(d)]),
@@ -290,6 +291,19 @@ class Magpie:
                                           ctypes.byref(al), ctypes.byref(pos)))
         return {"step_ms": sm.value, "accum_ms": am.value, "step_launches": sl.value,
                 "accum_launches": al.value, "positions": pos.value}
+
+    def launch_times(self, kind: int):
+        """(durations in us, positions) of the recorded launches of the step (0) or
+        accumulation (1) kernel since timing was last read; does not reset them."""
+        n = self.lib.magpie_get_launch_times(self._h, kind, None, None, 0)
+        if n < 0:
+            _check(n)
+        us = np.empty(n, dtype=np.float64)
+        pos = np.empty(n, dtype=np.int32)
+        if n:
+            _check(min(0, self.lib.magpie_get_launch_times(self._h, kind, us.ctypes.data_as(ctypes.c_void_p),
+                                                           pos.ctypes.data_as(ctypes.c_void_p), n)))
+        return us, pos
 
     def set_tuning(self, threads_per_transform: int = 0, tile_rows: int = 0):
         _check(self.lib.magpie_set_tuning(self._h, threads_per_transform, tile_rows))
