@@ -89,6 +89,18 @@ int build_tiles(magpie_ctx* c) {
   c->tiles_x = (c->nc + mg::ACC_TILE_W - 1) / mg::ACC_TILE_W;
   c->tiles_y = (c->nr + c->th - 1) / c->th;
   const int nt = c->tiles_x * c->tiles_y;
+  // the box of tiles some window reaches (the accumulation runs over it only)
+  int r0 = c->nr, r1 = 0, c0 = c->nc, c1 = 0;
+  for (int k = 0; k < n_pos; ++k) {
+    r0 = std::min(r0, offsets[2 * k]);
+    r1 = std::max(r1, offsets[2 * k] + m - 1);
+    c0 = std::min(c0, offsets[2 * k + 1]);
+    c1 = std::max(c1, offsets[2 * k + 1] + m - 1);
+  }
+  c->box_x0 = c0 / mg::ACC_TILE_W;
+  c->box_y0 = r0 / c->th;
+  c->box_nx = c1 / mg::ACC_TILE_W - c->box_x0 + 1;
+  c->box_ny = r1 / c->th - c->box_y0 + 1;
   std::vector<std::vector<int>> lists(nt);
   for (int k = 0; k < n_pos; ++k) {
     const int r = offsets[2 * k], cc = offsets[2 * k + 1];
@@ -643,13 +655,19 @@ int mgrt::launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoc
   aa.n_cols = c->nc;
   aa.m = m;
   aa.tiles_x = c->tiles_x;
+  aa.box_x0 = c->box_x0;
+  aa.box_y0 = c->box_y0;
+  aa.box_nx = c->box_nx;
   aa.tile_ptr = c->tile_ptr;
   aa.tile_ent = c->tile_ent;
   aa.batch = B;
   aa.stage = buf.stage;
   aa.offs = c->offs;
   aa.w0f = c->w0f;
-  const int n_tiles = c->tiles_x * c->tiles_y;
+  const int n_tiles = c->box_nx * c->box_ny;
+  aa.n_tiles = n_tiles;
+  // small minibatches: each tile screens the minibatch's own records
+  const bool scan = B <= mg::ACC_SCAN_MAX;
   const bool use_graph = allow_graph && !c->timing && (c->flags & MAGPIE_GRAPH);
   if (use_graph) {
     const void* key[4] = {buf.posrec, buf.inv, buf.stage, c->pnum};
@@ -669,6 +687,8 @@ int mgrt::launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoc
         sa.count = std::min(B, N - t * B);
         ce = mg::launch_step(m, c->rb, mg::MODE_STEP, sa, c->stream);
         aa.batch_index = t;
+        aa.pos = scan ? sa.pos : nullptr;
+        aa.count = sa.count;
         if (ce == hipSuccess) ce = mg::launch_accumulate(aa, c->th, n_tiles, c->stream);
         if (ce == hipSuccess && alternate) ce = probe_pass();
         if (ce == hipSuccess && probe_step) ce = probe_tail(sa.count);
@@ -704,6 +724,8 @@ int mgrt::launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoc
                              ti >= 0 ? c->timed[ti].b : nullptr));
       aa.inv = buf.inv + (size_t)e * N;
       aa.batch_index = t;
+      aa.pos = scan ? sa.pos : nullptr;
+      aa.count = sa.count;
       ti = timed_slot(c, 1, 0);
       MG_HIP(mg::launch_accumulate(aa, c->th, n_tiles, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
                                    ti >= 0 ? c->timed[ti].b : nullptr));
@@ -1260,6 +1282,9 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
         a.n_cols = c->nc;
         a.m = c->m;
         a.tiles_x = c->tiles_x;
+        a.box_x0 = c->box_x0;
+        a.box_y0 = c->box_y0;
+        a.box_nx = c->box_nx;
         a.tile_ptr = c->tile_ptr;
         a.tile_ent = c->tile_ent;
         a.stage = c->stage;
@@ -1270,7 +1295,11 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
           const int e = r / nb[i], t = r % nb[i];
           a.inv = c->inv + (size_t)e * c->n_pos;
           a.batch_index = t;
-          a.n_tiles = c->tiles_x * c->tiles_y;
+          a.n_tiles = c->box_nx * c->box_ny;
+          if (B[i] <= mg::ACC_SCAN_MAX) {
+            a.pos = c->posrec + (size_t)e * c->n_pos + (size_t)t * B[i];
+            a.count = std::min(B[i], c->n_pos - t * B[i]);
+          }
         } else {
           a.inv = c->inv;
           a.n_tiles = 0;

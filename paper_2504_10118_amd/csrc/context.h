@@ -119,6 +119,7 @@ struct magpie_ctx {
   int* tile_ptr = nullptr;
   int4* tile_ent = nullptr;
   int tiles_x = 0, tiles_y = 0;
+  int box_x0 = 0, box_y0 = 0, box_nx = 0, box_ny = 0;   // tiles some window reaches
   std::vector<int32_t> h_offs;
 
   float2* stage = nullptr;

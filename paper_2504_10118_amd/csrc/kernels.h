@@ -45,10 +45,15 @@ struct StepArgs {
 struct AccumArgs {
   float2* z;              // object, updated in place
   int n_rows, n_cols, m;
-  int tiles_x;            // number of 64-wide tile columns
-  int n_tiles;
-  const int* tile_ptr;    // CSR over tiles: positions overlapping each tile, ascending
+  int tiles_x;            // number of tile columns of the object (ACC_TILE_W wide)
+  int box_x0, box_y0;     // first tile column / row of the box of tiles any window reaches
+  int box_nx;             // tile columns of that box; workgroup b takes box tile b (row-major)
+  int n_tiles;            // tiles of the box (= workgroups)
+  const int* tile_ptr;    // CSR over all tiles: positions overlapping each tile, ascending
   const int4* tile_ent;   // (k, row, col, 0) of each overlapping position
+  const int4* pos;        // nullable: this minibatch's records (k, row, col, 0), `count` of them in processing
+                          // order, screened directly (sums in that order); NULL: the static lists with inv
+  int count;
   const int* inv;         // position -> index in this epoch's permutation
   const int* epoch;       // nullable: inv is advanced by (*epoch) * epoch_stride (graph replays)
   int epoch_stride;
@@ -60,6 +65,8 @@ struct AccumArgs {
 
 constexpr int ACC_TILE_W = 32;   // accumulation tile width (two rows per wave)
 constexpr int ACC_THREADS = 256;
+// minibatches of at most this many positions are screened from their own records
+constexpr int ACC_SCAN_MAX = 256;
 
 // FFT plans (m, rb): rb threads per 1-D transform.  plans_for lists the
 // compiled plans of m, default first.

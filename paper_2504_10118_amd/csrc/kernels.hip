@@ -162,9 +162,14 @@ __device__ __forceinline__ AccumArgs load_accum_args(const AccumArgs* p) {
   a.n_cols = d->n_cols;
   a.m = d->m;
   a.tiles_x = d->tiles_x;
+  a.box_x0 = d->box_x0;
+  a.box_y0 = d->box_y0;
+  a.box_nx = d->box_nx;
   a.n_tiles = d->n_tiles;
   a.tile_ptr = d->tile_ptr;
   a.tile_ent = d->tile_ent;
+  a.pos = d->pos;
+  a.count = d->count;
   a.inv = d->inv;
   a.epoch = d->epoch;
   a.epoch_stride = d->epoch_stride;
@@ -959,14 +964,15 @@ size_t step_lds_bytes(int m, int rb) {
 // rather than branched so that several positions' loads are in flight.
 // ---------------------------------------------------------------------------
 template <int TH>
-__device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int tile) {
+__device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b) {
   constexpr int RPT = TH / (2 * ACC_THREADS / 64);
   constexpr int NW = ACC_THREADS / 64;
   constexpr int U = 4;   // positions whose loads are in flight together
   __shared__ int s_slot[ACC_THREADS];
   __shared__ int2 s_off[ACC_THREADS];
   __shared__ int s_wcnt[NW];
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const int tx = a.box_x0 + b % a.box_nx, ty = a.box_y0 + b / a.box_nx;
+  const int tile = ty * a.tiles_x + tx;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int X = tx * ACC_TILE_W + (lane & 31);
@@ -984,19 +990,35 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int ti
     const int Y = Y0 + 8 * i;
     zo[i] = (X < a.n_cols && Y < a.n_rows) ? a.z[(size_t)Y * a.n_cols + X] : make_float2(0.0f, 0.0f);
   }
-  const int beg = a.tile_ptr[tile], end = a.tile_ptr[tile + 1];
+  // candidates: the minibatch's own records (slot = processing index; a window
+  // overlaps the tile where it reaches both its column and its row range), or the
+  // static list of positions overlapping the tile, kept where the inverse
+  // permutation puts them in this minibatch (slot order = ascending position)
+  const size_t eoff = a.epoch ? (size_t)(*a.epoch) * a.epoch_stride : 0;
+  const bool scan = a.pos != nullptr;
+  const int4* recs = scan ? a.pos + eoff : nullptr;
+  const int x0 = tx * ACC_TILE_W, y0 = ty * TH;
+  const int beg = scan ? 0 : a.tile_ptr[tile], end = scan ? a.count : a.tile_ptr[tile + 1];
   const int lo_idx = a.batch_index * a.batch;
-  const int* inv = a.inv + (a.epoch ? (size_t)(*a.epoch) * a.epoch_stride : 0);
+  const int* inv = a.inv + eoff;
   for (int base = beg; base < end; base += ACC_THREADS) {
     const int idx = base + tid;
     int slot = -1;
     int2 off = make_int2(0, 0);
     if (idx < end) {
-      const int4 te = a.tile_ent[idx];
-      const int s = inv[te.x] - lo_idx;
-      if (s >= 0 && s < a.batch) {
-        slot = s;
-        off = make_int2(te.y, te.z);
+      if (scan) {
+        const int4 pr = recs[idx];
+        if (pr.z < x0 + ACC_TILE_W && pr.z + m > x0 && pr.y < y0 + TH && pr.y + m > y0) {
+          slot = idx;
+          off = make_int2(pr.y, pr.z);
+        }
+      } else {
+        const int4 te = a.tile_ent[idx];
+        const int s = inv[te.x] - lo_idx;
+        if (s >= 0 && s < a.batch) {
+          slot = s;
+          off = make_int2(te.y, te.z);
+        }
       }
     }
     const bool in = slot >= 0;

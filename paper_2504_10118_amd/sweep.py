@@ -219,6 +219,82 @@ def run_blind(config: int = 2, levels=(1, 3), modes=("fixed", "simultaneous", "a
     return out
 
 
+def run_batches(config: int = 2, batches=(256, 400, 800, 1600), levels: int | None = None, alpha: float = 0.5,
+                target: float = 1e-3, max_epochs: int = 20000, noisy_epochs: int = 400, check: int = 10,
+                seed: int = 7, log=print) -> dict:
+    """Wall time to error against the minibatch size B (flat start, the workload's levels):
+    noiseless data until the relative object error reaches `target` (checked every `check`
+    epochs off the clock, at most `max_epochs`), and data with the workload's Poisson noise
+    for `noisy_epochs` epochs, where the error passes through a minimum (the noise floor)
+    before the iteration fits the noise: the epoch and time at which the error first comes
+    within 5 % of that minimum, and at which Phi first comes within 1e-3 of its last value."""
+    from synth import CONFIGS, make_problem_inputs, poisson_counts
+    cfg = CONFIGS[config]
+    L = levels or cfg.levels
+    z_true, Q, offs, _, _ = make_problem_inputs(cfg)
+    Q32 = Q.astype(np.complex64)
+    z32 = z_true.astype(np.complex64)
+    n, m = cfg.n, cfg.m
+    mask = illumination_mask(Q32, offs, n)
+    with Magpie(n, n, m, 1, alpha) as fm:
+        fm.set_probe(Q32)
+        fm.set_positions(offs)
+        dtilde = fm.forward_model(z32)
+    data = {"noiseless": dtilde.astype(np.float32),
+            f"{cfg.peak:g} photons": poisson_counts(dtilde, cfg.peak, np.random.default_rng(seed + 1000))
+            .astype(np.float32)}
+    out = {"config": config, "levels": L, "alpha": alpha, "target": target, "check": check, "runs": []}
+    for label, d in data.items():
+        noiseless = label == "noiseless"
+        for B in batches:
+            with Magpie(n, n, m, L, alpha) as ctx:
+                ctx.set_probe(Q32)
+                ctx.set_positions(offs)
+                ctx.load_intensities(d, is_sqrt=False)
+                ctx.set_object(np.ones((n, n), dtype=np.complex64))
+                ctx.epoch_index = 0
+                ctx.run_epochs(check, B, seed=seed + 99)      # warm the kernels (discarded)
+                ctx.set_object(np.ones((n, n), dtype=np.complex64))
+                ctx.epoch_index = 0
+                ctx.sync()
+                trace, gpu_s, e = [], 0.0, 0
+                limit = max_epochs if noiseless else noisy_epochs
+                while e < limit:
+                    t0 = time.perf_counter()
+                    ctx.run_epochs(check, B, seed=seed)
+                    ctx.sync()
+                    gpu_s += time.perf_counter() - t0
+                    e += check
+                    err, _ = object_errors(ctx.get_object(), z32, mask)
+                    phi, _ = ctx.objective()
+                    trace.append((e, gpu_s, err, phi))
+                    if noiseless and err <= target:
+                        break
+            r = {"data": label, "batch": B, "ms_per_epoch": gpu_s * 1e3 / e, "trace": trace}
+            if noiseless:
+                hit = trace[-1] if trace[-1][2] <= target else None
+                r.update(reached=hit is not None, epochs=hit[0] if hit else None, seconds=hit[1] if hit else None,
+                         final_error=trace[-1][2])
+                log(f"{label} B {B}: {r['ms_per_epoch']:.3f} ms/epoch, error {target:g} "
+                    + (f"at epoch {hit[0]} after {hit[1] * 1e3:.1f} ms" if hit else
+                       f"not reached in {e} epochs (error {trace[-1][2]:.3e})"))
+            else:
+                errs = np.array([t[2] for t in trace])
+                best = int(np.argmin(errs))
+                near = int(np.argmax(errs <= 1.05 * errs[best]))
+                phis = np.array([t[3] for t in trace])
+                plate = int(np.argmax(np.abs(phis - phis[-1]) <= 1e-3 * phis[-1]))
+                r.update(best_error=float(errs[best]), best_epoch=trace[best][0],
+                         near_best_epoch=trace[near][0], near_best_seconds=trace[near][1],
+                         phi_plateau_epoch=trace[plate][0], phi_plateau_seconds=trace[plate][1],
+                         final_phi=float(phis[-1]))
+                log(f"{label} B {B}: {r['ms_per_epoch']:.3f} ms/epoch, best error {errs[best]:.3e} at epoch "
+                    f"{trace[best][0]}, within 5 % of it at epoch {trace[near][0]} ({trace[near][1] * 1e3:.1f} ms), "
+                    f"Phi within 1e-3 of its end at epoch {trace[plate][0]} ({trace[plate][1] * 1e3:.1f} ms)")
+            out["runs"].append(r)
+    return out
+
+
 def table(res: dict, at=None) -> str:
     """Markdown table: relative error at a few checkpoints per (peak, alpha, L)."""
     cps = at or [c for c in res["checkpoints"] if c in (1, 10, 50, 100, 200, 500, 1000)] or res["checkpoints"][-3:]
@@ -251,7 +327,23 @@ def main():
                     help="blind runs instead: the start probe lacks its phase; fixed / simultaneous / alternating "
                          "probe steps at each --levels (default 1,3), --alphas[0], --beta")
     ap.add_argument("--beta", type=float, default=0.5)
+    ap.add_argument("--batches", type=str, default="",
+                    help="comma list of minibatch sizes: wall time to error for each (noiseless: to --target; "
+                         "with the workload's noise: to the error minimum) at the workload's levels and "
+                         "--alphas[0]")
+    ap.add_argument("--target", type=float, default=1e-3)
+    ap.add_argument("--max-epochs", type=int, default=20000)
     a = ap.parse_args()
+    if a.batches:
+        bs = [int(x) for x in a.batches.split(",") if x]
+        lv = [int(x) for x in a.levels.split(",") if x]
+        res = run_batches(a.config, bs, lv[0] if lv else None, float(a.alphas.split(",")[0]), a.target,
+                          a.max_epochs, a.epochs, seed=a.seed)
+        if a.out:
+            os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+            with open(a.out, "w") as f:
+                json.dump(res, f)
+        return
     if a.blind:
         lv = [int(x) for x in a.levels.split(",") if x] or [1, 3]
         res = run_blind(a.config, lv, epochs=a.epochs, beta=a.beta, alpha=float(a.alphas.split(",")[0]),
