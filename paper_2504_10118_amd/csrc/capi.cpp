@@ -756,8 +756,10 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   // of epochs are drawn and uploaded (two pinned slots, two device halves) while
   // the GPU runs the current chunk.  The first chunk is one epoch, so the first
   // launch waits for one epoch's records only.
+  // (buffers sized for a whole chunk from the first call on, so later calls with
+  // more epochs reuse them)
   constexpr int CH = 8;
-  const size_t ch = (size_t)std::min(CH, n_epochs);
+  const size_t ch = (size_t)CH;
   rc = ensure_epoch_buffers(c, n_epochs, batch, 2 * ch);
   if (!rc && order) rc = check_orders(c, n_epochs, order);
   if (!rc) rc = ensure_pinned(c, ch);

@@ -64,7 +64,8 @@ struct AccumArgs {
 };
 
 constexpr int ACC_TILE_W = 32;   // accumulation tile width (two rows per wave)
-constexpr int ACC_THREADS = 256;
+// one pixel per thread: a 32 x TH tile takes 32 TH threads (TH / 2 waves)
+constexpr int acc_threads(int th) { return ACC_TILE_W * th; }
 // minibatches of at most this many positions are screened from their own records
 constexpr int ACC_SCAN_MAX = 256;
 

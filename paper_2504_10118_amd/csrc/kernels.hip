@@ -117,6 +117,19 @@ constexpr int inwave_levels(int M, int P, int LW) {
   return lw;
 }
 
+// Coarse levels of the in-wave V-cycle of a plan (0: the V-cycle runs through LDS).
+// At M >= 128 every thread holds 16 points of a column, so the in-wave form would
+// repeat each level's FP64 work in all 4^l threads of a bin and stage up to 136 KB
+// of constants per workgroup; the LDS form computes each coarse bin once
+// (cfg-3 step launch 38.7 -> 35.7 us).
+constexpr int VCYCLE_LDS_MIN_M = 128;
+template <int M, int RB>
+constexpr int inwave_depth() {
+  constexpr int TPB = M * RB, P = M + Plan<M, RB>::PAD;
+  constexpr int LW = ilog2c((TPB < 64 ? TPB : 64) / RB);
+  return M >= VCYCLE_LDS_MIN_M ? 0 : inwave_levels(M, P, LW);
+}
+
 // Argument blocks read from memory through the constant address space: the
 // loads are scalar and the compiler may re-read a field instead of keeping it
 // live, so a descriptor costs no vector registers.
@@ -271,9 +284,20 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     }
   }
   __syncthreads();
+  // two grids: level 1 is the coarsest, e_1 = -r_1 g^_1 (r_1 follows V_1, rho_1)
+  const double* r1 = a.lvl + 2 * M1 * M1;
 #pragma unroll
-  for (int i = 0; i < E1; ++i)
-    if (tid + i * TPB < M1 * M1) C[tid + i * TPB] = gh1[i];
+  for (int i = 0; i < E1; ++i) {
+    const int e = tid + i * TPB;
+    if (e < M1 * M1) {
+      double2 v = gh1[i];
+      if (L == 2) {
+        const double rr = r1[e];
+        v = make_double2(-rr * v.x, -rr * v.y);
+      }
+      C[e] = v;
+    }
+  }
   // restriction down: g^_l = I(V_{l-1} g^_{l-1}); coarsest: e = -r g^
   int off_prev = 0, lv_prev = 0, Mp = M1;
   for (int l = 2; l < L; ++l) {
@@ -346,7 +370,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr int LANES = TPB < 64 ? TPB : 64;
   constexpr int CPW = LANES / RB;
   constexpr int LRB = ilog2c(RB), LW = ilog2c(CPW);
-  constexpr int LWI = inwave_levels(M, P, LW);   // coarse levels handled inside the wave
+  constexpr int LWI = inwave_depth<M, RBv>();    // coarse levels handled inside the wave
   constexpr int NW = (TPB + 63) / 64;
   // cross-lane exchanges in VALU form while the plan runs few waves per SIMD
   // (up to 512 threads); the 1024-thread plans, whose LDS pipe and VALU are both
@@ -398,10 +422,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr bool PREQ = (RA <= 8);        // probe table entries in flight with the gather
   // MODE_STEP_PR is the object step with the eq. (3.2) phase store
   constexpr bool STEPM = (MODE == MODE_STEP) || (MODE == MODE_STEP_PR);
-  constexpr bool CST = STEPM && (M <= 64);
+  constexpr bool CST = STEPM && (M <= 64) && (LWI > 0);
   // M = 128: the V-cycle constants do not fit beside the FFT tile; they are
   // staged into the tile once the FFT and the gradient are done with it.
-  constexpr bool CSTL = STEPM && (M > 64);
+  constexpr bool CSTL = STEPM && (M > 64) && (LWI > 0);
   // The twiddle table reads go first (small, needed by the first FFT stage).
   float2 qk[KEEP ? RA : 1];
   float u0k[KEEP ? RA : 1];
@@ -863,8 +887,8 @@ __global__ __launch_bounds__(M * RBv) void step_multi_kernel(const StepArgs* __r
 
 template <int M, int RB>
 constexpr size_t lds_bytes_c() {
-  constexpr int TPB = M * RB, P = M + Plan<M, RB>::PAD;
-  constexpr int LW = inwave_levels(M, P, ilog2c((TPB < 64 ? TPB : 64) / RB));
+  constexpr int P = M + Plan<M, RB>::PAD;
+  constexpr int LW = inwave_depth<M, RB>();
   size_t b = (size_t)M * P * sizeof(float2);
   const size_t c = (size_t)((cst_count_max(M, LW) + 1) & ~1) * sizeof(double);
   if (M <= 64) b += c;          // constants parked beside the tile
@@ -965,11 +989,12 @@ size_t step_lds_bytes(int m, int rb) {
 // ---------------------------------------------------------------------------
 template <int TH>
 __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b) {
-  constexpr int RPT = TH / (2 * ACC_THREADS / 64);
-  constexpr int NW = ACC_THREADS / 64;
+  constexpr int NT = acc_threads(TH);
+  constexpr int NW = NT / 64;
+  constexpr int RPT = TH / (2 * NW);   // rows per thread (1)
   constexpr int U = 4;   // positions whose loads are in flight together
-  __shared__ int s_slot[ACC_THREADS];
-  __shared__ int2 s_off[ACC_THREADS];
+  __shared__ int s_slot[NT];
+  __shared__ int2 s_off[NT];
   __shared__ int s_wcnt[NW];
   const int tx = a.box_x0 + b % a.box_nx, ty = a.box_y0 + b / a.box_nx;
   const int tile = ty * a.tiles_x + tx;
@@ -987,7 +1012,7 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
   float2 zo[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int Y = Y0 + 8 * i;
+    const int Y = Y0 + 2 * NW * i;
     zo[i] = (X < a.n_cols && Y < a.n_rows) ? a.z[(size_t)Y * a.n_cols + X] : make_float2(0.0f, 0.0f);
   }
   // candidates: the minibatch's own records (slot = processing index; a window
@@ -1001,7 +1026,7 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
   const int beg = scan ? 0 : a.tile_ptr[tile], end = scan ? a.count : a.tile_ptr[tile + 1];
   const int lo_idx = a.batch_index * a.batch;
   const int* inv = a.inv + eoff;
-  for (int base = beg; base < end; base += ACC_THREADS) {
+  for (int base = beg; base < end; base += NT) {
     const int idx = base + tid;
     int slot = -1;
     int2 off = make_int2(0, 0);
@@ -1052,7 +1077,7 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
         const bool okx = have && (unsigned)xx < (unsigned)m;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          const int yy = Y0 + 8 * i - o.x;
+          const int yy = Y0 + 2 * NW * i - o.x;
           ok[u][i] = okx && ((unsigned)yy < (unsigned)m);
           const int e = ok[u][i] ? (yy * m + xx) : 0;
           cv[u][i] = a.stage[(size_t)sl * mm + e];
@@ -1074,7 +1099,7 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
   if (X < a.n_cols) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int Y = Y0 + 8 * i;
+      const int Y = Y0 + 2 * NW * i;
       if (Y < a.n_rows && dd[i] > 0.0)
         a.z[(size_t)Y * a.n_cols + X] =
             make_float2((float)((double)zo[i].x + nr[i] / dd[i]), (float)((double)zo[i].y + ni[i] / dd[i]));
@@ -1083,12 +1108,12 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
 }
 
 template <int TH>
-__global__ __launch_bounds__(ACC_THREADS) void accumulate_kernel(AccumArgs a) {
+__global__ __launch_bounds__(acc_threads(TH)) void accumulate_kernel(AccumArgs a) {
   accumulate_body<TH>(a, (int)blockIdx.x);
 }
 
 template <int TH>
-__global__ __launch_bounds__(ACC_THREADS) void accumulate_multi_kernel(const AccumArgs* __restrict__ descs,
+__global__ __launch_bounds__(acc_threads(TH)) void accumulate_multi_kernel(const AccumArgs* __restrict__ descs,
                                                                        const int* __restrict__ prefix, int n_ctx) {
   const int b = (int)blockIdx.x;
   const int j = owner_of(prefix, n_ctx, b);
@@ -1099,9 +1124,9 @@ __global__ __launch_bounds__(ACC_THREADS) void accumulate_multi_kernel(const Acc
 template <int TH>
 static void launch_accumulate_t(const AccumArgs& a, int n_tiles, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0)
-    hipExtLaunchKernelGGL(accumulate_kernel<TH>, dim3(n_tiles), dim3(ACC_THREADS), 0, s, ev0, ev1, 0, a);
+    hipExtLaunchKernelGGL(accumulate_kernel<TH>, dim3(n_tiles), dim3(acc_threads(TH)), 0, s, ev0, ev1, 0, a);
   else
-    hipLaunchKernelGGL(accumulate_kernel<TH>, dim3(n_tiles), dim3(ACC_THREADS), 0, s, a);
+    hipLaunchKernelGGL(accumulate_kernel<TH>, dim3(n_tiles), dim3(acc_threads(TH)), 0, s, a);
 }
 
 bool tile_valid(int th) { return th == 8 || th == 16 || th == 32; }
@@ -1131,10 +1156,10 @@ template <int TH>
 static void launch_acc_multi_t(const AccumArgs* descs, const int* prefix, int n_ctx, int total, hipStream_t s,
                                hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0)
-    hipExtLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(total), dim3(ACC_THREADS), 0, s, ev0, ev1, 0, descs,
+    hipExtLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(total), dim3(acc_threads(TH)), 0, s, ev0, ev1, 0, descs,
                           prefix, n_ctx);
   else
-    hipLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(total), dim3(ACC_THREADS), 0, s, descs, prefix, n_ctx);
+    hipLaunchKernelGGL(accumulate_multi_kernel<TH>, dim3(total), dim3(acc_threads(TH)), 0, s, descs, prefix, n_ctx);
 }
 
 hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, const int* prefix, int n_ctx, int total,
