@@ -1,5 +1,7 @@
 // Host runtime of the MAGPIE C ABI (include/magpie.h): context, device
 // buffers, input validation, epoch scheduling and kernel launches.
+#include <mutex>
+
 #include "context.h"
 
 using namespace mgrt;
@@ -77,6 +79,49 @@ int timed_slot(magpie_ctx* c, int kind, int count) {
   if (!t.a || !t.b) return -1;
   c->timed.push_back(t);
   return (int)c->timed.size() - 1;
+}
+
+// The library's own streams of a device (default priority, non-blocking), created
+// on first use and kept until the process ends: multi-context runs put all but
+// the first partition of their reconstructions on them.
+int side_stream(int device, int index, hipStream_t* out) {
+  static std::mutex mu;
+  static std::vector<std::vector<hipStream_t>> pool;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)pool.size() <= device) pool.resize((size_t)device + 1);
+  auto& v = pool[(size_t)device];
+  while ((int)v.size() <= index) {
+    hipStream_t sN = nullptr;
+    MG_HIP(hipStreamCreateWithFlags(&sN, hipStreamNonBlocking));
+    v.push_back(sN);
+  }
+  *out = v[(size_t)index];
+  return MAGPIE_OK;
+}
+
+// Round descriptors of a multi-context chunk: pinned host and device slot `slot`
+// of the first context, grown to `bytes`, once its previous upload is done.
+int multi_slot(magpie_ctx* c, int slot, size_t bytes) {
+  if (c->mdesc_pending[slot]) {
+    MG_HIP(hipEventSynchronize(c->mdesc_done[slot]));
+    c->mdesc_pending[slot] = false;
+  }
+  if (bytes <= c->mdesc_cap[slot]) return MAGPIE_OK;
+  if (c->mdesc_host[slot]) hipHostFree(c->mdesc_host[slot]);
+  c->mdesc_host[slot] = nullptr;
+  dev_free(c->mdesc_dev[slot]);
+  c->mdesc_cap[slot] = 0;
+  const size_t cap = std::max(bytes, (size_t)1 << 20);
+  if (hipHostMalloc(&c->mdesc_host[slot], cap, hipHostMallocDefault) != hipSuccess) {
+    c->mdesc_host[slot] = nullptr;
+    return fail(MAGPIE_ERR_OOM, "pinned host allocation failed");
+  }
+  unsigned char* d = nullptr;
+  int rc = dev_alloc(&d, cap);
+  if (rc) return rc;
+  c->mdesc_dev[slot] = d;
+  c->mdesc_cap[slot] = cap;
+  return MAGPIE_OK;
 }
 
 // Per-tile ascending lists of overlapping positions (with their offsets) for
@@ -193,7 +238,9 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   if (!rc) rc = dev_alloc(&c->red, 4);
   if (!rc) rc = dev_alloc(&c->epoch_ctr, 1);
   if (!rc && (hipEventCreateWithFlags(&c->pin_done[0], hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&c->pin_done[1], hipEventDisableTiming) != hipSuccess))
+              hipEventCreateWithFlags(&c->pin_done[1], hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&c->mdesc_done[0], hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&c->mdesc_done[1], hipEventDisableTiming) != hipSuccess))
     rc = fail(MAGPIE_ERR_HIP, "hipEventCreate failed");
   if (rc) {
     magpie_destroy(c);
@@ -250,6 +297,11 @@ int magpie_destroy(magpie_ctx* c) {
   if (c->h_pin) hipHostFree(c->h_pin);
   for (hipEvent_t ev : c->pin_done)
     if (ev) hipEventDestroy(ev);
+  for (int k = 0; k < 2; ++k) {
+    if (c->mdesc_done[k]) hipEventDestroy(c->mdesc_done[k]);
+    if (c->mdesc_host[k]) hipHostFree(c->mdesc_host[k]);
+    dev_free(c->mdesc_dev[k]);
+  }
   for (auto& t : c->timed) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);
@@ -534,7 +586,7 @@ static int check_orders(magpie_ctx* c, int n_epochs, const int32_t* order) {
 // slot `slot` (slot_epochs epochs wide) and uploaded to the device records from
 // epoch offset dev_epoch; the slot's event marks the end of its upload.
 static int fill_records(magpie_ctx* c, int e0, int ne, uint64_t seed, const int32_t* order, int slot,
-                        size_t slot_epochs, size_t dev_epoch) {
+                        size_t slot_epochs, size_t dev_epoch, hipStream_t s) {
   const int N = c->n_pos;
   // a slot's region moves with its width: then both slots' uploads must be done
   for (int s = 0; s < 2; ++s)
@@ -566,9 +618,9 @@ static int fill_records(magpie_ctx* c, int e0, int ne, uint64_t seed, const int3
     }
   }
   const size_t n = (size_t)ne * N;
-  MG_HIP(hipMemcpyAsync(c->inv + dev_epoch * N, hi, n * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-  MG_HIP(hipMemcpyAsync(c->posrec + dev_epoch * N, hr, n * sizeof(int4), hipMemcpyHostToDevice, c->stream));
-  MG_HIP(hipEventRecord(c->pin_done[slot], c->stream));
+  MG_HIP(hipMemcpyAsync(c->inv + dev_epoch * N, hi, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  MG_HIP(hipMemcpyAsync(c->posrec + dev_epoch * N, hr, n * sizeof(int4), hipMemcpyHostToDevice, s));
+  MG_HIP(hipEventRecord(c->pin_done[slot], s));
   c->pin_pending[slot] = true;
   return MAGPIE_OK;
 }
@@ -579,7 +631,7 @@ static int prepare_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed,
   int rc = ensure_epoch_buffers(c, n_epochs, batch, (size_t)n_epochs);
   if (!rc && order) rc = check_orders(c, n_epochs, order);
   if (!rc) rc = ensure_pinned(c, (size_t)n_epochs);
-  if (!rc) rc = fill_records(c, 0, n_epochs, seed, order, 0, (size_t)n_epochs, 0);
+  if (!rc) rc = fill_records(c, 0, n_epochs, seed, order, 0, (size_t)n_epochs, 0, c->stream);
   return rc;
 }
 
@@ -770,7 +822,7 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   for (int e0 = 0; e0 < n_epochs; ++chunk) {
     const int ne = chunk == 0 ? 1 : std::min(CH, n_epochs - e0);
     const int slot = chunk & 1;
-    rc = fill_records(c, e0, ne, seed, order, slot, ch, (size_t)slot * ch);
+    rc = fill_records(c, e0, ne, seed, order, slot, ch, (size_t)slot * ch, c->stream);
     if (rc) return rc;
     const size_t off = (size_t)slot * ch * N;
     rc = launch_epochs(c, ne, B, (N + B - 1) / B, false, EpochBuffers{c->stage, c->posrec + off, c->inv + off});
@@ -1169,191 +1221,237 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
   int rc = set_dev(c0);
   if (rc) return rc;
   hipStream_t st = c0->stream;
-  // every context's earlier work precedes this run (its permutation uploads are
-  // enqueued on its own stream by prepare_epochs, so join afterwards)
+  // Epochs run in chunks of up to CH (the first chunk one epoch): the records and
+  // round descriptors of a chunk are built on the host and uploaded (two pinned
+  // and two device slots) while the GPU runs the previous chunk, and no buffer
+  // grows with the number of epochs.
+  constexpr int CH = 8;
   for (int i = 0; i < count; ++i) {
-    rc = prepare_epochs(ctxs[i], n_epochs, batch[i], seed, nullptr);
+    rc = ensure_epoch_buffers(ctxs[i], n_epochs, batch[i], 2 * (size_t)CH);
+    if (!rc) rc = ensure_pinned(ctxs[i], CH);
     if (rc) return rc;
   }
   std::vector<hipEvent_t> evs;
   auto join = [&](hipStream_t from, hipStream_t to) -> int {
     if (from == to) return MAGPIE_OK;
-    hipEvent_t e;
-    MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    evs.push_back(e);
-    MG_HIP(hipEventRecord(e, from));
-    MG_HIP(hipStreamWaitEvent(to, e, 0));
+    hipEvent_t ev;
+    MG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    evs.push_back(ev);
+    MG_HIP(hipEventRecord(ev, from));
+    MG_HIP(hipStreamWaitEvent(to, ev, 0));
     return MAGPIE_OK;
   };
   auto cleanup = [&]() {
-    for (auto e : evs) hipEventDestroy(e);
+    for (auto ev : evs) hipEventDestroy(ev);
   };
+  // every context's earlier work precedes this run
   for (int i = 1; i < count && !rc; ++i) rc = join(ctxs[i]->stream, st);
   if (rc) {
     cleanup();
     return rc;
   }
-  // groups: step kernel by plan (m, rb), accumulation by tile height
-  struct Group {
+  // Partitions by FFT plan (m, rb).  Each runs its own rounds on a stream of its
+  // own (the first on st, the others on the library's streams of this device, which
+  // fork from st after each chunk's uploads and join it at the chunk's end), so the
+  // partitions overlap and fill each other's launch tails.  Within a partition a
+  // round pairs the t-th minibatches of its members: one step launch, then one
+  // accumulation launch per tile height.
+  struct Part {
     int m, rb;
     std::vector<int> members;
+    std::vector<int> ths;                 // distinct tile heights of the members
+    int R = 0;                            // rounds of the current chunk
+    size_t desc0 = 0, pre0 = 0;           // offsets of its descriptors / running totals
+    size_t pre_per_round = 0;
+    hipStream_t stream = nullptr;
   };
-  std::vector<Group> sgroups;
-  std::vector<Group> agroups;   // m field holds th
+  std::vector<Part> parts;
   for (int i = 0; i < count; ++i) {
     magpie_ctx* c = ctxs[i];
-    bool found = false;
-    for (auto& g : sgroups)
-      if (g.m == c->m && g.rb == c->rb) {
-        g.members.push_back(i);
-        found = true;
-      }
-    if (!found) sgroups.push_back({c->m, c->rb, {i}});
-    found = false;
-    for (auto& g : agroups)
-      if (g.m == c->th) {
-        g.members.push_back(i);
-        found = true;
-      }
-    if (!found) agroups.push_back({c->th, 0, {i}});
+    Part* pp = nullptr;
+    for (auto& p : parts)
+      if (p.m == c->m && p.rb == c->rb) pp = &p;
+    if (!pp) {
+      parts.push_back(Part{c->m, c->rb, {}, {}});
+      pp = &parts.back();
+    }
+    pp->members.push_back(i);
+    if (std::find(pp->ths.begin(), pp->ths.end(), c->th) == pp->ths.end()) pp->ths.push_back(c->th);
   }
-  std::vector<int> B(count), nb(count), T(count);
-  int R = 0;
+  std::vector<int> B(count), nb(count);
   for (int i = 0; i < count; ++i) {
     B[i] = std::min(batch[i], ctxs[i]->n_pos);
     nb[i] = (ctxs[i]->n_pos + B[i] - 1) / B[i];
-    T[i] = n_epochs * nb[i];
-    R = std::max(R, T[i]);
   }
-  // descriptors for every round: step args per plan group, accum args per tile group
-  std::vector<mg::StepArgs> hs((size_t)R * count);
-  std::vector<mg::AccumArgs> ha((size_t)R * count);
-  // per round and group: running totals of the members' positions (step) or
-  // tiles (accumulation), n_members + 1 ints each, consecutive in hp
-  size_t s_pre = 0, a_pre = 0;
-  for (auto& g : sgroups) s_pre += g.members.size() + 1;
-  for (auto& g : agroups) a_pre += g.members.size() + 1;
-  std::vector<int> hp((size_t)R * (s_pre + a_pre), 0);
-  auto s_prefix = [&](int r, size_t gi_off) { return (size_t)r * (s_pre + a_pre) + gi_off; };
-  auto a_prefix = [&](int r, size_t gi_off) { return (size_t)r * (s_pre + a_pre) + s_pre + gi_off; };
-  for (int r = 0; r < R; ++r) {
-    size_t base = (size_t)r * count;
-    size_t off = 0, poff = 0;
-    for (auto& g : sgroups) {
-      int* pre = hp.data() + s_prefix(r, poff);
-      for (size_t j = 0; j < g.members.size(); ++j) {
-        const int i = g.members[j];
-        magpie_ctx* c = ctxs[i];
-        mg::StepArgs a{};
-        a.z = c->z;
-        a.n_rows = c->nr;
-        a.n_cols = c->nc;
-        a.q = c->qf;
-        a.qtab = c->qtab;
-        a.sqrtd = c->sqrtd;
-        a.offs = c->offs;
-        a.stage = c->stage;
-        a.u0f = c->u0f;
-        a.lvl = c->lvl;
-        a.levels = c->L;
-        a.lvl_a_off = c->lvl_a_off;
-        a.phi_part = c->step_part;
-        if (r < T[i]) {
-          const int e = r / nb[i], t = r % nb[i];
-          a.pos = c->posrec + (size_t)e * c->n_pos + (size_t)t * B[i];
-          a.count = std::min(B[i], c->n_pos - t * B[i]);
-        } else {
-          a.count = 0;
-        }
-        pre[j + 1] = pre[j] + a.count;
-        hs[base + off + j] = a;
-      }
-      off += g.members.size();
-      poff += g.members.size() + 1;
+  std::vector<hipEvent_t> fork_ev(parts.size(), nullptr), join_ev(parts.size(), nullptr);
+  for (size_t g = 0; g < parts.size() && !rc; ++g) {
+    if (g == 0) {
+      parts[g].stream = st;
+      continue;
     }
-    off = 0;
-    poff = 0;
-    for (auto& g : agroups) {
-      int* pre = hp.data() + a_prefix(r, poff);
-      for (size_t j = 0; j < g.members.size(); ++j) {
-        const int i = g.members[j];
-        magpie_ctx* c = ctxs[i];
-        mg::AccumArgs a{};
-        a.z = c->z;
-        a.n_rows = c->nr;
-        a.n_cols = c->nc;
-        a.m = c->m;
-        a.tiles_x = c->tiles_x;
-        a.box_x0 = c->box_x0;
-        a.box_y0 = c->box_y0;
-        a.box_nx = c->box_nx;
-        a.tile_ptr = c->tile_ptr;
-        a.tile_ent = c->tile_ent;
-        a.stage = c->stage;
-        a.offs = c->offs;
-        a.w0f = c->w0f;
-        a.batch = B[i];
-        if (r < T[i]) {
-          const int e = r / nb[i], t = r % nb[i];
-          a.inv = c->inv + (size_t)e * c->n_pos;
-          a.batch_index = t;
-          a.n_tiles = c->box_nx * c->box_ny;
-          if (B[i] <= mg::ACC_SCAN_MAX) {
-            a.pos = c->posrec + (size_t)e * c->n_pos + (size_t)t * B[i];
-            a.count = std::min(B[i], c->n_pos - t * B[i]);
-          }
-        } else {
-          a.inv = c->inv;
-          a.n_tiles = 0;
-        }
-        pre[j + 1] = pre[j] + a.n_tiles;
-        ha[base + off + j] = a;
-      }
-      off += g.members.size();
-      poff += g.members.size() + 1;
-    }
+    rc = side_stream(c0->device, (int)g - 1, &parts[g].stream);
+    if (!rc && hipEventCreateWithFlags(&fork_ev[g], hipEventDisableTiming) != hipSuccess)
+      rc = fail(MAGPIE_ERR_HIP, "hipEventCreate failed");
+    if (fork_ev[g]) evs.push_back(fork_ev[g]);
+    if (!rc && hipEventCreateWithFlags(&join_ev[g], hipEventDisableTiming) != hipSuccess)
+      rc = fail(MAGPIE_ERR_HIP, "hipEventCreate failed");
+    if (join_ev[g]) evs.push_back(join_ev[g]);
   }
-  mg::StepArgs* ds = nullptr;
-  mg::AccumArgs* da = nullptr;
-  int* dp = nullptr;
-  rc = dev_alloc(&ds, hs.size());
-  if (!rc) rc = dev_alloc(&da, ha.size());
-  if (!rc) rc = dev_alloc(&dp, hp.size());
   hipError_t e = hipSuccess;
-  if (!rc) e = hipMemcpyAsync(ds, hs.data(), hs.size() * sizeof(mg::StepArgs), hipMemcpyHostToDevice, st);
-  if (!rc && e == hipSuccess)
-    e = hipMemcpyAsync(da, ha.data(), ha.size() * sizeof(mg::AccumArgs), hipMemcpyHostToDevice, st);
-  if (!rc && e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(int), hipMemcpyHostToDevice, st);
-  for (int r = 0; r < R && !rc && e == hipSuccess; ++r) {
-    size_t off = 0, poff = 0;
-    for (size_t gi = 0; gi < sgroups.size() && e == hipSuccess; ++gi) {
-      const auto& g = sgroups[gi];
-      const int nm = (int)g.members.size();
-      const int npat = hp[s_prefix(r, poff) + nm];
-      const int ti = (npat > 0) ? timed_slot(c0, 0, npat) : -1;
-      e = mg::launch_step_multi(g.m, g.rb, ds + (size_t)r * count + off, dp + s_prefix(r, poff), nm, npat, st,
-                                ti >= 0 ? c0->timed[ti].a : nullptr, ti >= 0 ? c0->timed[ti].b : nullptr);
-      off += g.members.size();
-      poff += g.members.size() + 1;
+  int chunk = 0;
+  for (int e0 = 0; e0 < n_epochs && !rc && e == hipSuccess; ++chunk) {
+    const int ne = chunk == 0 ? 1 : std::min(CH, n_epochs - e0);
+    const int slot = chunk & 1;
+    // records of every member for these epochs, uploaded on st into its device slot
+    for (int i = 0; i < count && !rc; ++i)
+      rc = fill_records(ctxs[i], e0, ne, seed, nullptr, slot, CH, (size_t)slot * CH, st);
+    if (rc) break;
+    // round descriptors of the chunk: per partition and round its members' step
+    // descriptors, then their accumulation descriptors by tile height; running
+    // totals: one block for the step launch, one per tile height (n_members + 1 ints)
+    size_t n_desc = 0, n_pre = 0;
+    for (auto& p : parts) {
+      p.R = 0;
+      for (int i : p.members) p.R = std::max(p.R, ne * nb[i]);
+      p.desc0 = n_desc;
+      p.pre0 = n_pre;
+      p.pre_per_round = (p.members.size() + 1) * (1 + p.ths.size());
+      n_desc += (size_t)p.R * p.members.size();
+      n_pre += (size_t)p.R * p.pre_per_round;
     }
-    off = 0;
-    poff = 0;
-    for (size_t gi = 0; gi < agroups.size() && e == hipSuccess; ++gi) {
-      const auto& g = agroups[gi];
-      const int nm = (int)g.members.size();
-      const int ntile = hp[a_prefix(r, poff) + nm];
-      const int ti = (ntile > 0) ? timed_slot(c0, 1, 0) : -1;
-      e = mg::launch_accumulate_multi(g.m, da + (size_t)r * count + off, dp + a_prefix(r, poff), nm, ntile, st,
-                                      ti >= 0 ? c0->timed[ti].a : nullptr, ti >= 0 ? c0->timed[ti].b : nullptr);
-      off += g.members.size();
-      poff += g.members.size() + 1;
+    const size_t off_a = (n_desc * sizeof(mg::StepArgs) + 255) & ~(size_t)255;
+    const size_t off_p = (off_a + n_desc * sizeof(mg::AccumArgs) + 255) & ~(size_t)255;
+    const size_t bytes = off_p + n_pre * sizeof(int);
+    rc = multi_slot(c0, slot, bytes);
+    if (rc) break;
+    unsigned char* hbase = static_cast<unsigned char*>(c0->mdesc_host[slot]);
+    unsigned char* dbase = c0->mdesc_dev[slot];
+    mg::StepArgs* hs = reinterpret_cast<mg::StepArgs*>(hbase);
+    mg::AccumArgs* ha = reinterpret_cast<mg::AccumArgs*>(hbase + off_a);
+    int* hp = reinterpret_cast<int*>(hbase + off_p);
+    std::fill(hp, hp + n_pre, 0);
+    for (auto& p : parts) {
+      const size_t nm = p.members.size();
+      for (int r = 0; r < p.R; ++r) {
+        mg::StepArgs* sd = hs + p.desc0 + (size_t)r * nm;
+        mg::AccumArgs* ad = ha + p.desc0 + (size_t)r * nm;
+        int* pre = hp + p.pre0 + (size_t)r * p.pre_per_round;
+        for (size_t j = 0; j < nm; ++j) {
+          const int i = p.members[j];
+          magpie_ctx* c = ctxs[i];
+          mg::StepArgs a{};
+          a.z = c->z;
+          a.n_rows = c->nr;
+          a.n_cols = c->nc;
+          a.q = c->qf;
+          a.qtab = c->qtab;
+          a.sqrtd = c->sqrtd;
+          a.offs = c->offs;
+          a.stage = c->stage;
+          a.u0f = c->u0f;
+          a.lvl = c->lvl;
+          a.levels = c->L;
+          a.lvl_a_off = c->lvl_a_off;
+          a.phi_part = c->step_part;
+          if (r < ne * nb[i]) {
+            const int er = r / nb[i], t = r % nb[i];
+            a.pos = c->posrec + ((size_t)slot * CH + er) * c->n_pos + (size_t)t * B[i];
+            a.count = std::min(B[i], c->n_pos - t * B[i]);
+          } else {
+            a.count = 0;
+          }
+          pre[j + 1] = pre[j] + a.count;
+          sd[j] = a;
+        }
+        size_t k = 0;
+        for (size_t h = 0; h < p.ths.size(); ++h) {
+          int* apre = pre + (nm + 1) * (1 + h);
+          size_t jj = 0;
+          for (size_t j = 0; j < nm; ++j) {
+            const int i = p.members[j];
+            magpie_ctx* c = ctxs[i];
+            if (c->th != p.ths[h]) continue;
+            mg::AccumArgs a{};
+            a.z = c->z;
+            a.n_rows = c->nr;
+            a.n_cols = c->nc;
+            a.m = c->m;
+            a.tiles_x = c->tiles_x;
+            a.box_x0 = c->box_x0;
+            a.box_y0 = c->box_y0;
+            a.box_nx = c->box_nx;
+            a.tile_ptr = c->tile_ptr;
+            a.tile_ent = c->tile_ent;
+            a.stage = c->stage;
+            a.offs = c->offs;
+            a.w0f = c->w0f;
+            a.batch = B[i];
+            if (r < ne * nb[i]) {
+              const int er = r / nb[i], t = r % nb[i];
+              a.inv = c->inv + ((size_t)slot * CH + er) * c->n_pos;
+              a.batch_index = t;
+              a.n_tiles = c->box_nx * c->box_ny;
+              if (B[i] <= mg::ACC_SCAN_MAX) {
+                a.pos = c->posrec + ((size_t)slot * CH + er) * c->n_pos + (size_t)t * B[i];
+                a.count = std::min(B[i], c->n_pos - t * B[i]);
+              }
+            } else {
+              a.inv = c->inv;
+              a.n_tiles = 0;
+            }
+            apre[jj + 1] = apre[jj] + a.n_tiles;
+            ad[k++] = a;
+            ++jj;
+          }
+        }
+      }
     }
+    e = hipMemcpyAsync(dbase, hbase, bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(c0->mdesc_done[slot], st);
+    if (e != hipSuccess) break;
+    c0->mdesc_pending[slot] = true;
+    const mg::StepArgs* ds = reinterpret_cast<const mg::StepArgs*>(dbase);
+    const mg::AccumArgs* da = reinterpret_cast<const mg::AccumArgs*>(dbase + off_a);
+    const int* dp = reinterpret_cast<const int*>(dbase + off_p);
+    // the other partitions start after the chunk's uploads
+    for (size_t g = 1; g < parts.size() && e == hipSuccess; ++g) {
+      e = hipEventRecord(fork_ev[g], st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(parts[g].stream, fork_ev[g], 0);
+    }
+    int R = 0;
+    for (auto& p : parts) R = std::max(R, p.R);
+    for (int r = 0; r < R && e == hipSuccess; ++r) {
+      for (size_t g = 0; g < parts.size() && e == hipSuccess; ++g) {
+        const Part& p = parts[g];
+        if (r >= p.R) continue;
+        const size_t nm = p.members.size();
+        const size_t dsc = p.desc0 + (size_t)r * nm;
+        const size_t pre = p.pre0 + (size_t)r * p.pre_per_round;
+        const int npat = hp[pre + nm];
+        int ti = (npat > 0) ? timed_slot(c0, 0, npat) : -1;
+        e = mg::launch_step_multi(p.m, p.rb, ds + dsc, dp + pre, (int)nm, npat, p.stream,
+                                  ti >= 0 ? c0->timed[ti].a : nullptr, ti >= 0 ? c0->timed[ti].b : nullptr);
+        size_t k = 0;
+        for (size_t h = 0; h < p.ths.size() && e == hipSuccess; ++h) {
+          size_t members_h = 0;
+          for (int i : p.members) members_h += (ctxs[i]->th == p.ths[h]) ? 1 : 0;
+          const size_t apre = pre + (nm + 1) * (1 + h);
+          const int ntile = hp[apre + members_h];
+          ti = (ntile > 0) ? timed_slot(c0, 1, 0) : -1;
+          e = mg::launch_accumulate_multi(p.ths[h], da + dsc + k, dp + apre, (int)members_h, ntile, p.stream,
+                                          ti >= 0 ? c0->timed[ti].a : nullptr, ti >= 0 ? c0->timed[ti].b : nullptr);
+          k += members_h;
+        }
+      }
+    }
+    // the chunk ends on st (the chunk after next reuses this chunk's slots)
+    for (size_t g = 1; g < parts.size() && e == hipSuccess; ++g) {
+      e = hipEventRecord(join_ev[g], parts[g].stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, join_ev[g], 0);
+    }
+    e0 += ne;
   }
-  // the descriptor buffers are freed once the launches that read them are done
-  if (e == hipSuccess && !rc) e = hipStreamSynchronize(st);
-  dev_free(ds);
-  dev_free(da);
-  dev_free(dp);
+  if (!rc && e == hipSuccess) e = hipStreamSynchronize(st);
   if (!rc && e != hipSuccess) rc = fail(MAGPIE_ERR_HIP, std::string("multi-context run: ") + hipGetErrorString(e));
   for (int i = 1; i < count && !rc; ++i) rc = join(st, ctxs[i]->stream);
   cleanup();

@@ -140,6 +140,12 @@ struct magpie_ctx {
   size_t pin_width = 0;  // epochs per slot of the last fill
   hipEvent_t pin_done[2] = {nullptr, nullptr};
   bool pin_pending[2] = {false, false};
+  // round descriptors of multi-context chunks led by this context (two slots)
+  void* mdesc_host[2] = {nullptr, nullptr};
+  unsigned char* mdesc_dev[2] = {nullptr, nullptr};
+  size_t mdesc_cap[2] = {0, 0};
+  hipEvent_t mdesc_done[2] = {nullptr, nullptr};
+  bool mdesc_pending[2] = {false, false};
   std::vector<int32_t> h_perm;   // host scratch: one epoch's permutation
   std::vector<int> h_seen;       // host scratch: permutation check
 
