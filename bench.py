@@ -50,11 +50,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(cfg_id: int, m: int, rb: int):
-    """Counter-measured HBM bytes per full launch of the step kernel, from the
-    committed rocprofv3 summary, if it was taken on the current sources with the
-    same FFT plan (threads per transform rb)."""
-    path = os.path.join(ROOT, "profiles", f"step_kernel_m{m}_cfg{cfg_id}.md")
+def stored_traffic(cfg_id: int, m: int, rb: int, kind: str = "step"):
+    """Counter-measured HBM bytes per launch of the step kernel (full launches) or of the
+    accumulation kernel (kind "accumulate", mean over its launches), from the committed
+    rocprofv3 summary, if it was taken on the current kernel sources (and, for the step
+    kernel, with the same FFT plan: threads per transform rb)."""
+    name = f"step_kernel_m{m}_cfg{cfg_id}.md" if kind == "step" else f"accumulate_kernel_cfg{cfg_id}.md"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -65,12 +67,17 @@ def stored_traffic(cfg_id: int, m: int, rb: int):
                                                          "patterns_per_launch", "plan_threads_per_transform")):
                 k, v = line.strip().split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != kernel_source_hash() or vals.get("plan_threads_per_transform") != str(rb):
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    if kind == "step" and vals.get("plan_threads_per_transform") != str(rb):
         return None
     try:
-        return {"bytes_per_full_launch": float(vals["traffic_bytes_per_launch"]),
-                "fetch": float(vals["traffic_fetch_bytes"]), "write": float(vals["traffic_write_bytes"]),
-                "patterns_per_launch": int(vals["patterns_per_launch"]), "summary": os.path.basename(path)}
+        out = {"bytes_per_launch": float(vals["traffic_bytes_per_launch"]),
+               "fetch": float(vals["traffic_fetch_bytes"]), "write": float(vals["traffic_write_bytes"]),
+               "summary": os.path.basename(path)}
+        if kind == "step":
+            out["patterns_per_launch"] = int(vals["patterns_per_launch"])
+        return out
     except (KeyError, ValueError):
         return None
 
@@ -326,7 +333,10 @@ def run_single(cfg_id, steps, warmup, seed, batch=None, levels=None, alpha=None,
     acc_full_us = float(acc_us[acc_full].mean())
     acc_bytes = B * 8 * m * m + 16 * cov_full
     epoch_bytes = N * bytes_per_pattern + 16 * cov_mean * nb
-    n_tiles = ((n + ACC_TILE_W - 1) // ACC_TILE_W) * ((n + th_used - 1) // th_used)
+    # the accumulation runs over the box of tiles some window reaches
+    bx = (offs[:, 1].max() + m - 1) // ACC_TILE_W - offs[:, 1].min() // ACC_TILE_W + 1
+    by = (offs[:, 0].max() + m - 1) // th_used - offs[:, 0].min() // th_used + 1
+    n_tiles = int(bx * by)
     return {
         "cfg": cfg, "batch": batch, "levels": levels, "alpha": alpha, "N": N, "m": m, "n": n, "B": B,
         "tuning": tune, "rb": rb_used, "th": th_used,
@@ -562,7 +572,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": r["achieved"] / HBM_PEAK_GBS,
-        "traffic": None if traffic is None else traffic["bytes_per_full_launch"],
+        "traffic": None if traffic is None else traffic["bytes_per_launch"],
         "traffic_detail": traffic,
         "algorithmic_bytes_per_full_launch": r["bytes_per_pattern"] * B,
         "bytes_per_pattern": r["bytes_per_pattern"],
@@ -576,8 +586,12 @@ def main():
             "bytes_per_epoch": r["epoch_bytes"], "achieved": pipe_achieved, "frac": pipe_achieved / HBM_PEAK_GBS,
             "bytes_per_pattern": r["epoch_bytes"] / r["N"], "covered_pixels_per_minibatch": r["cov_mean"]},
     }
+    acc_traffic = stored_traffic(args.config, m, r["rb"], "accumulate") \
+        if r["batch"] == cfg.batch and r["th"] == 8 else None
     out["accumulate_kernel"] = {
         "avg_launch_us": r["acc_full_us"], "launches": r["acc_launches"], "tiles_per_launch": r["n_tiles"],
+        "traffic_per_launch_all": None if acc_traffic is None else acc_traffic["bytes_per_launch"],
+        "traffic_detail": acc_traffic,
         "tile": f"{ACC_TILE_W}x{r['th']}",
         "algorithmic_bytes_per_full_launch": r["acc_bytes"],
         "frac": r["acc_bytes"] / (r["acc_full_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,

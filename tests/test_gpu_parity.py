@@ -574,3 +574,45 @@ def test_multi_context_matches_oracle():
         rel, relx = c.rel(zg, zo), c.rel_max(zg, zo)
         _print("multi m", c.m, "N", c.n_pos, "B", B, "rel", rel, "element-wise", relx)
         assert rel <= 1e-5 and relx <= 1e-5
+
+
+def test_long_runs_reuse_chunk_slots():
+    """Epochs are prepared in chunks (1, then 8 at a time) whose host and device slots
+    alternate: 20 epochs in one call (chunks 1 + 8 + 8 + 3, both slots reused) equal the
+    same epochs in calls of 1, 8 and 11 epochs, and the same permutations given
+    explicitly, bit for bit; so does a 20-epoch multi-reconstruction run against
+    separate runs."""
+    from paper_2504_10118_amd import run_epochs_multi
+    rng = np.random.default_rng(48)
+    c = Case(rng, 110, 104, 32, 9, noise=0.05)
+    g = c.gpu(3, 0.5)
+    g.run_epochs(20, 9, seed=61)
+    one = g.get_object()
+    g.close()
+    g = c.gpu(3, 0.5)
+    for n in (1, 8, 11):
+        g.run_epochs(n, 9, seed=61)
+    split = g.get_object()
+    assert g.epoch_index == 20
+    g.close()
+    orders = np.stack([oracle.library_permutation(61, e, c.n_pos) for e in range(20)])
+    g = c.gpu(3, 0.5)
+    g.run_epochs(20, 9, order=orders)
+    explicit = g.get_object()
+    g.close()
+    assert np.array_equal(one.view(np.uint64), split.view(np.uint64))
+    assert np.array_equal(one.view(np.uint64), explicit.view(np.uint64))
+    cases = [c, Case(rng, 150, 160, 64, 13, noise=0.05)]
+    levels, batches = [3, 3], [9, 5]
+    single = []
+    for cc, L, B in zip(cases, levels, batches):
+        g = cc.gpu(L, 0.5)
+        g.run_epochs(20, B, seed=62)
+        single.append(g.get_object())
+        g.close()
+    gs = [cc.gpu(L, 0.5) for cc, L in zip(cases, levels)]
+    run_epochs_multi(gs, 20, batches, seed=62)
+    for g, ref in zip(gs, single):
+        assert g.epoch_index == 20
+        assert np.array_equal(g.get_object().view(np.uint64), ref.view(np.uint64))
+        g.close()
