@@ -55,7 +55,9 @@ def stored_traffic(cfg_id: int, m: int, rb: int, kind: str = "step"):
     accumulation kernel (kind "accumulate", mean over its launches), from the committed
     rocprofv3 summary, if it was taken on the current kernel sources (and, for the step
     kernel, with the same FFT plan: threads per transform rb)."""
-    name = f"step_kernel_m{m}_cfg{cfg_id}.md" if kind == "step" else f"accumulate_kernel_cfg{cfg_id}.md"
+    from synth import CONFIGS
+    n = CONFIGS[cfg_id].n
+    name = f"step_kernel_m{m}_n{n}.md" if kind == "step" else f"accumulate_kernel_n{n}.md"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -91,7 +93,7 @@ def workload_inputs(cfg_id: int):
 
 def describe(cfg, batch, levels, alpha):
     noise = "noiseless" if cfg.peak is None else f"Poisson {cfg.peak:.0e} peak photons"
-    return (f"cfg{cfg.cfg_id}: object {cfg.n}x{cfg.n} complex64, probe {cfg.m}x{cfg.m}, "
+    return (f"object {cfg.n}x{cfg.n} complex64, probe {cfg.m}x{cfg.m}, "
             f"{cfg.P}x{cfg.P} jittered raster step {cfg.step} ({cfg.n_pos} positions), {noise}, "
             f"{levels} levels, minibatch {batch}, alpha {alpha}")
 
@@ -433,7 +435,7 @@ def bench_batched(steps, warmup, seed, batch=None, alpha=None, tuning=""):
         "acc_launch_us": tm["accum_ms"] * 1e3 / max(1, tm["accum_launches"]), "acc_launches": tm["accum_launches"],
         "event_wall": t3 - t2, "step_ms_sum": tm["step_ms"], "acc_ms_sum": tm["accum_ms"],
         "phi_median": float(np.median(phis)), "alpha": alpha,
-        "workload": (f"cfg4: {len(specs)} independent reconstructions, objects "
+        "workload": (f"{len(specs)} independent reconstructions, objects "
                      f"{min(sp.n for sp in specs)}..{max(sp.n for sp in specs)} px, probes 64 ({ms.count(64)}) "
                      f"and 128 ({ms.count(128)}), {min(sp.n_pos for sp in specs)}..{max(sp.n_pos for sp in specs)} "
                      f"positions each ({total_pos} total), Poisson 1e4..1e5 peak photons, L = 3 (m 64) / 4 "
@@ -515,11 +517,11 @@ def main():
     cpu = {}
     if not args.no_cpu_baseline and args.config != 4:
         _, cpu["main"] = cpu_line(args, args.config)
-        if default_run:
+        if default_run and not args.no_extra_workloads:
             for cid in (1, 3):
                 c, line = cpu_line(args, cid)
                 cpu[cid] = {"value": line["value"], "cores": line["cores"], "one_core": line["one_core"]["value"],
-                            "workload": describe(c, c.batch, c.levels, c.alpha)}
+                            "workload": describe(c, c.batch, c.levels, c.alpha), "n": c.n}
 
     import torch
     if not torch.cuda.is_available():
@@ -612,16 +614,16 @@ def main():
     out["stopping_statistic_after"] = r["stat"]
     if default_run and not args.no_extra_workloads:
         r3 = run_single(3, 20, 5, args.seed, device_noise=True)
-        out["cfg3"] = single_summary(r3, 20)
-        out["cfg3"]["noise"] = "Poisson counts drawn on the device (same model)"
-        r4 = bench_batched(3, 1, args.seed)
-        out["cfg4"] = batched_summary(r4, 3)
+        out["workload_1024x1024"] = single_summary(r3, 20)
+        out["workload_1024x1024"]["noise"] = "Poisson counts drawn on the device (same model)"
+        r4 = bench_batched(8, 2, args.seed)
+        out["workload_64_reconstructions"] = batched_summary(r4, 8)
         torch.cuda.synchronize()
     if args.race_objects > 0 and args.config == 2:
         out["learned_race"] = learned_race(args.race_objects)
     if "main" in cpu:
         out["cpu_baseline"] = cpu["main"]
-        others = {f"cfg{cid}": v for cid, v in cpu.items() if cid != "main"}
+        others = {f"workload_{v['n']}x{v['n']}": v for cid, v in cpu.items() if cid != "main"}
         if others:
             out["cpu_baseline"]["other_workloads"] = others
     print(json.dumps(out), flush=True)

@@ -103,15 +103,13 @@ __host__ __device__ constexpr int cst_v_off(int M, int L, int l) {
 constexpr int cst_count_max(int M, int LW) { return cst_count(M, LW + 1); }
 
 // Deepest in-wave V-cycle (number of coarse levels, at most LW) whose constants
-// the LDS holds: M <= 64 parks them beside the M x P tile, larger M stages
-// them into the tile's space once the FFT is done with it.
+// fit in LDS beside the M x P tile.
 constexpr int LDS_MAX_BYTES = 160 * 1024;
 constexpr int inwave_levels(int M, int P, int LW) {
   int lw = LW;
   while (lw > 0) {
     const long c = (long)cst_count(M, lw + 1) * 8, t = (long)M * P * 8;
-    const long need = (M <= 64) ? t + c : (c > t ? c : t);
-    if (need <= LDS_MAX_BYTES) break;
+    if (t + c <= LDS_MAX_BYTES) break;
     --lw;
   }
   return lw;
@@ -121,7 +119,7 @@ constexpr int inwave_levels(int M, int P, int LW) {
 // At M >= 128 every thread holds 16 points of a column, so the in-wave form would
 // repeat each level's FP64 work in all 4^l threads of a bin and stage up to 136 KB
 // of constants per workgroup; the LDS form computes each coarse bin once
-// (cfg-3 step launch 38.7 -> 35.7 us).
+// (1024 x 1024 object, 128 x 128 probe, 256 positions per launch: 38.7 -> 35.7 us).
 constexpr int VCYCLE_LDS_MIN_M = 128;
 template <int M, int RB>
 constexpr int inwave_depth() {
@@ -375,7 +373,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // cross-lane exchanges in VALU form while the plan runs few waves per SIMD
   // (up to 512 threads); the 1024-thread plans, whose LDS pipe and VALU are both
   // about half busy, keep distances 4 and 16 in the LDS pipe (measured: all in
-  // VALU form +4 us per cfg 3 launch, 4 or 16 as well +0.3-0.8 us, 32 alone -0.2 us)
+  // VALU form +4 us per launch on the 1024 x 1024 object with the 128 x 128 probe, 4 or 16 as well +0.3-0.8 us, 32 alone -0.2 us)
   constexpr int XV = TPB <= 512 ? XOR_ALL_VALU : 32;
   extern __shared__ double2 smem_d2[];
   float2* T = reinterpret_cast<float2*>(smem_d2);
@@ -422,10 +420,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr bool PREQ = (RA <= 8);        // probe table entries in flight with the gather
   // MODE_STEP_PR is the object step with the eq. (3.2) phase store
   constexpr bool STEPM = (MODE == MODE_STEP) || (MODE == MODE_STEP_PR);
+  // in-wave V-cycle constants parked in LDS beside the tile (M <= 64; larger M
+  // takes the V-cycle through LDS, which reads its constants from memory)
   constexpr bool CST = STEPM && (M <= 64) && (LWI > 0);
-  // M = 128: the V-cycle constants do not fit beside the FFT tile; they are
-  // staged into the tile once the FFT and the gradient are done with it.
-  constexpr bool CSTL = STEPM && (M > 64) && (LWI > 0);
   // The twiddle table reads go first (small, needed by the first FFT stage).
   float2 qk[KEEP ? RA : 1];
   float u0k[KEEP ? RA : 1];
@@ -491,7 +488,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     // before the first transpose) and sqrt(d) (needed at the modulus) are issued
     // after the patch, in the order they are needed: loads return in issue
     // order, so issued first they had held up the patch the barrier below waits
-    // for (cfg 2 epoch: -2 % for sqrt(d) and the constants, -1.3 % for the
+    // for (512 x 512 object, 64 x 64 probe: epoch -2 % for sqrt(d) and the constants, -1.3 % for the
     // table, -0.6 % for the constants ahead of sqrt(d)).
     if constexpr (PREQ) {
 #pragma unroll
@@ -758,27 +755,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         // Chunks of NC register rows: while every restriction pairs rows across
         // lanes (LW <= log2 RB) the rows n1 are independent.
         // in-thread row pairs (levels above log2 RB) stay inside aligned chunks of NC
-        if constexpr (CSTL) {
-          // every wave is done with the tile: stage A_l, V_l there
-          __syncthreads();
-          const int nC = cst_count(M, L);
-          const double2* src = reinterpret_cast<const double2*>(a.lvl + a.lvl_a_off);
-          double2* dst = reinterpret_cast<double2*>(T);
-          // every copy of a thread in flight at once (a loop trip per load was latency-bound)
-          constexpr int NSTG = (cst_count_max(M, LWI) / 2 + 1 + TPB - 1) / TPB;   // copies per thread at most
-          double2 tmp[NSTG];
-#pragma unroll
-          for (int i = 0; i < NSTG; ++i) {
-            const int e = tid + i * TPB;
-            tmp[i] = (2 * e < nC) ? src[e] : make_double2(0.0, 0.0);
-          }
-#pragma unroll
-          for (int i = 0; i < NSTG; ++i) {
-            const int e = tid + i * TPB;
-            if (2 * e < nC) dst[e] = tmp[i];
-          }
-          __syncthreads();
-        }
         constexpr int NCB = (M >= 128) ? 2 : 4;
         constexpr int NCP = (LW > LRB) ? (1 << (LW - LRB)) : 1;
         constexpr int NC0 = NCP > NCB ? NCP : NCB;
@@ -812,9 +788,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
                   s[i] = make_double2(cur[i].x + o.x, cur[i].y + o.y);
                 }
               }
-              const double* Cb = CST ? (const double*)Cst : reinterpret_cast<const double*>(T);
-              const double* A = ((CST || CSTL) ? Cb : Abase) + (size_t)(l - 1) * M1c * M1c;
-              const double* V = (CST || CSTL) ? Cb + cst_v_off(M, L, l) : a.lvl + lv_off;
+              const double* Cb = (const double*)Cst;
+              const double* A = (CST ? Cb : Abase) + (size_t)(l - 1) * M1c * M1c;
+              const double* V = CST ? Cb + cst_v_off(M, L, l) : a.lvl + lv_off;
               const bool more = (l + 1 < L);
 #pragma unroll
               for (int i = 0; i < NC; ++i) {
@@ -891,8 +867,7 @@ constexpr size_t lds_bytes_c() {
   constexpr int LW = inwave_depth<M, RB>();
   size_t b = (size_t)M * P * sizeof(float2);
   const size_t c = (size_t)((cst_count_max(M, LW) + 1) & ~1) * sizeof(double);
-  if (M <= 64) b += c;          // constants parked beside the tile
-  else if (c > b) b = c;        // constants staged into the tile after the FFT
+  b += c;                       // in-wave constants parked beside the tile (none where LW = 0)
   return b;
 }
 template <int M, int RB>
@@ -980,7 +955,7 @@ size_t step_lds_bytes(int m, int rb) {
 // rows 2w, 2w+1, 2w+8, 2w+9, ... .  32-column tiles are overlapped by fewer
 // positions than 64-column ones (a window reaches a tile from a 32 + m - 1
 // column range instead of 64 + m - 1), so each pixel loops over fewer members
-// that do not cover it (cfg 2 epoch -3 % against 64 x 4 tiles).  The positions
+// that do not cover it (512 x 512 object, 64 x 64 probe: epoch -3 % against 64 x 4 tiles).  The positions
 // overlapping the tile (ascending index, with their offsets) are screened 256
 // at a time in parallel: those in minibatch t are compacted, order preserved,
 // into LDS, then every thread sums their staged c_k and w0 over its pixels in

@@ -154,7 +154,7 @@ def make_problem_inputs(cfg: ScanConfig):
 
 @dataclasses.dataclass(frozen=True)
 class BatchedRecon:
-    """One reconstruction of the batched workload (cfg 4)."""
+    """One reconstruction of the batched workload (64 independent reconstructions)."""
 
     index: int
     n: int
@@ -172,7 +172,7 @@ class BatchedRecon:
 
 
 def batched_workload(count: int = 64, cfg_id: int = 4):
-    """cfg 4: `count` independent reconstructions of uneven size.
+    """The batched workload: `count` independent reconstructions of uneven size.
 
     Per reconstruction: n ~ U{256, 384, 512, 768, 1024}, m ~ U{64, 128},
     P ~ U{20..80} (capped so the raster fits), step = min(10, (n-m-2)//(P-1)),

@@ -21,7 +21,8 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.gpu
 def test_bench_line_fields():
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1",
-                          "--no-autotune", "--race-objects", "0", "--cpu-seconds", "1"],
+                          "--no-autotune", "--race-objects", "0", "--cpu-seconds", "1", "--cpu-seconds-single", "1",
+                          "--no-extra-workloads"],
                          capture_output=True, text=True, timeout=110, cwd=ROOT)
     print(res.stderr[-2000:], flush=True)
     assert res.returncode == 0

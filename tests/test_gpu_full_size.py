@@ -147,7 +147,7 @@ def test_full_size_steps_match_oracle(cfg_id, first, steps):
         rel = _rel(zg, zo, mask)
         relx = _relx(zg, zo, cfg, offs)
         _, floor_x = _fp32_fft_step_errors(cfg, Q32, offs, sd32, chunk, z_in, mask)
-        print(f"cfg {cfg_id} minibatch {t}: plan {tuning}, rel {rel:.2e}, element-wise {relx:.2e} "
+        print(f"{cfg.n}x{cfg.n} minibatch {t}: plan {tuning}, rel {rel:.2e}, element-wise {relx:.2e} "
               f"(FP32 floor {floor_x:.2e})", flush=True)
         assert rel <= 1e-5
         assert relx <= max(1e-5, 2.0 * floor_x)

@@ -148,8 +148,8 @@ def test_step_phi_matches_objective_terms():
     np.testing.assert_allclose(ph, want, rtol=2e-5)
 
 
-def test_several_epochs_cfg1_geometry():
-    """cfg-1 sizes (n=128, m=32, 8x8 raster, L=2, B=8), 20 epochs from the flat start.
+def test_several_epochs_128_workload():
+    """The 128 x 128 workload (n=128, m=32, 8x8 raster, L=2, B=8), 20 epochs from the flat start.
 
     Gated: every epoch started from the GPU's own z agrees with one oracle
     epoch from that z (<= 1e-5), and the objective after 20 epochs of the two
@@ -189,7 +189,7 @@ def test_several_epochs_cfg1_geometry():
     zo = oracle.run_epochs(z0.astype(np.complex128), Qd, offs, sd, u, cfg.levels, orders, cfg.batch)
     phi_o = oracle.objective(zo, Qd, offs, sd)
     drift = np.linalg.norm((zg - zo)[mask]) / np.linalg.norm(zo[mask])
-    _print("cfg1 worst per-epoch rel", worst, "phi", phi_g, phi_o, "trajectory drift", drift)
+    _print("128 x 128 workload: worst per-epoch rel", worst, "phi", phi_g, phi_o, "trajectory drift", drift)
     assert worst <= 1e-5
     assert abs(phi_g - phi_o) <= 1e-4 * phi_o
 

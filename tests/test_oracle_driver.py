@@ -3,7 +3,7 @@
 * one position per minibatch == Alg 4 (sequential MAGPIE);
 * one grid == Alg 1 (rPIE) with eq. (2.3);
 * the truth (and any global phase of it) is a fixed point for noiseless data;
-* near-truth starts converge on the cfg-1 geometry (noiseless);
+* near-truth starts converge on the 128 x 128 workload's geometry (noiseless);
 * the library's splitmix64 permutation generator reproduces the published
   splitmix64 test vector and yields permutations;
 * phase recycling (eq. 3.2): no effect without exact zeros, theta = 0 on the first
@@ -79,7 +79,7 @@ def _cfg1_problem():
 @pytest.mark.slow
 @pytest.mark.parametrize("L,B", [(1, 1), (2, 8), (3, 1)])
 def test_recovery_near_truth_cfg1(L, B):
-    """Noiseless cfg 1 from z* (1 + 0.05 CN(0,1)): the masked relative error falls >= 20x in 60 epochs."""
+    """Noiseless 128 x 128 workload from z* (1 + 0.05 CN(0,1)): the masked relative error falls >= 20x in 60 epochs."""
     cfg, zt, Q, offs, sd, r_perm = _cfg1_problem()
     rng = np.random.default_rng(7)
     z0 = zt * (1 + 0.05 * (rng.standard_normal(zt.shape) + 1j * rng.standard_normal(zt.shape)) / np.sqrt(2))
