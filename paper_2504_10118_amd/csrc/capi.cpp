@@ -220,8 +220,7 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   for (int l = 1; l < n_levels; ++l) nlvl += 3 * (size_t)(m >> l) * (m >> l);
   nlvl = (nlvl + 1) & ~(size_t)1;          // the A block starts 16-byte aligned (read as double pairs)
   c->lvl_a_off = (int)nlvl;
-  nlvl += (size_t)(n_levels - 1) * half;   // A_l coefficients per level-1 bin
-  for (int l = 1; l <= n_levels - 2; ++l) nlvl += (size_t)(m >> l) * (m >> l);  // copies of V_l
+  nlvl += (size_t)mg::cst_count(m, n_levels);  // the in-wave V-cycle block: A_l per level-1 bin, copies of V_l
   nlvl += 2;                               // a pair read may cover one double past the block
   rc = dev_alloc(&c->z, (size_t)n_rows * n_cols);
   if (!rc) rc = dev_alloc(&c->qf, mm);

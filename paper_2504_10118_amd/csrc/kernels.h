@@ -12,6 +12,22 @@ constexpr int MODE_STEP_PR = 3;
 
 constexpr int MAX_WAVES = 16;   // per-position partial sums (one per wave of a workgroup)
 
+// The in-wave V-cycle's constant block (doubles), laid out for LDS: A_1..A_{L-1}
+// at level-1 resolution, then V_1..V_{L-2} at their own resolutions; every row of
+// a grid of side s is padded to s + CST_PAD doubles, so that the rows the lanes of
+// one LDS access read fall in different banks.
+constexpr int CST_PAD = 2;
+__host__ __device__ constexpr int cst_count(int M, int L) {
+  int n = (L - 1) * (M / 2) * (M / 2 + CST_PAD);
+  for (int l = 1; l <= L - 2; ++l) n += (M >> l) * ((M >> l) + CST_PAD);
+  return n;
+}
+__host__ __device__ constexpr int cst_v_off(int M, int L, int l) {
+  int n = (L - 1) * (M / 2) * (M / 2 + CST_PAD);
+  for (int j = 1; j < l; ++j) n += (M >> j) * ((M >> j) + CST_PAD);
+  return n;
+}
+
 // Arguments of the per-position kernel (one workgroup per scan position).
 struct StepArgs {
   const float2* z;        // object [n_rows][n_cols]
@@ -29,7 +45,7 @@ struct StepArgs {
   const float4* qtab;     // probe table in the plan's thread order [n1][tid], pixel (RB*n1 + g, col): m <= 64
                           // (Re Q, Im Q, u0, 0) per entry; m = 128 m*m float2 Q, then m*m float u0
   const double* lvl;      // coarse-level constants (V, rho, r per level), then A_l
-  int lvl_a_off;          // offset in lvl of the in-wave V-cycle block: A_1..A_{L-1}, then V_1..V_{L-2}
+  int lvl_a_off;          // offset in lvl of the in-wave V-cycle block (cst_count(m, L) doubles)
   int levels;             // number of grids L
   double* phi_part;       // per-wave partials of Phi_k [N][MAX_WAVES] (nullable)
   double* gn_part;        // MODE_OBJECTIVE: per-wave partials of ||grad_k||^2 [N][MAX_WAVES]

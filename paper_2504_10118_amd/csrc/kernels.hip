@@ -53,10 +53,26 @@ hipError_t init_twiddles(hipStream_t s) {
 
 // FFT plan: RB threads per 1-D transform, RA = M / RB points per thread
 // (RA >= RB), PAD = row padding of the LDS transpose tile in float2.
+//
+// LDS banks: 64 banks of 4 bytes; the lanes of a 64-bit access are served 32 at
+// a time (a float2 slot s sits in bank pair s mod 32), those of a 128-bit access
+// 16 at a time.  With 8 threads per transform a wave holds 8 columns (column
+// passes) or 8 rows (row passes) of the tile, and lane (cl, g) = (lane / 8,
+// lane % 8).  For M >= 64 an odd pitch M + 5 makes the column-slice exchanges
+// and the gathers conflict-free and leaves the transposes one extra cycle per
+// access, and the row-slice exchange stores a wave's values point-major,
+// slot n2 * PX + cl * RA + k1 from the first row of its slice (PX = M + 1 at
+// M = 64, M + 2 at M = 128, where the stores pair into 128-bit writes): both its
+// stores (k1 fixed) and its loads (n2 fixed) then spread over all bank pairs.
+// Smaller plans keep pitch M + 2 and the row-major exchange (cl * P + k1 * RB + n2).
 template <int M, int RB_>
 struct Plan {
-  static constexpr int RB = RB_, RA = M / RB_, PAD = 2;
+  static constexpr int RB = RB_, RA = M / RB_;
+  static constexpr bool WIDE = (M >= 64 && RB_ == 8);
+  static constexpr int PAD = WIDE ? 5 : 2;
+  static constexpr int PX = M == 64 ? M + 1 : M + 2;
   static_assert(RA >= RB && RA % RB == 0, "stage B needs RA a multiple of RB");
+  static_assert(!WIDE || 7 * PX + M <= 8 * (M + PAD), "row-slice exchange exceeds the wave's rows");
 };
 
 template <int M>
@@ -88,18 +104,6 @@ __device__ __forceinline__ void powers(int b, float2 (&w)[R]) {
   }
 }
 
-// In-wave V-cycle block (doubles): A_1..A_{L-1} at level-1 resolution, then
-// V_1..V_{L-2} at their own resolutions.
-__host__ __device__ constexpr int cst_count(int M, int L) {
-  int n = (L - 1) * (M / 2) * (M / 2);
-  for (int l = 1; l <= L - 2; ++l) n += (M >> l) * (M >> l);
-  return n;
-}
-__host__ __device__ constexpr int cst_v_off(int M, int L, int l) {
-  int n = (L - 1) * (M / 2) * (M / 2);
-  for (int j = 1; j < l; ++j) n += (M >> j) * (M >> j);
-  return n;
-}
 constexpr int cst_count_max(int M, int LW) { return cst_count(M, LW + 1); }
 
 // Deepest in-wave V-cycle (number of coarse levels, at most LW) whose constants
@@ -260,14 +264,23 @@ __device__ __forceinline__ bool modulus_diff(float2 t, float s, float2& out, flo
 
 // MAGPS V-cycle through LDS for hierarchies whose coarse bins span several
 // waves.  On entry g0 is in T[y][x] (pitch P) and in v (thread (x, g) holds
-// rows RB*n1 + g).  Coarse grids (FP64) overwrite the start of the LDS tile.
+// rows RB*n1 + g).  Coarse grids (FP64) overwrite the start of the LDS tile:
+// level 1 with rows padded to M / 2 + 1 (the final prolongation reads 4 rows of it
+// per 16 lanes, in 4 different banks), then levels 2.. unpadded.
 template <int M, int TPB, int P, int RB, int RA>
 __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const float2* v, int col, int g,
                           float2* outp) {
   const int tid = threadIdx.x;
   const int L = a.levels;
-  constexpr int M1 = M / 2;
+  constexpr int M1 = M / 2, S1 = M1 + 1;
   constexpr int E1 = (M1 * M1 + TPB - 1) / TPB;
+  // level l's grid: offset and row pitch in C
+  auto off_of = [&](int l) {
+    int o = 0;
+    for (int j = 1; j < l; ++j) o += (j == 1) ? M1 * S1 : (M >> j) * (M >> j);
+    return o;
+  };
+  auto pitch_of = [&](int l) { return l == 1 ? S1 : (M >> l); };
   double2 gh1[E1];
 #pragma unroll
   for (int i = 0; i < E1; ++i) {
@@ -293,21 +306,21 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
         const double rr = r1[e];
         v = make_double2(-rr * v.x, -rr * v.y);
       }
-      C[e] = v;
+      C[(e / M1) * S1 + e % M1] = v;
     }
   }
   // restriction down: g^_l = I(V_{l-1} g^_{l-1}); coarsest: e = -r g^
-  int off_prev = 0, lv_prev = 0, Mp = M1;
+  int lv_prev = 0, Mp = M1;
   for (int l = 2; l < L; ++l) {
     __syncthreads();
     const int Ml = Mp >> 1;
-    const int off_cur = off_prev + Mp * Mp;
+    const int off_prev = off_of(l - 1), sp = pitch_of(l - 1), off_cur = off_of(l);
     const int lv_cur = lv_prev + 3 * Mp * Mp;
     const double* Vp = a.lvl + lv_prev;
     const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
     for (int e = tid; e < Ml * Ml; e += TPB) {
       const int Y = e / Ml, X = e % Ml;
-      const int c0 = off_prev + (2 * Y) * Mp + 2 * X, c1 = c0 + Mp;
+      const int c0 = off_prev + (2 * Y) * sp + 2 * X, c1 = c0 + sp;
       const int i0 = (2 * Y) * Mp + 2 * X, i1 = i0 + Mp;
       double2 s;
       s.x = 0.25 * ((Vp[i0] * C[c0].x + Vp[i0 + 1] * C[c0 + 1].x) + (Vp[i1] * C[c1].x + Vp[i1 + 1] * C[c1 + 1].x));
@@ -319,7 +332,6 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
       }
       C[off_cur + e] = s;
     }
-    off_prev = off_cur;
     lv_prev = lv_cur;
     Mp = Ml;
   }
@@ -327,18 +339,17 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
   for (int l = L - 2; l >= 1; --l) {
     __syncthreads();
     const int Ml = Mp << 1;
-    const int off_cur = off_prev - Ml * Ml;
+    const int off_prev = off_of(l + 1), sp = pitch_of(l + 1), off_cur = off_of(l), sc = pitch_of(l);
     const int lv_cur = lv_prev - 3 * Ml * Ml;
     const double* rhol = a.lvl + lv_cur + Ml * Ml;
     const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
     for (int e = tid; e < Ml * Ml; e += TPB) {
       const int Y = e / Ml, X = e % Ml;
-      const double2 ec = C[off_prev + (Y >> 1) * Mp + (X >> 1)];
-      const double2 gh = C[off_cur + e];
+      const double2 ec = C[off_prev + (Y >> 1) * sp + (X >> 1)];
+      const double2 gh = C[off_cur + Y * sc + X];
       const double rh = rhol[e], rr = rl[e];
-      C[off_cur + e] = make_double2(rh * ec.x - rr * gh.x, rh * ec.y - rr * gh.y);
+      C[off_cur + Y * sc + X] = make_double2(rh * ec.x - rr * gh.x, rh * ec.y - rr * gh.y);
     }
-    off_prev = off_cur;
     lv_prev = lv_cur;
     Mp = Ml;
   }
@@ -347,7 +358,7 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
 #pragma unroll
   for (int n1 = 0; n1 < RA; ++n1) {
     const int y = RB * n1 + g;
-    const double2 e1 = C[(y >> 1) * M1 + (col >> 1)];
+    const double2 e1 = C[(y >> 1) * S1 + (col >> 1)];
     const double uu = (double)a.u0f[y * M + col];
     bstore2_stage(outr, make_float2((float)(uu * e1.x - (double)v[n1].x), (float)(uu * e1.y - (double)v[n1].y)),
                   (y * M + col) * (int)sizeof(float2), 0, a.stage_wt != 0);
@@ -400,6 +411,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   auto xi = [&](int k1, int n2) { return (cl * RA + k1) * RB + n2; };
   auto colslice = [&](int i) { return T + (i / CPW) * P + c0w + (i & (CPW - 1)); };
   auto rowslice = [&](int i) { return T + (c0w + i / M) * P + (i & (M - 1)); };
+  // row-slice exchange slot of this thread's value (k1, n2)
+  auto rx = [&](int k1, int n2) {
+    if constexpr (Plan<M, RBv>::WIDE) return T + c0w * P + n2 * Plan<M, RBv>::PX + cl * RA + k1;
+    else return rowslice(xi(k1, n2));
+  };
 
   // ---- gather z_k, exit wave Q * z_k: thread (x = col, g) holds rows y = RB*n1 + g
   float2 v[RA];
@@ -575,12 +591,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   for (int k1 = 1; k1 < RA; ++k1) v[k1] = cmul(v[k1], twA[k1]);
   wave_sync();
 #pragma unroll
-  for (int k1 = 0; k1 < RA; ++k1) *rowslice(xi(k1, g)) = v[k1];
+  for (int k1 = 0; k1 < RA; ++k1) *rx(k1, g) = v[k1];
   wave_sync();
 #pragma unroll
   for (int c = 0; c < CB; ++c)
 #pragma unroll
-    for (int n2 = 0; n2 < RB; ++n2) v[c * RB + n2] = *rowslice(xi(g * CB + c, n2));
+    for (int n2 = 0; n2 < RB; ++n2) v[c * RB + n2] = *rx(g * CB + c, n2);
 #pragma unroll
   for (int c = 0; c < CB; ++c) dft<RB, 1>(&v[c * RB]);
   // v[c*RB + k2] = Psi[ky = col][kx = g*CB + c + RA*k2]
@@ -658,10 +674,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
-      for (int n2 = 0; n2 < RB; ++n2) *rowslice(xi(g * CB + c, n2)) = v[c * RB + n2];
+      for (int n2 = 0; n2 < RB; ++n2) *rx(g * CB + c, n2) = v[c * RB + n2];
     wave_sync();
 #pragma unroll
-    for (int k1 = 0; k1 < RA; ++k1) v[k1] = *rowslice(xi(k1, g));
+    for (int k1 = 0; k1 < RA; ++k1) v[k1] = *rx(k1, g);
     dft<RA, -1>(v);
     wave_sync();
     // v[n1] = row ky = col at x = RB*n1 + g; transpose back into T[ky][x] (own rows)
@@ -759,7 +775,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         constexpr int NCP = (LW > LRB) ? (1 << (LW - LRB)) : 1;
         constexpr int NC0 = NCP > NCB ? NCP : NCB;
         constexpr int NC = NC0 < RA ? NC0 : RA;
-        const double* Abase = a.lvl + a.lvl_a_off;
 #pragma unroll
         for (int n0 = 0; n0 < RA; n0 += NC) {
           double2 cur[NC], e1[NC];
@@ -768,7 +783,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
             cur[i] = make_double2(v[n0 + i].x, v[n0 + i].y);
             e1[i] = make_double2(0.0, 0.0);
           }
-          int lv_off = 0;
 #pragma unroll
           for (int l = 1; l <= LWI; ++l) {
             if (l < L) {
@@ -788,23 +802,22 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
                   s[i] = make_double2(cur[i].x + o.x, cur[i].y + o.y);
                 }
               }
-              const double* Cb = (const double*)Cst;
-              const double* A = (CST ? Cb : Abase) + (size_t)(l - 1) * M1c * M1c;
-              const double* V = CST ? Cb + cst_v_off(M, L, l) : a.lvl + lv_off;
+              // A_l and V_l from the block parked in LDS (rows padded by CST_PAD)
+              const double* A = (const double*)Cst + (size_t)(l - 1) * M1c * (M1c + CST_PAD);
+              const double* V = (const double*)Cst + cst_v_off(M, L, l);
               const bool more = (l + 1 < L);
 #pragma unroll
               for (int i = 0; i < NC; ++i) {
                 const double2 o = xor_lane_rt<XV>(s[i], RB << (l - 1));
                 const double2 gh = make_double2(0.25 * (s[i].x + o.x), 0.25 * (s[i].y + o.y));
                 const int y = RB * (n0 + i) + g;
-                const double aa = A[(y >> 1) * (M / 2) + (col >> 1)];
+                const double aa = A[(y >> 1) * (M1c + CST_PAD) + (col >> 1)];
                 e1[i] = make_double2(e1[i].x + aa * gh.x, e1[i].y + aa * gh.y);
                 if (more) {
-                  const double vv = V[(y >> l) * Ml + (col >> l)];
+                  const double vv = V[(y >> l) * (Ml + CST_PAD) + (col >> l)];
                   cur[i] = make_double2(vv * gh.x, vv * gh.y);
                 }
               }
-              lv_off += 3 * Ml * Ml;
             }
           }
           // level 0: c_k = u0 P(e_1) - g0
@@ -1247,32 +1260,40 @@ __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels
     Mp = Ml;
   }
   // A_l = -r_l prod_{j<l} rho_j along the ancestors of each level-1 bin, so
-  // that e_1 = sum_l A_l g^_l (the upward pass of the V-cycle, unrolled).
+  // that e_1 = sum_l A_l g^_l (the upward pass of the V-cycle, unrolled).  The
+  // in-wave V-cycle's block: A_1..A_{L-1}, then copies of V_1..V_{L-2}, every
+  // grid row padded to side + CST_PAD doubles (pads zero).
   __syncthreads();
   if (levels > 1) {
-    const int M1 = m / 2;
+    const int M1 = m / 2, S1 = M1 + CST_PAD;
     double* A = lvl + a_off;
-    for (int e = tid; e < M1 * M1; e += blockDim.x) {
-      const int Y1 = e / M1, X1 = e % M1;
+    for (int e = tid; e < M1 * S1; e += blockDim.x) {
+      const int Y1 = e / S1, X1 = e % S1;
       double prod = 1.0;
       int off = 0;
       for (int l = 1; l < levels; ++l) {
         const int Ml = m >> l;
-        const int idx = (Y1 >> (l - 1)) * Ml + (X1 >> (l - 1));
-        const double rho = lvl[off + Ml * Ml + idx];
-        const double r = lvl[off + 2 * Ml * Ml + idx];
-        A[(size_t)(l - 1) * M1 * M1 + e] = -r * prod;
-        prod *= rho;
+        double val = 0.0;
+        if (X1 < M1) {
+          const int idx = (Y1 >> (l - 1)) * Ml + (X1 >> (l - 1));
+          const double rho = lvl[off + Ml * Ml + idx];
+          const double r = lvl[off + 2 * Ml * Ml + idx];
+          val = -r * prod;
+          prod *= rho;
+        }
+        A[(size_t)(l - 1) * M1 * S1 + e] = val;
         off += 3 * Ml * Ml;
       }
     }
-    // copies of V_1..V_{L-2} right after the A block (the in-wave V-cycle's block)
-    double* Vc = A + (size_t)(levels - 1) * M1 * M1;
+    double* Vc = lvl + a_off + cst_v_off(m, levels, 1);
     int off = 0;
     for (int l = 1; l <= levels - 2; ++l) {
-      const int Ml = m >> l;
-      for (int e = tid; e < Ml * Ml; e += blockDim.x) Vc[e] = lvl[off + e];
-      Vc += Ml * Ml;
+      const int Ml = m >> l, Sl = Ml + CST_PAD;
+      for (int e = tid; e < Ml * Sl; e += blockDim.x) {
+        const int Y = e / Sl, X = e % Sl;
+        Vc[e] = X < Ml ? lvl[off + Y * Ml + X] : 0.0;
+      }
+      Vc += Ml * Sl;
       off += 3 * Ml * Ml;
     }
   }
