@@ -269,7 +269,7 @@ __device__ __forceinline__ bool modulus_diff(float2 t, float s, float2& out, flo
 // per 16 lanes, in 4 different banks), then levels 2.. unpadded.
 template <int M, int TPB, int P, int RB, int RA>
 __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const float2* v, int col, int g,
-                          float2* outp) {
+                          float2* stage_k) {
   const int tid = threadIdx.x;
   const int L = a.levels;
   constexpr int M1 = M / 2, S1 = M1 + 1;
@@ -354,7 +354,8 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     Mp = Ml;
   }
   __syncthreads();
-  const rsrc_t outr = make_rsrc(outp - col, (unsigned)(M * M * sizeof(float2)));
+  // stage_k (this position's staged update) is uniform, so the resource stays scalar
+  const rsrc_t outr = make_rsrc(stage_k, (unsigned)(M * M * sizeof(float2)));
 #pragma unroll
   for (int n1 = 0; n1 < RA; ++n1) {
     const int y = RB * n1 + g;
@@ -752,7 +753,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       if ((tid & 63) == 0) a.gn_part[(size_t)k * MAX_WAVES + wave] = tot;
       return;
     } else {
-      float2* outp = a.stage + (size_t)wg * M * M + col;
       const rsrc_t outr = make_rsrc(a.stage + (size_t)wg * M * M, (unsigned)(M * M * sizeof(float2)));
       const int ovo = (g * M + col) * (int)sizeof(float2);
       const int L = a.levels;
@@ -840,7 +840,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
       for (int n1 = 0; n1 < RA; ++n1) T[(RB * n1 + g) * P + col] = v[n1];
       __syncthreads();
-      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, col, g, outp);
+      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, col, g, a.stage + (size_t)wg * M * M);
     }
   }
 }
