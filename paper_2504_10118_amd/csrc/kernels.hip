@@ -264,16 +264,20 @@ __device__ __forceinline__ bool modulus_diff(float2 t, float s, float2& out, flo
 
 // MAGPS V-cycle through LDS for hierarchies whose coarse bins span several
 // waves.  On entry g0 is in T[y][x] (pitch P) and in v (thread (x, g) holds
-// rows RB*n1 + g).  Coarse grids (FP64) overwrite the start of the LDS tile:
-// level 1 with rows padded to M / 2 + 1 (the final prolongation reads 4 rows of it
-// per 16 lanes, in 4 different banks), then levels 2.. unpadded.
+// rows RB*n1 + g), and u0v holds u0 at the same pixels.  Coarse grids (FP64)
+// overwrite the start of the LDS tile: level 1 with rows padded to M / 2 + 1 (the
+// final prolongation reads 4 rows of it per 16 lanes, in 4 different banks), then
+// levels 2.. unpadded.  Each level's constants (V, rho, r: they do not depend on
+// the data) are loaded before the barrier that precedes the level, so their
+// latency overlaps the wait.
 template <int M, int TPB, int P, int RB, int RA>
-__device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const float2* v, int col, int g,
-                          float2* stage_k) {
+__device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const float2* v, const float* u0v,
+                          int col, int g, float2* stage_k) {
   const int tid = threadIdx.x;
   const int L = a.levels;
   constexpr int M1 = M / 2, S1 = M1 + 1;
-  constexpr int E1 = (M1 * M1 + TPB - 1) / TPB;
+  constexpr int E1 = (M1 * M1 + TPB - 1) / TPB;               // level-1 bins per thread
+  constexpr int E2 = ((M / 4) * (M / 4) + TPB - 1) / TPB;     // bins per thread on levels >= 2
   // level l's grid: offset and row pitch in C
   auto off_of = [&](int l) {
     int o = 0;
@@ -281,10 +285,14 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     return o;
   };
   auto pitch_of = [&](int l) { return l == 1 ? S1 : (M >> l); };
+  // two grids: level 1 is the coarsest, e_1 = -r_1 g^_1 (r_1 follows V_1, rho_1)
+  const double* r1 = a.lvl + 2 * M1 * M1;
+  double r1v[E1];
   double2 gh1[E1];
 #pragma unroll
   for (int i = 0; i < E1; ++i) {
     const int e = tid + i * TPB;
+    r1v[i] = (L == 2 && e < M1 * M1) ? r1[e] : 0.0;
     gh1[i] = make_double2(0.0, 0.0);
     if (e < M1 * M1) {
       const int Y = e / M1, X = e % M1;
@@ -295,60 +303,84 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     }
   }
   __syncthreads();
-  // two grids: level 1 is the coarsest, e_1 = -r_1 g^_1 (r_1 follows V_1, rho_1)
-  const double* r1 = a.lvl + 2 * M1 * M1;
 #pragma unroll
   for (int i = 0; i < E1; ++i) {
     const int e = tid + i * TPB;
     if (e < M1 * M1) {
-      double2 v = gh1[i];
-      if (L == 2) {
-        const double rr = r1[e];
-        v = make_double2(-rr * v.x, -rr * v.y);
-      }
-      C[(e / M1) * S1 + e % M1] = v;
+      double2 w = gh1[i];
+      if (L == 2) w = make_double2(-r1v[i] * w.x, -r1v[i] * w.y);
+      C[(e / M1) * S1 + e % M1] = w;
     }
   }
   // restriction down: g^_l = I(V_{l-1} g^_{l-1}); coarsest: e = -r g^
   int lv_prev = 0, Mp = M1;
   for (int l = 2; l < L; ++l) {
-    __syncthreads();
     const int Ml = Mp >> 1;
     const int off_prev = off_of(l - 1), sp = pitch_of(l - 1), off_cur = off_of(l);
     const int lv_cur = lv_prev + 3 * Mp * Mp;
     const double* Vp = a.lvl + lv_prev;
     const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
-    for (int e = tid; e < Ml * Ml; e += TPB) {
-      const int Y = e / Ml, X = e % Ml;
-      const int c0 = off_prev + (2 * Y) * sp + 2 * X, c1 = c0 + sp;
-      const int i0 = (2 * Y) * Mp + 2 * X, i1 = i0 + Mp;
-      double2 s;
-      s.x = 0.25 * ((Vp[i0] * C[c0].x + Vp[i0 + 1] * C[c0 + 1].x) + (Vp[i1] * C[c1].x + Vp[i1 + 1] * C[c1 + 1].x));
-      s.y = 0.25 * ((Vp[i0] * C[c0].y + Vp[i0 + 1] * C[c0 + 1].y) + (Vp[i1] * C[c1].y + Vp[i1 + 1] * C[c1 + 1].y));
-      if (l == L - 1) {
-        const double rr = rl[e];
-        s.x = -rr * s.x;
-        s.y = -rr * s.y;
+    double vq[E2][4], rq[E2];
+#pragma unroll
+    for (int i = 0; i < E2; ++i) {
+      const int e = tid + i * TPB;
+      rq[i] = 0.0;
+      vq[i][0] = vq[i][1] = vq[i][2] = vq[i][3] = 0.0;
+      if (e < Ml * Ml) {
+        const int Y = e / Ml, X = e % Ml;
+        const int i0 = (2 * Y) * Mp + 2 * X, i1 = i0 + Mp;
+        vq[i][0] = Vp[i0];
+        vq[i][1] = Vp[i0 + 1];
+        vq[i][2] = Vp[i1];
+        vq[i][3] = Vp[i1 + 1];
+        if (l == L - 1) rq[i] = rl[e];
       }
-      C[off_cur + e] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E2; ++i) {
+      const int e = tid + i * TPB;
+      if (e < Ml * Ml) {
+        const int Y = e / Ml, X = e % Ml;
+        const int c0 = off_prev + (2 * Y) * sp + 2 * X, c1 = c0 + sp;
+        double2 s;
+        s.x = 0.25 * ((vq[i][0] * C[c0].x + vq[i][1] * C[c0 + 1].x) + (vq[i][2] * C[c1].x + vq[i][3] * C[c1 + 1].x));
+        s.y = 0.25 * ((vq[i][0] * C[c0].y + vq[i][1] * C[c0 + 1].y) + (vq[i][2] * C[c1].y + vq[i][3] * C[c1 + 1].y));
+        if (l == L - 1) {
+          s.x = -rq[i] * s.x;
+          s.y = -rq[i] * s.y;
+        }
+        C[off_cur + e] = s;
+      }
     }
     lv_prev = lv_cur;
     Mp = Ml;
   }
   // prolongation up: e_l = rho_l P(e_{l+1}) - r_l g^_l for l = L-2 .. 1
   for (int l = L - 2; l >= 1; --l) {
-    __syncthreads();
     const int Ml = Mp << 1;
     const int off_prev = off_of(l + 1), sp = pitch_of(l + 1), off_cur = off_of(l), sc = pitch_of(l);
     const int lv_cur = lv_prev - 3 * Ml * Ml;
     const double* rhol = a.lvl + lv_cur + Ml * Ml;
     const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
-    for (int e = tid; e < Ml * Ml; e += TPB) {
-      const int Y = e / Ml, X = e % Ml;
-      const double2 ec = C[off_prev + (Y >> 1) * sp + (X >> 1)];
-      const double2 gh = C[off_cur + Y * sc + X];
-      const double rh = rhol[e], rr = rl[e];
-      C[off_cur + Y * sc + X] = make_double2(rh * ec.x - rr * gh.x, rh * ec.y - rr * gh.y);
+    double rh[E1], rr[E1];
+#pragma unroll
+    for (int i = 0; i < E1; ++i) {
+      const int e = tid + i * TPB;
+      const bool in = e < Ml * Ml;
+      rh[i] = in ? rhol[e] : 0.0;
+      rr[i] = in ? rl[e] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E1; ++i) {
+      const int e = tid + i * TPB;
+      if (e < Ml * Ml) {
+        const int Y = e / Ml, X = e % Ml;
+        const double2 ec = C[off_prev + (Y >> 1) * sp + (X >> 1)];
+        const double2 gh = C[off_cur + Y * sc + X];
+        C[off_cur + Y * sc + X] = make_double2(rh[i] * ec.x - rr[i] * gh.x, rh[i] * ec.y - rr[i] * gh.y);
+      }
     }
     lv_prev = lv_cur;
     Mp = Ml;
@@ -360,7 +392,7 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
   for (int n1 = 0; n1 < RA; ++n1) {
     const int y = RB * n1 + g;
     const double2 e1 = C[(y >> 1) * S1 + (col >> 1)];
-    const double uu = (double)a.u0f[y * M + col];
+    const double uu = (double)u0v[n1];
     bstore2_stage(outr, make_float2((float)(uu * e1.x - (double)v[n1].x), (float)(uu * e1.y - (double)v[n1].y)),
                   (y * M + col) * (int)sizeof(float2), 0, a.stage_wt != 0);
   }
@@ -835,12 +867,20 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         }
         return;
       }
-      // ---- deep hierarchies (coarse bins wider than a wave): V-cycle through LDS
+      // ---- deep hierarchies (coarse bins wider than a wave): V-cycle through LDS.
+      // u0 of this thread's pixels: from registers, or (M = 128) from the
+      // thread-ordered table, loaded here so that the V-cycle hides the latency.
+      float u0v[RA];
+#pragma unroll
+      for (int n1 = 0; n1 < RA; ++n1) {
+        if constexpr (KEEP) u0v[n1] = u0k[n1];
+        else u0v[n1] = ut[n1 * TPB];
+      }
       __syncthreads();
 #pragma unroll
       for (int n1 = 0; n1 < RA; ++n1) T[(RB * n1 + g) * P + col] = v[n1];
       __syncthreads();
-      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, col, g, a.stage + (size_t)wg * M * M);
+      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, u0v, col, g, a.stage + (size_t)wg * M * M);
     }
   }
 }
