@@ -33,6 +33,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+BATCHED = "64-reconstructions"   # 64 independent reconstructions of uneven size
 ROOT = os.path.dirname(os.path.abspath(__file__))
 ACC_TILE_W = 32           # accumulation tile width of the library (columns)
 
@@ -50,13 +51,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(cfg_id: int, m: int, rb: int, kind: str = "step"):
+def stored_traffic(workload: str, m: int, rb: int, kind: str = "step"):
     """Counter-measured HBM bytes per launch of the step kernel (full launches) or of the
     accumulation kernel (kind "accumulate", mean over its launches), from the committed
     rocprofv3 summary, if it was taken on the current kernel sources (and, for the step
     kernel, with the same FFT plan: threads per transform rb)."""
-    from synth import CONFIGS
-    n = CONFIGS[cfg_id].n
+    from synth import WORKLOADS
+    n = WORKLOADS[workload].n
     name = f"step_kernel_m{m}_n{n}.md" if kind == "step" else f"accumulate_kernel_n{n}.md"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
@@ -84,9 +85,9 @@ def stored_traffic(cfg_id: int, m: int, rb: int, kind: str = "step"):
         return None
 
 
-def workload_inputs(cfg_id: int):
-    from synth import CONFIGS, make_problem_inputs
-    cfg = CONFIGS[cfg_id]
+def workload_inputs(workload: str):
+    from synth import WORKLOADS, make_problem_inputs
+    cfg = WORKLOADS[workload]
     z_true, Q, offs, r_noise, _ = make_problem_inputs(cfg)
     return cfg, z_true.astype(np.complex64), Q.astype(np.complex64), offs, r_noise
 
@@ -183,11 +184,11 @@ def cpu_baseline(n, Q, offs, sqrt_d, levels, batch, alpha, seed, seconds, worker
     return done, dt, nb
 
 
-def cpu_baselines(cfg_id, seconds_multi, seconds_single, seed):
+def cpu_baselines(workload, seconds_multi, seconds_single, seed):
     """Oracle patterns/s on a workload: all usable cores and one core."""
     import oracle
-    from synth import CONFIGS, make_problem_inputs, poisson_counts
-    cfg = CONFIGS[cfg_id]
+    from synth import WORKLOADS, make_problem_inputs, poisson_counts
+    cfg = WORKLOADS[workload]
     z, Q, offs, r_noise, _ = make_problem_inputs(cfg)
     Q32 = Q.astype(np.complex64)
     d = oracle.forward_model(z.astype(np.complex64).astype(np.complex128), Q32.astype(np.complex128), offs)
@@ -242,15 +243,15 @@ def learned_race(n_objects: int):
     }
 
 
-def run_single(cfg_id, steps, warmup, seed, batch=None, levels=None, alpha=None, tuning="", autotune=True,
+def run_single(workload, steps, warmup, seed, batch=None, levels=None, alpha=None, tuning="", autotune=True,
                device_noise=False):
-    """One reconstruction of workload cfg_id: timed epochs (production path), then the
+    """One reconstruction of the named workload: timed epochs (production path), then the
     same epochs with per-launch events.  Returns a dict of figures."""
     import torch
     from paper_2504_10118_amd import Magpie
     from synth import poisson_counts, poisson_counts_device
 
-    cfg, z_true, Q32, offs, r_noise = workload_inputs(cfg_id)
+    cfg, z_true, Q32, offs, r_noise = workload_inputs(workload)
     batch = batch or cfg.batch
     levels = levels or cfg.levels
     alpha = cfg.alpha if alpha is None else alpha
@@ -264,7 +265,7 @@ def run_single(cfg_id, steps, warmup, seed, batch=None, levels=None, alpha=None,
         dt = torch.empty((N, m, m), dtype=torch.float32, device="cuda")
         ctx.forward_model(z_true, out=dt)                    # GPU forward model
         torch.cuda.synchronize()
-        d = poisson_counts_device(dt, cfg.peak, 1000 + cfg_id) if cfg.peak else dt
+        d = poisson_counts_device(dt, cfg.peak, 1000 + cfg.seed_id) if cfg.peak else dt
         torch.cuda.synchronize()
         tl0 = time.perf_counter()
         ctx.load_intensities(d, is_sqrt=False)
@@ -466,8 +467,8 @@ def base_line(metric_value, steps, warmup, ms_per_step):
     }
 
 
-def cpu_line(args, cfg_id):
-    cfg, res = cpu_baselines(cfg_id, args.cpu_seconds, args.cpu_seconds_single, args.seed)
+def cpu_line(args, workload):
+    cfg, res = cpu_baselines(workload, args.cpu_seconds, args.cpu_seconds_single, args.seed)
     a, o = res["all_cores"], res["one_core"]
     return cfg, {
         "value": a["value"], "unit": "patterns/s", "cores": a["cores"], "kind": "oracle",
@@ -484,8 +485,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed epochs")
     ap.add_argument("--warmup", type=int, default=20, help="untimed epochs")
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
-                    help="1-3: one reconstruction; 4: 64 independent reconstructions of uneven size")
+    ap.add_argument("--workload", default="512x512", choices=["128x128", "512x512", "1024x1024", BATCHED],
+                    help="one reconstruction of the named object size, or 64 independent reconstructions "
+                         "of uneven size")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--alpha", type=float, default=None)
@@ -513,14 +515,14 @@ def main():
     # The oracle's CPU baselines run first, before anything initialises the GPU or
     # loads the HIP library: their worker processes are forked and must not inherit
     # GPU state.
-    default_run = args.config == 2 and not args.batch and not args.levels and args.alpha is None
+    default_run = args.workload == "512x512" and not args.batch and not args.levels and args.alpha is None
     cpu = {}
-    if not args.no_cpu_baseline and args.config != 4:
-        _, cpu["main"] = cpu_line(args, args.config)
+    if not args.no_cpu_baseline and args.workload != BATCHED:
+        _, cpu["main"] = cpu_line(args, args.workload)
         if default_run and not args.no_extra_workloads:
-            for cid in (1, 3):
-                c, line = cpu_line(args, cid)
-                cpu[cid] = {"value": line["value"], "cores": line["cores"], "one_core": line["one_core"]["value"],
+            for wl in ("128x128", "1024x1024"):
+                c, line = cpu_line(args, wl)
+                cpu[wl] = {"value": line["value"], "cores": line["cores"], "one_core": line["one_core"]["value"],
                             "workload": describe(c, c.batch, c.levels, c.alpha), "n": c.n}
 
     import torch
@@ -536,7 +538,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    if args.config == 4:
+    if args.workload == BATCHED:
         r = bench_batched(args.steps, args.warmup, args.seed, args.batch, args.alpha, args.tuning)
         out = base_line(r["value"], args.steps, args.warmup, r["ms_per_step"])
         out["config"] = {"workload": r["workload"], "reconstructions": len(r["specs"]), "positions": r["total_pos"],
@@ -554,10 +556,10 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    r = run_single(args.config, args.steps, args.warmup, args.seed, args.batch, args.levels, args.alpha,
+    r = run_single(args.workload, args.steps, args.warmup, args.seed, args.batch, args.levels, args.alpha,
                    args.tuning, not args.no_autotune)
     cfg, m, B = r["cfg"], r["m"], r["B"]
-    traffic = stored_traffic(args.config, m, r["rb"]) if r["batch"] == cfg.batch and r["levels"] == cfg.levels \
+    traffic = stored_traffic(args.workload, m, r["rb"]) if r["batch"] == cfg.batch and r["levels"] == cfg.levels \
         else None
     pipe_achieved = r["epoch_bytes"] * args.steps / r["wall"] / 1e9
     out = base_line(r["value"], args.steps, args.warmup, r["ms_per_step"])
@@ -588,7 +590,7 @@ def main():
             "bytes_per_epoch": r["epoch_bytes"], "achieved": pipe_achieved, "frac": pipe_achieved / HBM_PEAK_GBS,
             "bytes_per_pattern": r["epoch_bytes"] / r["N"], "covered_pixels_per_minibatch": r["cov_mean"]},
     }
-    acc_traffic = stored_traffic(args.config, m, r["rb"], "accumulate") \
+    acc_traffic = stored_traffic(args.workload, m, r["rb"], "accumulate") \
         if r["batch"] == cfg.batch and r["th"] == 8 else None
     out["accumulate_kernel"] = {
         "avg_launch_us": r["acc_full_us"], "launches": r["acc_launches"], "tiles_per_launch": r["n_tiles"],
@@ -613,17 +615,17 @@ def main():
     out["objective_after"] = r["phi"]
     out["stopping_statistic_after"] = r["stat"]
     if default_run and not args.no_extra_workloads:
-        r3 = run_single(3, 20, 5, args.seed, device_noise=True)
+        r3 = run_single("1024x1024", 20, 5, args.seed, device_noise=True)
         out["workload_1024x1024"] = single_summary(r3, 20)
         out["workload_1024x1024"]["noise"] = "Poisson counts drawn on the device (same model)"
         r4 = bench_batched(8, 2, args.seed)
         out["workload_64_reconstructions"] = batched_summary(r4, 8)
         torch.cuda.synchronize()
-    if args.race_objects > 0 and args.config == 2:
+    if args.race_objects > 0 and args.workload == "512x512":
         out["learned_race"] = learned_race(args.race_objects)
     if "main" in cpu:
         out["cpu_baseline"] = cpu["main"]
-        others = {f"workload_{v['n']}x{v['n']}": v for cid, v in cpu.items() if cid != "main"}
+        others = {f"workload_{wl}": v for wl, v in cpu.items() if wl != "main"}
         if others:
             out["cpu_baseline"]["other_workloads"] = others
     print(json.dumps(out), flush=True)

@@ -39,8 +39,8 @@ SEED_TRAIN = 250410118 + 5
 
 def geometry():
     """Probe and scan of the 512 x 512 / 64 / 40 x 40 workload (fixed seed positions)."""
-    from synth import CONFIGS, make_problem_inputs
-    cfg = CONFIGS[2]
+    from synth import WORKLOADS, make_problem_inputs
+    cfg = WORKLOADS["512x512"]
     _, Q, offs, _, _ = make_problem_inputs(cfg)
     return cfg, Q.astype(np.complex64), offs
 
@@ -230,11 +230,11 @@ def held_out_objects(count: int):
     """The 512 x 512 workload's own object followed by count - 1 objects of the training model drawn
     from a seed the training set does not use (complex64, host)."""
     import torch
-    from synth import CONFIGS, make_problem_inputs, make_objects_device
-    z0 = make_problem_inputs(CONFIGS[2])[0].astype(np.complex64)
+    from synth import WORKLOADS, make_problem_inputs, make_objects_device
+    z0 = make_problem_inputs(WORKLOADS["512x512"])[0].astype(np.complex64)
     out = [z0]
     if count > 1:
-        zs = make_objects_device(count - 1, CONFIGS[2].n, np.random.default_rng(SEED_TRAIN + 100), device="cuda")
+        zs = make_objects_device(count - 1, WORKLOADS["512x512"].n, np.random.default_rng(SEED_TRAIN + 100), device="cuda")
         out += [zs[i].cpu().numpy() for i in range(count - 1)]
         del zs
         torch.cuda.synchronize()

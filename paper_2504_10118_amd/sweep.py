@@ -119,17 +119,17 @@ def noise_label(noise) -> str:
     return "none" if kind == "none" else f"{kind} {val:g}"
 
 
-def run(config: int = 2, levels=None, alphas=(0.2, 0.5, 1.0), peaks=(None, 1e4), epochs: int = 200,
+def run(workload: str = "512x512", levels=None, alphas=(0.2, 0.5, 1.0), peaks=(None, 1e4), epochs: int = 200,
         batch: int | None = None, tol: float = 1e-4, seed: int = 7, log=print, etas=(), overlaps=(None,)) -> dict:
-    """The whole sweep on workload `config` of the synthetic suite (object, probe and scan of
-    synth.CONFIGS); intensities from the library's forward model with Poisson noise, given as
+    """The whole sweep on the named workload of the synthetic suite (object, probe and scan of
+    synth.WORKLOADS); intensities from the library's forward model with Poisson noise, given as
     peak photon counts (None = noiseless) and as the paper's eta (d = eta Poisson(d~ / eta))."""
-    from synth import CONFIGS, make_problem_inputs, poisson_counts
-    base = CONFIGS[config]
+    from synth import WORKLOADS, make_problem_inputs, poisson_counts
+    base = WORKLOADS[workload]
     noises = [("none", 0.0) if p is None else ("peak", float(p)) for p in peaks] + [("eta", float(e)) for e in etas]
     max_l = int(np.log2(base.m)) + 1
     levels = list(levels) if levels else list(range(1, max_l + 1))
-    out = {"config": config, "n": base.n, "m": base.m, "epochs": epochs, "tol": tol,
+    out = {"workload": workload, "n": base.n, "m": base.m, "epochs": epochs, "tol": tol,
            "checkpoints": checkpoints(epochs), "runs": []}
     for ov in overlaps:
         cfg = overlap_geometry(base, ov)
@@ -169,16 +169,16 @@ def run(config: int = 2, levels=None, alphas=(0.2, 0.5, 1.0), peaks=(None, 1e4),
     return out
 
 
-def run_blind(config: int = 2, levels=(1, 3), modes=("fixed", "simultaneous", "alternating"), epochs: int = 300,
+def run_blind(workload: str = "512x512", levels=(1, 3), modes=("fixed", "simultaneous", "alternating"), epochs: int = 300,
               beta: float = 0.5, alpha: float = 0.5, batch: int | None = None, seed: int = 7, log=print) -> dict:
     """Blind reconstruction from noiseless data with the probe's defocus phase unknown: the
     start probe is |Q| (the aperture without its quadratic phase).  Modes: the probe kept
     at that start ("fixed"), probe steps simultaneous with the object steps, or alternating
     (each minibatch's probe step at its updated object).  Errors after removing the complex
     scale that blind data cannot fix, at log-spaced epochs; GPU wall time of the epochs."""
-    from synth import CONFIGS, make_problem_inputs
+    from synth import WORKLOADS, make_problem_inputs
     from .magpie import PROBE_ALTERNATE, UPDATE_PROBE
-    cfg = CONFIGS[config]
+    cfg = WORKLOADS[workload]
     z_true, Q, offs, _, _ = make_problem_inputs(cfg)
     Q32 = Q.astype(np.complex64)
     Q0 = np.abs(Q).astype(np.complex64)
@@ -192,7 +192,7 @@ def run_blind(config: int = 2, levels=(1, 3), modes=("fixed", "simultaneous", "a
         d = fm.forward_model(z32)
     flags = {"fixed": 0, "simultaneous": UPDATE_PROBE, "alternating": UPDATE_PROBE | PROBE_ALTERNATE}
     cps = set(checkpoints(epochs))
-    out = {"config": config, "epochs": epochs, "beta": beta, "alpha": alpha, "batch": B,
+    out = {"workload": workload, "epochs": epochs, "beta": beta, "alpha": alpha, "batch": B,
            "probe_start": "|Q| (quadratic phase unknown)", "runs": []}
     for L in levels:
         for mode in modes:
@@ -219,7 +219,7 @@ def run_blind(config: int = 2, levels=(1, 3), modes=("fixed", "simultaneous", "a
     return out
 
 
-def run_batches(config: int = 2, batches=(256, 400, 800, 1600), levels: int | None = None, alpha: float = 0.5,
+def run_batches(workload: str = "512x512", batches=(256, 400, 800, 1600), levels: int | None = None, alpha: float = 0.5,
                 target: float = 1e-3, max_epochs: int = 20000, noisy_epochs: int = 400, check: int = 10,
                 seed: int = 7, log=print) -> dict:
     """Wall time to error against the minibatch size B (flat start, the workload's levels):
@@ -228,8 +228,8 @@ def run_batches(config: int = 2, batches=(256, 400, 800, 1600), levels: int | No
     for `noisy_epochs` epochs, where the error passes through a minimum (the noise floor)
     before the iteration fits the noise: the epoch and time at which the error first comes
     within 5 % of that minimum, and at which Phi first comes within 1e-3 of its last value."""
-    from synth import CONFIGS, make_problem_inputs, poisson_counts
-    cfg = CONFIGS[config]
+    from synth import WORKLOADS, make_problem_inputs, poisson_counts
+    cfg = WORKLOADS[workload]
     L = levels or cfg.levels
     z_true, Q, offs, _, _ = make_problem_inputs(cfg)
     Q32 = Q.astype(np.complex64)
@@ -243,7 +243,7 @@ def run_batches(config: int = 2, batches=(256, 400, 800, 1600), levels: int | No
     data = {"noiseless": dtilde.astype(np.float32),
             f"{cfg.peak:g} photons": poisson_counts(dtilde, cfg.peak, np.random.default_rng(seed + 1000))
             .astype(np.float32)}
-    out = {"config": config, "levels": L, "alpha": alpha, "target": target, "check": check, "runs": []}
+    out = {"workload": workload, "levels": L, "alpha": alpha, "target": target, "check": check, "runs": []}
     for label, d in data.items():
         noiseless = label == "noiseless"
         for B in batches:
@@ -311,7 +311,7 @@ def table(res: dict, at=None) -> str:
 
 def main():
     ap = argparse.ArgumentParser(description="Sweep the number of multigrid levels on a synthetic workload.")
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--workload", default="512x512", choices=["128x128", "512x512", "1024x1024"])
     ap.add_argument("--levels", type=str, default="", help="comma list (default 1 .. log2(m) + 1)")
     ap.add_argument("--alphas", type=str, default="0.2,0.5,1.0")
     ap.add_argument("--peaks", type=str, default="none,1e4", help="comma list; 'none' = noiseless")
@@ -337,7 +337,7 @@ def main():
     if a.batches:
         bs = [int(x) for x in a.batches.split(",") if x]
         lv = [int(x) for x in a.levels.split(",") if x]
-        res = run_batches(a.config, bs, lv[0] if lv else None, float(a.alphas.split(",")[0]), a.target,
+        res = run_batches(a.workload, bs, lv[0] if lv else None, float(a.alphas.split(",")[0]), a.target,
                           a.max_epochs, a.epochs, seed=a.seed)
         if a.out:
             os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
@@ -346,7 +346,7 @@ def main():
         return
     if a.blind:
         lv = [int(x) for x in a.levels.split(",") if x] or [1, 3]
-        res = run_blind(a.config, lv, epochs=a.epochs, beta=a.beta, alpha=float(a.alphas.split(",")[0]),
+        res = run_blind(a.workload, lv, epochs=a.epochs, beta=a.beta, alpha=float(a.alphas.split(",")[0]),
                         batch=a.batch or None, seed=a.seed)
         print("| L | mode | " + " | ".join(f"obj/probe err @{r[0]}" for r in res["runs"][0]["trace"]) + " |")
         for r in res["runs"]:
@@ -362,7 +362,7 @@ def main():
     peaks = [None if x.strip().lower() == "none" else float(x) for x in a.peaks.split(",") if x]
     etas = [float(x) for x in a.etas.split(",") if x]
     overlaps = [float(x) for x in a.overlaps.split(",") if x] or [None]
-    res = run(a.config, levels, alphas, peaks, a.epochs, a.batch or None, a.tol, a.seed, etas=etas,
+    res = run(a.workload, levels, alphas, peaks, a.epochs, a.batch or None, a.tol, a.seed, etas=etas,
               overlaps=overlaps)
     print(table(res), flush=True)
     if a.out:

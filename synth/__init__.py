@@ -15,9 +15,9 @@ paragraph, re-parameterised by peak photon count).
 """
 
 from .generators import (  # noqa: F401
-    CONFIGS,
+    WORKLOADS,
     ScanConfig,
-    config_rngs,
+    workload_rngs,
     make_object,
     make_probe,
     make_scan,

@@ -19,9 +19,11 @@ SEED_BASE = 250410118
 
 @dataclasses.dataclass(frozen=True)
 class ScanConfig:
-    """One ptychography workload: object side n, probe side m, P x P raster."""
+    """One ptychography workload: object side n, probe side m, P x P raster; named by its
+    object side, and seeded by seed_id (an offset of the seed sequence)."""
 
-    cfg_id: int
+    name: str
+    seed_id: int
     n: int                 # object side (pixels)
     m: int                 # probe / patch side (pixels)
     P: int                 # raster is P x P positions
@@ -39,19 +41,19 @@ class ScanConfig:
 
 
 # Workloads (sizes of the paper's Section 5 setup scaled around it).
-CONFIGS = {
-    1: ScanConfig(1, n=128, m=32, P=8, step=12, levels=2, peak=None, batch=8,
-                  rectangles=False, epochs=20),
-    2: ScanConfig(2, n=512, m=64, P=40, step=10, levels=3, peak=1e4, batch=256,
-                  rectangles=True, epochs=50),
-    3: ScanConfig(3, n=1024, m=128, P=80, step=10, levels=4, peak=1e5, batch=256,
-                  rectangles=True, epochs=20),
+WORKLOADS = {
+    "128x128": ScanConfig("128x128", 1, n=128, m=32, P=8, step=12, levels=2, peak=None, batch=8,
+                          rectangles=False, epochs=20),
+    "512x512": ScanConfig("512x512", 2, n=512, m=64, P=40, step=10, levels=3, peak=1e4, batch=256,
+                          rectangles=True, epochs=50),
+    "1024x1024": ScanConfig("1024x1024", 3, n=1024, m=128, P=80, step=10, levels=4, peak=1e5, batch=256,
+                            rectangles=True, epochs=20),
 }
 
 
-def config_rngs(cfg_id: int):
+def workload_rngs(seed_id: int):
     """Independent generators: object, scan jitter, noise, permutations, learned-start set."""
-    ss = np.random.SeedSequence(SEED_BASE + int(cfg_id))
+    ss = np.random.SeedSequence(SEED_BASE + int(seed_id))
     return [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(5)]
 
 
@@ -145,7 +147,7 @@ def make_problem_inputs(cfg: ScanConfig):
     Returns (z_true complex128 [n,n], probe complex128 [m,m], offsets int32 [N,2],
     noise_rng, perm_rng).  Intensities are not formed here.
     """
-    r_obj, r_scan, r_noise, r_perm, _ = config_rngs(cfg.cfg_id)
+    r_obj, r_scan, r_noise, r_perm, _ = workload_rngs(cfg.seed_id)
     z = make_object(cfg.n, r_obj, cfg.rectangles)
     q = make_probe(cfg.m)
     offs = make_scan(cfg.n, cfg.m, cfg.P, cfg.step, r_scan)
@@ -171,7 +173,7 @@ class BatchedRecon:
         return self.P * self.P
 
 
-def batched_workload(count: int = 64, cfg_id: int = 4):
+def batched_workload(count: int = 64, seed_id: int = 4):
     """The batched workload: `count` independent reconstructions of uneven size.
 
     Per reconstruction: n ~ U{256, 384, 512, 768, 1024}, m ~ U{64, 128},
@@ -179,7 +181,7 @@ def batched_workload(count: int = 64, cfg_id: int = 4):
     peak photons log-uniform in [1e4, 1e5], L = 3 (m = 64) or 4 (m = 128),
     minibatch min(256, P*P).
     """
-    rng = config_rngs(cfg_id)[0]
+    rng = workload_rngs(seed_id)[0]
     out = []
     for i in range(count):
         n = int(rng.choice([256, 384, 512, 768, 1024]))

@@ -26,19 +26,19 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import CONFIGS, make_problem_inputs, poisson_counts
+from synth import WORKLOADS, make_problem_inputs, poisson_counts
 
 pytestmark = pytest.mark.gpu
 
 
-def _problem(cfg_id):
-    cfg = CONFIGS[cfg_id]
+def _problem(name):
+    cfg = WORKLOADS[name]
     z, Q, offs, r_noise, _ = make_problem_inputs(cfg)
     Q32 = Q.astype(np.complex64)
     d = oracle.forward_model(z, Q32.astype(np.complex128), offs)
     sd32 = np.sqrt(poisson_counts(d, cfg.peak, r_noise)).astype(np.float32)
     ill = oracle.illumination((cfg.n, cfg.n), Q32.astype(np.complex128), offs)
-    order = oracle.library_permutation(31 + cfg_id, 0, cfg.n_pos)
+    order = oracle.library_permutation(31 + cfg.seed_id, 0, cfg.n_pos)
     return cfg, Q32, offs, sd32, order, ill >= 0.1 * ill.max()
 
 
@@ -98,7 +98,7 @@ def test_full_size_flat_start_step_within_fp32_floor(levels):
     grid, and the workload's four) must stay within 1.5x the floor of an independent
     single-precision computation of the one-grid step (the rounding sits in the
     transforms, which every depth shares)."""
-    cfg, Q32, offs, sd32, order, mask = _problem(3)
+    cfg, Q32, offs, sd32, order, mask = _problem("1024x1024")
     chunk = order[:cfg.batch]
     Q = Q32.astype(np.complex128)
     u = oracle.u_rpie(Q, cfg.alpha)
@@ -122,12 +122,12 @@ def test_full_size_flat_start_step_within_fp32_floor(levels):
     assert relx <= max(1e-5, 2.0 * floor_x)
 
 
-@pytest.mark.parametrize("cfg_id,first,steps", [(2, 0, 3), (3, 1, 3)])
-def test_full_size_steps_match_oracle(cfg_id, first, steps):
+@pytest.mark.parametrize("name,first,steps", [("512x512", 0, 3), ("1024x1024", 1, 3)])
+def test_full_size_steps_match_oracle(name, first, steps):
     """Steps t = first .. steps-1 of the epoch, each from the oracle's object after t steps
     (the 1024 x 1024 case starts after its flat-start step, which the FP32 floor test covers),
     one minibatch at a time in the context of all positions."""
-    cfg, Q32, offs, sd32, order, mask = _problem(cfg_id)
+    cfg, Q32, offs, sd32, order, mask = _problem(name)
     Q = Q32.astype(np.complex128)
     u = oracle.u_rpie(Q, cfg.alpha)
     sd = sd32.astype(np.float64)
@@ -156,7 +156,7 @@ def test_full_size_steps_match_oracle(cfg_id, first, steps):
 
 
 def test_full_size_epoch_and_objective():
-    cfg, Q32, offs, sd32, order, mask = _problem(2)
+    cfg, Q32, offs, sd32, order, mask = _problem("512x512")
     g = _gpu(cfg, Q32, offs, sd32, np.ones((cfg.n, cfg.n)))
     g.run_epochs(1, cfg.batch, order=order[None, :])
     zg = g.get_object().astype(np.complex128)
@@ -180,7 +180,7 @@ def test_full_size_objective_after_50_epochs():
     """512 x 512, 64 x 64 probe, 3 levels, minibatch 256, 1e4 photons: 50 epochs from the
     flat start with the same explicit permutations on both sides; the objective (eq. 2.1,
     FP64 reduction) of the GPU's object and of the oracle's object agree to 1e-4."""
-    cfg, Q32, offs, sd32, _, mask = _problem(2)
+    cfg, Q32, offs, sd32, _, mask = _problem("512x512")
     epochs = 50
     orders = np.stack([oracle.library_permutation(41, e, cfg.n_pos) for e in range(epochs)])
     g = _gpu(cfg, Q32, offs, sd32, np.ones((cfg.n, cfg.n)))

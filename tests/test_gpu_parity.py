@@ -157,8 +157,8 @@ def test_several_epochs_128_workload():
     themselves drift apart slowly (FP32 rounding amplified by the
     iteration); that distance is printed, not gated.
     """
-    from synth import CONFIGS, make_problem_inputs
-    cfg = CONFIGS[1]
+    from synth import WORKLOADS, make_problem_inputs
+    cfg = WORKLOADS["128x128"]
     z_true, Q, offs, _, r_perm = make_problem_inputs(cfg)
     Q32 = Q.astype(np.complex64)
     zt32 = z_true.astype(np.complex64)

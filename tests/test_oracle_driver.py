@@ -67,8 +67,8 @@ def test_truth_is_fixed_point(rng, L, B):
 
 
 def _cfg1_problem():
-    from synth import CONFIGS, make_problem_inputs
-    cfg = CONFIGS[1]
+    from synth import WORKLOADS, make_problem_inputs
+    cfg = WORKLOADS["128x128"]
     z_true, Q, offs, _, r_perm = make_problem_inputs(cfg)
     zt = z_true.astype(np.complex64).astype(np.complex128)
     Qf = Q.astype(np.complex64).astype(np.complex128)

@@ -15,8 +15,8 @@ def test_checkpoints_log_spaced():
 def test_overlap_geometry_steps():
     """Overlap ratio r of the probe's disc (diameter 20 m / 32) gives step (1 - r) * 2R over
     the workload's own span; None keeps the workload."""
-    from synth import CONFIGS
-    cfg = CONFIGS[2]                      # m = 64: disc diameter 40 px, span 39 * 10 px
+    from synth import WORKLOADS
+    cfg = WORKLOADS["512x512"]                      # m = 64: disc diameter 40 px, span 39 * 10 px
     assert overlap_geometry(cfg, None) is cfg
     for r, step, P in ((0.25, 30, 14), (0.5, 20, 20), (0.75, 10, 40)):
         g = overlap_geometry(cfg, r)
@@ -55,8 +55,8 @@ def test_object_errors_global_phase_and_magnitude():
 def test_short_sweep_runs_every_level():
     from paper_2504_10118_amd import Magpie
     from paper_2504_10118_amd.sweep import illumination_mask, run, run_one
-    from synth import CONFIGS, make_problem_inputs
-    res = run(config=1, alphas=(0.5,), peaks=(None,), epochs=20, log=lambda s: print(s, flush=True))
+    from synth import WORKLOADS, make_problem_inputs
+    res = run(workload="128x128", alphas=(0.5,), peaks=(None,), epochs=20, log=lambda s: print(s, flush=True))
     assert [r["levels"] for r in res["runs"]] == [1, 2, 3, 4, 5, 6]
     for r in res["runs"]:
         assert r["finite"] and len(r["phi"]) == 21 and len(r["stat"]) == 21
@@ -64,7 +64,7 @@ def test_short_sweep_runs_every_level():
         assert [e for e, _, _ in r["errors"]] == [0, 1, 2, 3, 5, 10, 20]
         assert r["errors"][-1][1] < r["errors"][0][1]
     # the sweep's L = 2 trajectory is the context's own: same permutations, same kernels
-    cfg = CONFIGS[1]
+    cfg = WORKLOADS["128x128"]
     z_true, Q, offs, _, _ = make_problem_inputs(cfg)
     with Magpie(cfg.n, cfg.n, cfg.m, 1, 0.5) as fm:
         fm.set_probe(Q.astype(np.complex64))
@@ -82,7 +82,7 @@ def test_short_sweep_runs_every_level():
 @pytest.mark.gpu
 def test_sweep_noise_and_overlap_paths():
     from paper_2504_10118_amd.sweep import run
-    res = run(config=1, levels=[1, 2], alphas=(0.5,), peaks=(), etas=(0.05,), overlaps=(None, 0.25), epochs=5,
+    res = run(workload="128x128", levels=[1, 2], alphas=(0.5,), peaks=(), etas=(0.05,), overlaps=(None, 0.25), epochs=5,
               log=lambda s: print(s, flush=True))
     assert [(r["overlap"], r["levels"]) for r in res["runs"]] == [(None, 1), (None, 2), (0.25, 1), (0.25, 2)]
     for r in res["runs"]:
@@ -93,10 +93,10 @@ def test_sweep_noise_and_overlap_paths():
 @pytest.mark.gpu
 def test_blind_runs():
     from paper_2504_10118_amd.sweep import run_blind
-    from synth import CONFIGS, make_problem_inputs
-    res = run_blind(config=1, levels=(2,), epochs=20, log=lambda s: print(s, flush=True))
+    from synth import WORKLOADS, make_problem_inputs
+    res = run_blind(workload="128x128", levels=(2,), epochs=20, log=lambda s: print(s, flush=True))
     assert [r["mode"] for r in res["runs"]] == ["fixed", "simultaneous", "alternating"]
-    Q = make_problem_inputs(CONFIGS[1])[1]
+    Q = make_problem_inputs(WORKLOADS["128x128"])[1]
     start = scaled_error(np.abs(Q), Q)
     for r in res["runs"]:
         assert all(np.isfinite(v) for row in r["trace"] for v in row)

@@ -2,7 +2,7 @@
 
 import numpy as np
 
-from synth import CONFIGS, make_object, make_probe, make_scan, poisson_counts, epoch_orders, config_rngs
+from synth import WORKLOADS, make_object, make_probe, make_scan, poisson_counts, epoch_orders, workload_rngs
 
 
 def test_probe_model():
@@ -16,7 +16,7 @@ def test_probe_model():
 
 
 def test_object_model():
-    r = config_rngs(2)[0]
+    r = workload_rngs(2)[0]
     z = make_object(64, r, rectangles=True)
     amp = np.abs(z)
     assert amp.min() >= 0.8 and amp.max() <= 1.0
@@ -25,8 +25,8 @@ def test_object_model():
 
 
 def test_scan_origins_and_bounds():
-    for cid, origin in ((1, 6), (2, 29), (3, 53)):
-        c = CONFIGS[cid]
+    for name, origin in (("128x128", 6), ("512x512", 29), ("1024x1024", 53)):
+        c = WORKLOADS[name]
         offs = make_scan(c.n, c.m, c.P, c.step, np.random.default_rng(0), jitter=0)
         assert offs[0, 0] == origin and offs[0, 1] == origin
         j = make_scan(c.n, c.m, c.P, c.step, np.random.default_rng(1))
