@@ -76,7 +76,11 @@ hipEvent_t take_event(magpie_ctx* c) {
 int timed_slot(magpie_ctx* c, int kind, int count) {
   if (!c->timing) return -1;
   magpie_ctx::Timed t{take_event(c), take_event(c), kind, count};
-  if (!t.a || !t.b) return -1;
+  if (!t.a || !t.b) {   // untimed launch; an event already taken goes back to the pool
+    if (t.a) c->ev_pool.push_back(t.a);
+    if (t.b) c->ev_pool.push_back(t.b);
+    return -1;
+  }
   c->timed.push_back(t);
   return (int)c->timed.size() - 1;
 }
@@ -1017,8 +1021,24 @@ int magpie_forward_model(magpie_ctx* c, const void* z, int z_on_device, float* d
   return MAGPIE_OK;
 }
 
+// Returns the recorded launches' events to the pool and forgets the records.
+static void recycle_timed(magpie_ctx* c) {
+  for (auto& t : c->timed) {
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->timed.clear();
+}
+
 int magpie_set_timing(magpie_ctx* c, int enable) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (enable) {
+    // records start anew; events still pending on the stream are waited for first
+    int rc = set_dev(c);
+    if (rc) return rc;
+    MG_HIP(hipStreamSynchronize(c->stream));
+    recycle_timed(c);
+  }
   c->timing = enable != 0;
   return MAGPIE_OK;
 }
@@ -1034,14 +1054,12 @@ int magpie_get_timing(magpie_ctx* c, double* step_ms, double* accum_ms, int64_t*
   int64_t nl[2] = {0, 0}, pos = 0;
   for (auto& t : c->timed) {
     float f = 0.0f;
-    MG_HIP(hipEventElapsedTime(&f, t.a, t.b));
+    MG_HIP(hipEventElapsedTime(&f, t.a, t.b));   // on failure the records stay as they are
     ms[t.kind] += f;
     nl[t.kind] += 1;
     if (t.kind == 0) pos += t.count;
-    c->ev_pool.push_back(t.a);
-    c->ev_pool.push_back(t.b);
   }
-  c->timed.clear();
+  recycle_timed(c);
   *step_ms = ms[0];
   *accum_ms = ms[1];
   *step_launches = nl[0];
