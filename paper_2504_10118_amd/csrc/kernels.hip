@@ -465,7 +465,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // and the V-cycle output; M = 128 (1024 threads at the 128-register cap)
   // re-reads its table entries there instead.
   constexpr bool KEEP = keeps_table(M);
-  constexpr bool ROWS = true;             // row-wise gathers through the LDS tile
   constexpr bool PREQ = (RA <= 8);        // probe table entries in flight with the gather
   // MODE_STEP_PR is the object step with the eq. (3.2) phase store
   constexpr bool STEPM = (MODE == MODE_STEP) || (MODE == MODE_STEP_PR);
@@ -520,7 +519,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   // Gather: the patch is read as whole rows (each wave reads contiguous row
   // segments) into the LDS tile, and after one barrier every thread takes its
   // column values (rows y = RB*n1 + g of column col) from it; the tile is then
-  // reused by the FFT.
+  // reused by the FFT.  (Each wave loading its own columns directly, with no
+  // barrier, measured slower at 256 and at 1600 positions per launch.)
   // Row gather: load j of thread tid reads row tid / M + j * TPB / M, column
   // tid % M: one per-lane offset, and a uniform per-load row step.
   constexpr int GR = TPB / M;   // rows per load of the workgroup
@@ -531,62 +531,39 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
     for (int j = 0; j < RA; ++j) dst[j * GR * P] = bload2(zr, gvo, j * gso);
   };
-  if constexpr (ROWS) {
-    row_gather();
-    // The probe table (needed with the patch), the constants (parked in LDS
-    // before the first transpose) and sqrt(d) (needed at the modulus) are issued
-    // after the patch, in the order they are needed: loads return in issue
-    // order, so issued first they had held up the patch the barrier below waits
-    // for (512 x 512 object, 64 x 64 probe: epoch -2 % for sqrt(d) and the constants, -1.3 % for the
-    // table, -0.6 % for the constants ahead of sqrt(d)).
-    if constexpr (PREQ) {
+  row_gather();
+  // The probe table (needed with the patch), the constants (parked in LDS
+  // before the first transpose) and sqrt(d) (needed at the modulus) are issued
+  // after the patch, in the order they are needed: loads return in issue
+  // order, so issued first they had held up the patch the barrier below waits
+  // for (512 x 512 object, 64 x 64 probe: epoch -2 % for sqrt(d) and the constants, -1.3 % for the
+  // table, -0.6 % for the constants ahead of sqrt(d)).
+  if constexpr (PREQ) {
 #pragma unroll
-      for (int n1 = 0; n1 < RA; ++n1) qtv[n1] = qt[n1 * TPB];
+    for (int n1 = 0; n1 < RA; ++n1) qtv[n1] = qt[n1 * TPB];
+  }
+  load_cst();
+  if constexpr (!LAZY) load_sd();
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < RA; ++n1) {
+    float2 qv;
+    float uv = 0.0f;
+    if constexpr (KEEP) {
+      const float4 t = PREQ ? qtv[n1] : qt[n1 * TPB];
+      qv = make_float2(t.x, t.y);
+      uv = t.z;
+    } else {
+      qv = qt2[n1 * TPB];
     }
-    load_cst();
-    if constexpr (!LAZY) load_sd();
-    __syncthreads();
-#pragma unroll
-    for (int n1 = 0; n1 < RA; ++n1) {
-      float2 qv;
-      float uv = 0.0f;
-      if constexpr (KEEP) {
-        const float4 t = PREQ ? qtv[n1] : qt[n1 * TPB];
-        qv = make_float2(t.x, t.y);
-        uv = t.z;
-      } else {
-        qv = qt2[n1 * TPB];
-      }
-      const float2 zz = T[(RB * n1 + g) * P + col];
-      v[n1] = cmul(qv, zz);
-      if constexpr (KEEP) {
-        qk[n1] = qv;
-        u0k[n1] = uv;
-      }
-    }
-    wave_sync();   // the column pass below reuses this wave's own column slice of the tile
-  } else {
-    load_cst();
-    if constexpr (!LAZY) load_sd();
-#pragma unroll
-    for (int n1 = 0; n1 < RA; ++n1) {
-      float2 qv;
-      float uv = 0.0f;
-      if constexpr (KEEP) {
-        const float4 t = qt[n1 * TPB];
-        qv = make_float2(t.x, t.y);
-        uv = t.z;
-      } else {
-        qv = qt2[n1 * TPB];
-      }
-      const float2 zz = bload2(zr, zvo, n1 * zso);
-      v[n1] = cmul(qv, zz);
-      if constexpr (KEEP) {
-        qk[n1] = qv;
-        u0k[n1] = uv;
-      }
+    const float2 zz = T[(RB * n1 + g) * P + col];
+    v[n1] = cmul(qv, zz);
+    if constexpr (KEEP) {
+      qk[n1] = qv;
+      u0k[n1] = uv;
     }
   }
+  wave_sync();   // the column pass below reuses this wave's own column slice of the tile
 
   // ---- forward, columns: stage A (radix RA over n1), twiddle, exchange, stage B
   dft<RA, 1>(v);
