@@ -1470,6 +1470,11 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
   }
   if (!rc && e == hipSuccess) e = hipStreamSynchronize(st);
   if (!rc && e != hipSuccess) rc = fail(MAGPIE_ERR_HIP, std::string("multi-context run: ") + hipGetErrorString(e));
+  if (rc) {
+    // a failed run returns only once nothing it queued still runs on the contexts' buffers
+    for (auto& p : parts)
+      if (p.stream) (void)hipStreamSynchronize(p.stream);
+  }
   for (int i = 1; i < count && !rc; ++i) rc = join(st, ctxs[i]->stream);
   cleanup();
   if (rc) return rc;
