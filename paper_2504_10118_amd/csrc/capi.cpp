@@ -56,7 +56,8 @@ int free_positions(magpie_ctx* c) {
 
 int rebuild_levels(magpie_ctx* c) {
   MG_HIP(mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->w0f, c->u0f,
-                                    c->qf, c->lvl, c->lvl_a_off, c->scr_q, c->scr_u, c->rb, c->qtab, c->stream));
+                                    c->qf, c->lvl, c->lvl_a_off, c->scr_q, c->scr_u, c->rb, c->qtab, c->qspec,
+                                    c->spec_tmp, c->stream));
   return MAGPIE_OK;
 }
 
@@ -229,6 +230,8 @@ int magpie_create(magpie_ctx** out, int n_rows, int n_cols, int m, int n_levels,
   rc = dev_alloc(&c->z, (size_t)n_rows * n_cols);
   if (!rc) rc = dev_alloc(&c->qf, mm);
   if (!rc) rc = dev_alloc(&c->qtab, mm);
+  if (!rc) rc = dev_alloc(&c->qspec, mm);
+  if (!rc) rc = dev_alloc(&c->spec_tmp, mm + (size_t)m);   // row transforms, then row sums of |Q|
   if (!rc) rc = dev_alloc(&c->q64, mm);
   if (!rc) rc = dev_alloc(&c->u0, mm);
   if (!rc) rc = dev_alloc(&c->w0, mm);
@@ -273,6 +276,8 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->z);
   dev_free(c->qf);
   dev_free(c->qtab);
+  dev_free(c->qspec);
+  dev_free(c->spec_tmp);
   dev_free(c->q64);
   dev_free(c->u0);
   dev_free(c->w0);
@@ -656,6 +661,7 @@ int mgrt::launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoc
   sa.n_cols = c->nc;
   sa.q = c->qf;
   sa.qtab = c->qtab;
+  sa.qspec = c->qspec;
   sa.sqrtd = c->sqrtd;
   sa.offs = c->offs;
   sa.stage = buf.stage;
@@ -701,7 +707,7 @@ int mgrt::launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoc
     if (e == hipSuccess)
       e = mg::launch_level_constants(c->m, c->L, c->alpha, c->u_given ? 1 : 0, c->q64, c->u0, c->w0, c->w0f,
                                      c->u0f, c->qf, c->lvl, c->lvl_a_off, c->scr_q, c->scr_u, c->rb, c->qtab,
-                                     c->stream);
+                                     c->qspec, c->spec_tmp, c->stream);
     return e;
   };
   mg::AccumArgs aa{};
@@ -873,6 +879,7 @@ int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {
   sa.n_cols = c->nc;
   sa.q = c->qf;
   sa.qtab = c->qtab;
+  sa.qspec = c->qspec;
   sa.sqrtd = c->sqrtd;
   sa.offs = c->offs;
   sa.perm = nullptr;
@@ -1007,6 +1014,7 @@ int magpie_forward_model(magpie_ctx* c, const void* z, int z_on_device, float* d
   sa.n_cols = c->nc;
   sa.q = c->qf;
   sa.qtab = c->qtab;
+  sa.qspec = c->qspec;
   sa.offs = c->offs;
   sa.perm = nullptr;
   sa.count = c->n_pos;
@@ -1362,6 +1370,7 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
           a.n_cols = c->nc;
           a.q = c->qf;
           a.qtab = c->qtab;
+          a.qspec = c->qspec;
           a.sqrtd = c->sqrtd;
           a.offs = c->offs;
           a.stage = c->stage;

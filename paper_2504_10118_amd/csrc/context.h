@@ -96,6 +96,8 @@ struct magpie_ctx {
   float2* z = nullptr;
   float2* qf = nullptr;
   float4* qtab = nullptr;   // (Re Q, Im Q, u0, 0) in the current plan's thread order
+  float2* qspec = nullptr;  // F(Q) (computed in FP64) in the current plan's spectral thread order
+  double2* spec_tmp = nullptr;   // m*m + m scratch: its row transforms, then the rows' sums of |Q|
   double2* q64 = nullptr;
   double* u0 = nullptr;
   double* w0 = nullptr;

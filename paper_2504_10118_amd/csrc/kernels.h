@@ -44,6 +44,8 @@ struct StepArgs {
   const float* u0f;       // fine-grid u [m][m]
   const float4* qtab;     // probe table in the plan's thread order [n1][tid], pixel (RB*n1 + g, col): m <= 64
                           // (Re Q, Im Q, u0, 0) per entry; m = 128 m*m float2 Q, then m*m float u0
+  const float2* qspec;    // F(Q) of the FP32 probe, computed in FP64, in the order the forward transform
+                          // leaves the spectrum [j][tid] (thread (ky, g), j = c*RB + k2: kx = g*CB + c + RA*k2)
   const double* lvl;      // coarse-level constants (V, rho, r per level), then A_l
   int lvl_a_off;          // offset in lvl of the in-wave V-cycle block (cst_count(m, L) doubles)
   int levels;             // number of grids L
@@ -109,10 +111,12 @@ hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, const int* pr
                              hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, const int* prefix, int n_ctx, int total,
                                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Level constants, the plan's probe table and the probe spectrum (qspec; spec_tmp:
+// m*m + m double2 of scratch).
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given,
                                   const double2* q64, double* u0, double* w0, float* w0f, float* u0f,
                                   float2* qf, double* lvl, int lvl_a_off, double2* scr_q, double* scr_u, int rb,
-                                  float4* qtab, hipStream_t s);
+                                  float4* qtab, float2* qspec, double2* spec_tmp, hipStream_t s);
 hipError_t launch_permute_sqrt(int m, int rb, int n_pos, const float* src, int is_sqrt, float* dst,
                                int* bad_flag, hipStream_t s);
 hipError_t launch_unpermute_sqrt(int m, int rb, int n_pos, const float* src, float* dst, hipStream_t s);

@@ -155,6 +155,7 @@ __device__ __forceinline__ StepArgs load_step_args(const StepArgs* p) {
   a.stage = d->stage;
   a.u0f = d->u0f;
   a.qtab = d->qtab;
+  a.qspec = d->qspec;
   a.lvl = d->lvl;
   a.lvl_a_off = d->lvl_a_off;
   a.levels = d->levels;
@@ -545,6 +546,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   load_cst();
   if constexpr (!LAZY) load_sd();
   __syncthreads();
+  // reference value of the window: its centre pixel (see the spectrum term after
+  // the forward transform, which reads it back from s_zc past the next barrier
+  // rather than holding it in registers through the column pass)
+  __shared__ float2 s_zc;
+  const float2 zc = T[(M / 2) * P + M / 2];
+  if (tid == 0) s_zc = zc;
 #pragma unroll
   for (int n1 = 0; n1 < RA; ++n1) {
     float2 qv;
@@ -557,7 +564,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       qv = qt2[n1 * TPB];
     }
     const float2 zz = T[(RB * n1 + g) * P + col];
-    v[n1] = cmul(qv, zz);
+    v[n1] = cmul(qv, make_float2(zz.x - zc.x, zz.y - zc.y));   // Q (z_k - z_c); z_c F(Q) is added after the transform
     if constexpr (KEEP) {
       qk[n1] = qv;
       u0k[n1] = uv;
@@ -607,9 +614,29 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   for (int c = 0; c < CB; ++c)
 #pragma unroll
     for (int n2 = 0; n2 < RB; ++n2) v[c * RB + n2] = *rx(g * CB + c, n2);
+  // v[c*RB + k2] = F(Q (z_k - z_c))[ky = col][kx = g*CB + c + RA*k2]; adding z_c F(Q) gives
+  // Psi = F(Q z_k) (exact for any scalar z_c).  A window that is nearly constant
+  // (the flat start above all) has exit waves close to a multiple of Q, whose far
+  // field spans more than FP32 resolves in one transform (dark pixels would take
+  // their phase from rounding); with the probe's spectrum computed once in FP64 the
+  // transform only carries the departure from the window's centre value, whose
+  // size is that of the variation of z_k (never that of 1 - z_k: tiny objects
+  // stay exact).  The spectrum is added group by group after each RB-point DFT,
+  // so that only RB of its values are live at a time.
+  // Buffer loads: one per-lane offset and a constant per-load offset (a plain
+  // pointer per load costs an address pair each and spilled at 128 x 128).
+  const float2 zcs = s_zc;
+  const rsrc_t qsr = make_rsrc(a.qspec, (unsigned)(M * M * sizeof(float2)));
 #pragma unroll
-  for (int c = 0; c < CB; ++c) dft<RB, 1>(&v[c * RB]);
-  // v[c*RB + k2] = Psi[ky = col][kx = g*CB + c + RA*k2]
+  for (int c = 0; c < CB; ++c) {
+    dft<RB, 1>(&v[c * RB]);
+    if constexpr (LAZY) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k2 = 0; k2 < RB; ++k2) {
+      const float2 r = cmul(zcs, bload2(qsr, tid * (int)sizeof(float2), (c * RB + k2) * TPB * (int)sizeof(float2)));
+      v[c * RB + k2] = make_float2(v[c * RB + k2].x + r.x, v[c * RB + k2].y + r.y);
+    }
+  }
 
   if constexpr (MODE == MODE_FORWARD) {
     float* dp = a.d_out + (size_t)k * M * M + (size_t)col * M;
@@ -1336,17 +1363,69 @@ __global__ void qtab_kernel(const float2* qf, const float* u0f, float4* qtab) {
   }
 }
 
+// Probe spectrum F(Q) of the FP32 probe in FP64 (a direct DFT along each axis,
+// exact twiddles from sincospi of the reduced exponent), rounded to FP32 once.
+// Values within the DFT's own rounding bound, 2 m eps sum |Q| (doubled here), are
+// set to exactly zero: a symmetric probe's spectrum vanishes exactly on whole
+// lines, where the modulus replacement takes theta(0), and the sums leave there
+// only rounding (below 1e-16 sum |Q|, against 1e-8 sum |Q| for the smallest value
+// that does not vanish, with the 128 x 128 test probe).
+// Rows: one workgroup per row y, thread kx: A[y][kx] = sum_x Q[y][x] W^(kx x);
+// the row's sum |Q[y][x]| goes to tmp[m * m + y].x.
+__global__ void probe_spectrum_rows_kernel(int m, const float2* __restrict__ qf, double2* __restrict__ tmp) {
+  const int y = blockIdx.x, kx = threadIdx.x;
+  double re = 0.0, im = 0.0, l1 = 0.0;
+  for (int x = 0; x < m; ++x) {
+    double sn, cs;
+    sincospi(-2.0 * (double)((kx * x) % m) / (double)m, &sn, &cs);
+    const float2 q = qf[y * m + x];
+    re += (double)q.x * cs - (double)q.y * sn;
+    im += (double)q.x * sn + (double)q.y * cs;
+    l1 += hypot((double)q.x, (double)q.y);
+  }
+  tmp[y * m + kx] = make_double2(re, im);
+  if (kx == 0) tmp[m * m + y] = make_double2(l1, 0.0);
+}
+// Columns, written in the plan's spectral thread order: entry e = j * TPB + tid
+// holds F[ky][kx] with ky = tid / RB, kx = (tid % RB) * CB + j / RB + RA * (j % RB).
+template <int M, int RB>
+__global__ void probe_spectrum_cols_kernel(const double2* __restrict__ tmp, float2* __restrict__ qspec) {
+  constexpr int TPB = M * RB, RA = M / RB, CB = RA / RB;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int j = e / TPB, tid = e - j * TPB;
+  const int ky = tid / RB, kx = (tid % RB) * CB + j / RB + RA * (j % RB);
+  double re = 0.0, im = 0.0, l1 = 0.0;
+  for (int y = 0; y < M; ++y) {
+    double sn, cs;
+    sincospi(-2.0 * (double)((ky * y) % M) / (double)M, &sn, &cs);
+    const double2 t = tmp[y * M + kx];
+    re += t.x * cs - t.y * sn;
+    im += t.x * sn + t.y * cs;
+    l1 += tmp[M * M + y].x;
+  }
+  const double bound = 4.0 * M * 0x1p-52 * l1;
+  qspec[e] = hypot(re, im) <= bound ? make_float2(0.0f, 0.0f) : make_float2((float)re, (float)im);
+}
+
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given, const double2* q64,
                                   double* u0, double* w0, float* w0f, float* u0f, float2* qf, double* lvl,
                                   int lvl_a_off, double2* scr_q, double* scr_u, int rb, float4* qtab,
-                                  hipStream_t s) {
+                                  float2* qspec, double2* spec_tmp, hipStream_t s) {
   hipLaunchKernelGGL(level_constants_kernel, dim3(1), dim3(1024), 0, s, m, levels, alpha, u_given, q64, u0,
                      w0, w0f, u0f, qf, lvl, lvl_a_off, scr_q, scr_u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(probe_spectrum_rows_kernel, dim3(m), dim3(m), 0, s, m, (const float2*)qf, spec_tmp);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
 #define MG_QT(MM, RR)                                                                                     \
   if (m == MM && rb == RR) {                                                                              \
     hipLaunchKernelGGL((qtab_kernel<MM, RR>), dim3((MM * MM + 255) / 256), dim3(256), 0, s, qf, u0f, qtab); \
+    e = hipGetLastError();                                                                                \
+    if (e != hipSuccess) return e;                                                                        \
+    hipLaunchKernelGGL((probe_spectrum_cols_kernel<MM, RR>), dim3((MM * MM + 255) / 256), dim3(256), 0, s, \
+                       (const double2*)spec_tmp, qspec);                                                  \
     return hipGetLastError();                                                                             \
   }
   MG_FOR_EACH_PLAN(MG_QT)

@@ -162,7 +162,7 @@ def run(workload: str = "512x512", levels=None, alphas=(0.2, 0.5, 1.0), peaks=(N
                               "overlap": ov, "step": cfg.step, "positions": int(len(offs)), "batch": B})
                     out["runs"].append(r)
                     last = r["errors"][-1]
-                    log(f"overlap {ov if ov is not None else 'cfg'} (step {cfg.step}, {len(offs)} pos) "
+                    log(f"overlap {ov if ov is not None else 'as scanned'} (step {cfg.step}, {len(offs)} pos) "
                         f"noise {noise_label(noise):>10} alpha {alpha:<5g} L {L}: Phi {r['phi'][0]:.3e} -> "
                         f"{r['phi'][-1]:.3e}, err {last[1]:.3e} (magnitude {last[2]:.3e}) after {last[0]} epochs, "
                         f"stat <= {tol:g} at epoch {r['tol_epoch']}, {r['seconds'] * 1e3:.1f} ms")
@@ -303,7 +303,7 @@ def table(res: dict, at=None) -> str:
     for r in res["runs"]:
         e = {ep: er for ep, er, _ in r["errors"]}
         cells = " | ".join(f"{e[c]:.3e}" if c in e else "" for c in cps)
-        ov = "cfg" if r.get("overlap") is None else f"{r['overlap']:g}"
+        ov = "as scanned" if r.get("overlap") is None else f"{r['overlap']:g}"
         rows.append(f"| {ov} | {r.get('noise', 'none')} | {r['alpha']:g} | {r['levels']} | {cells} | "
                     f"{r['phi'][-1]:.3e} | {r['tol_epoch']} |")
     return "\n".join(rows)

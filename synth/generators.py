@@ -1,8 +1,8 @@
 """Seeded generators for objects, probes, scans, noise and permutations.
 
 Every stream comes from ``numpy.random.Generator(PCG64)`` spawned from
-``SeedSequence(250410118 + config_id)`` so that a configuration is fully
-reproducible from its id alone.  Nothing here evaluates the forward model:
+``SeedSequence(250410118 + seed_id)`` so that a workload is fully
+reproducible from its seed id alone.  Nothing here evaluates the forward model:
 callers compute noiseless intensities with their own implementation and pass
 them to :func:`poisson_counts`.
 """

@@ -66,7 +66,7 @@ def test_truth_is_fixed_point(rng, L, B):
         assert np.linalg.norm(z1 - zs) <= 1e-13 * np.linalg.norm(zs)
 
 
-def _cfg1_problem():
+def _problem_128x128():
     from synth import WORKLOADS, make_problem_inputs
     cfg = WORKLOADS["128x128"]
     z_true, Q, offs, _, r_perm = make_problem_inputs(cfg)
@@ -78,9 +78,9 @@ def _cfg1_problem():
 
 @pytest.mark.slow
 @pytest.mark.parametrize("L,B", [(1, 1), (2, 8), (3, 1)])
-def test_recovery_near_truth_cfg1(L, B):
+def test_recovery_near_truth_128x128(L, B):
     """Noiseless 128 x 128 workload from z* (1 + 0.05 CN(0,1)): the masked relative error falls >= 20x in 60 epochs."""
-    cfg, zt, Q, offs, sd, r_perm = _cfg1_problem()
+    cfg, zt, Q, offs, sd, r_perm = _problem_128x128()
     rng = np.random.default_rng(7)
     z0 = zt * (1 + 0.05 * (rng.standard_normal(zt.shape) + 1j * rng.standard_normal(zt.shape)) / np.sqrt(2))
     mask = oracle.illumination(zt.shape, Q, offs) >= 0.1 * oracle.illumination(zt.shape, Q, offs).max()
