@@ -422,6 +422,20 @@ def bench_batched(steps, warmup, seed, batch=None, alpha=None, tuning=""):
     t3 = time.perf_counter()
     ctxs[0].set_timing(False)
     phis = [c.objective()[0] for c in ctxs]
+    # the same epochs through the work-queue launch (flag PERSISTENT: one launch per FFT
+    # plan and chunk of epochs), after one untimed epoch
+    from paper_2504_10118_amd import PERSISTENT
+    for c in ctxs:
+        c.set_flags(PERSISTENT)
+    run_epochs_multi(ctxs, 1, batches, seed=seed + 2)
+    reset()
+    t4 = time.perf_counter()
+    run_epochs_multi(ctxs, steps, batches, seed=seed)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    phis_q = [c.objective()[0] for c in ctxs]
+    for c in ctxs:
+        c.set_flags(0)
     for c in ctxs:
         c.close()
     torch.cuda.set_stream(torch.cuda.default_stream())
@@ -436,6 +450,8 @@ def bench_batched(steps, warmup, seed, batch=None, alpha=None, tuning=""):
         "acc_launch_us": tm["accum_ms"] * 1e3 / max(1, tm["accum_launches"]), "acc_launches": tm["accum_launches"],
         "event_wall": t3 - t2, "step_ms_sum": tm["step_ms"], "acc_ms_sum": tm["accum_ms"],
         "phi_median": float(np.median(phis)), "alpha": alpha,
+        "queue": {"value": steps * total_pos / (t5 - t4), "ms_per_step": (t5 - t4) * 1e3 / steps,
+                  "objectives_equal": bool(phis_q == phis)},
         "workload": (f"{len(specs)} independent reconstructions, objects "
                      f"{min(sp.n for sp in specs)}..{max(sp.n for sp in specs)} px, probes 64 ({ms.count(64)}) "
                      f"and 128 ({ms.count(128)}), {min(sp.n_pos for sp in specs)}..{max(sp.n_pos for sp in specs)} "
@@ -447,7 +463,8 @@ def bench_batched(steps, warmup, seed, batch=None, alpha=None, tuning=""):
 def batched_summary(r, steps):
     return {"workload": r["workload"], "value": r["value"], "unit": "patterns/s", "ms_per_step": r["ms_per_step"],
             "steps": steps, "step_kernel_frac": (r["achieved"] / HBM_PEAK_GBS) if r["achieved"] else None,
-            "step_launch_us": r["step_launch_us"], "accumulate_launch_us": r["acc_launch_us"]}
+            "step_launch_us": r["step_launch_us"], "accumulate_launch_us": r["acc_launch_us"],
+            "work_queue": r["queue"]}
 
 
 def base_line(metric_value, steps, warmup, ms_per_step):
@@ -553,6 +570,8 @@ def main():
                              "step_share": r["step_ms_sum"] * 1e-3 / r["event_wall"],
                              "accumulate_share": r["acc_ms_sum"] * 1e-3 / r["event_wall"]}
         out["objective_after_median"] = r["phi_median"]
+        out["work_queue"] = dict(r["queue"], note="the same epochs with the flag PERSISTENT: one work-queue "
+                                 "launch per FFT plan and chunk of epochs instead of launches per round")
         print(json.dumps(out), flush=True)
         return
 

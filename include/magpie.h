@@ -64,6 +64,9 @@ extern "C" {
 #define MAGPIE_PROBE_ALTERNATE 0x8u /* with MAGPIE_UPDATE_PROBE: take the probe step at the
                                      minibatch's updated object (alternating half steps)
                                      instead of at the object the step started from */
+#define MAGPIE_PERSISTENT   0x10u /* run epochs as one work-queue launch per FFT plan and
+                                     chunk of epochs (see magpie_run_epochs_multi); same
+                                     results bit for bit */
 
 typedef struct magpie_ctx magpie_ctx;
 
@@ -320,6 +323,26 @@ int magpie_autotune(magpie_ctx* ctx, int batch, int trial_epochs, double* step_u
  * here.  Errors: INVALID_ARG, BAD_STATE, UNSUPPORTED, OOM, HIP.
  */
 int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, const int* batch, uint64_t seed);
+/*
+ * With MAGPIE_PERSISTENT set on every context of the call (or on none: mixing
+ * is INVALID_ARG), the rounds of each chunk of up to 8 epochs run as one
+ * work-queue launch per FFT plan instead of two or more launches per round
+ * (the batched, persistent execution of many reconstructions; the paper leaves
+ * the minibatch/GPU variant of Alg 4 to future work).  Workgroups, as many as
+ * are resident, take items in queue order: for each round, one per position of
+ * every context's minibatch (the step), then one per accumulation tile of every
+ * context (tile height m * threads_per_transform / 32, which gives the same
+ * sums: the summation order does not depend on the tile).  A step waits for its
+ * context's tiles of earlier rounds, a tile for its context's steps so far;
+ * data handed between workgroups is read and written at device scope.  Results
+ * are identical to those without the flag.  magpie_run_epochs with the flag set
+ * runs its context this way (caller orders: UNSUPPORTED).  A wait that exceeds
+ * its bound (2 s of the device clock; the environment variable
+ * MAGPIE_QUEUE_WAIT_US overrides it, in microseconds) stops the queue: the call
+ * returns MAGPIE_ERR_HIP and the objects are left part-way.  UNSUPPORTED: a
+ * context's FFT plan with fewer than 64 threads (m = 8, and m = 16 at 2
+ * threads per transform) or a minibatch of more than 256 positions.
+ */
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@ from .magpie import (  # noqa: F401
     UPDATE_PROBE,
     PHASE_RECYCLE,
     PROBE_ALTERNATE,
+    PERSISTENT,
     GRAPH,
     LIB_PATH,
     Magpie,

@@ -147,6 +147,8 @@ int build_tiles(magpie_ctx* c) {
     c0 = std::min(c0, offsets[2 * k + 1]);
     c1 = std::max(c1, offsets[2 * k + 1] + m - 1);
   }
+  c->scan_r0 = r0;
+  c->scan_r1 = r1;
   c->box_x0 = c0 / mg::ACC_TILE_W;
   c->box_y0 = r0 / c->th;
   c->box_nx = c1 / mg::ACC_TILE_W - c->box_x0 + 1;
@@ -278,6 +280,7 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->qtab);
   dev_free(c->qspec);
   dev_free(c->spec_tmp);
+  dev_free(c->qctr);
   dev_free(c->q64);
   dev_free(c->u0);
   dev_free(c->w0);
@@ -801,6 +804,12 @@ extern "C" {
 
 int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, const int32_t* order) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (c->flags & MAGPIE_PERSISTENT) {
+    // the work-queue launch of the multi-context runs, with this context alone
+    if (order) return fail(MAGPIE_ERR_UNSUPPORTED, "MAGPIE_PERSISTENT runs draw their own orders (seed)");
+    if (batch < 1) return fail(MAGPIE_ERR_INVALID_ARG, "batch >= 1 required");
+    return magpie_run_epochs_multi(&c, 1, n_epochs, &batch, seed);
+  }
   if (n_epochs == 0 && batch >= 1) return MAGPIE_OK;
   const bool use_graph = !c->timing && (c->flags & MAGPIE_GRAPH);
   int rc;
@@ -962,7 +971,8 @@ int magpie_sync(magpie_ctx* c) {
 
 int magpie_set_flags(magpie_ctx* c, uint32_t flags, double beta) {
   if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
-  if (flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_GRAPH | MAGPIE_PHASE_RECYCLE | MAGPIE_PROBE_ALTERNATE))
+  if (flags & ~(MAGPIE_UPDATE_PROBE | MAGPIE_GRAPH | MAGPIE_PHASE_RECYCLE | MAGPIE_PROBE_ALTERNATE |
+                MAGPIE_PERSISTENT))
     return fail(MAGPIE_ERR_INVALID_ARG, "unknown flag");
   if ((flags & MAGPIE_PROBE_ALTERNATE) && !(flags & MAGPIE_UPDATE_PROBE))
     return fail(MAGPIE_ERR_INVALID_ARG, "MAGPIE_PROBE_ALTERNATE needs MAGPIE_UPDATE_PROBE");
@@ -1241,6 +1251,18 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return fail(MAGPIE_ERR_INVALID_ARG, "a context appears twice");
   }
+  // MAGPIE_PERSISTENT: one work-queue launch per plan partition and chunk
+  const bool queue = (ctxs[0]->flags & MAGPIE_PERSISTENT) != 0;
+  for (int i = 1; i < count; ++i)
+    if (((ctxs[i]->flags & MAGPIE_PERSISTENT) != 0) != queue)
+      return fail(MAGPIE_ERR_INVALID_ARG, "MAGPIE_PERSISTENT must be set on every context of the run or on none");
+  if (queue)
+    for (int i = 0; i < count; ++i) {
+      if (mg::qtile_rows(ctxs[i]->m, ctxs[i]->rb) == 0)
+        return fail(MAGPIE_ERR_UNSUPPORTED, "the work-queue launch needs an FFT plan of at least 64 threads");
+      if (std::min(batch[i], ctxs[i]->n_pos) > mg::ACC_SCAN_MAX)
+        return fail(MAGPIE_ERR_UNSUPPORTED, "the work-queue launch takes minibatches of at most 256 positions");
+    }
   if (n_epochs == 0) return MAGPIE_OK;
   magpie_ctx* c0 = ctxs[0];
   int rc = set_dev(c0);
@@ -1288,6 +1310,7 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     int R = 0;                            // rounds of the current chunk
     size_t desc0 = 0, pre0 = 0;           // offsets of its descriptors / running totals
     size_t pre_per_round = 0;
+    size_t q0 = 0;                        // work queue: offset of its gpre / wait arrays (ints)
     hipStream_t stream = nullptr;
   };
   std::vector<Part> parts;
@@ -1308,6 +1331,41 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     B[i] = std::min(batch[i], ctxs[i]->n_pos);
     nb[i] = (ctxs[i]->n_pos + B[i] - 1) / B[i];
   }
+  // work queue: every member's tiles at the plan's queue tile height; counters per
+  // partition (done per member, then head), then the run's abort flag
+  std::vector<size_t> qctr0(parts.size(), 0);
+  long long wait_ticks = 0;
+  size_t n_ctr = 0;
+  if (queue) {
+    for (size_t g = 0; g < parts.size(); ++g) {
+      parts[g].ths.assign(1, mg::qtile_rows(parts[g].m, parts[g].rb));
+      qctr0[g] = n_ctr;
+      n_ctr += 2 * parts[g].members.size() + 1;
+    }
+    ++n_ctr;
+    if (c0->qctr_cap < n_ctr) {
+      dev_free(c0->qctr);
+      c0->qctr_cap = 0;
+      rc = dev_alloc(&c0->qctr, n_ctr);
+      if (rc) {
+        cleanup();
+        return rc;
+      }
+      c0->qctr_cap = n_ctr;
+    }
+    if (mg::clear_i32(c0->qctr, (int)n_ctr, st) != hipSuccess) {
+      cleanup();
+      return fail(MAGPIE_ERR_HIP, "work-queue counter clear failed");
+    }
+    // bound of one wait: 2 s of the GPU's constant wall clock (MAGPIE_QUEUE_WAIT_US overrides)
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c0->device) != hipSuccess || khz <= 0)
+      khz = 100000;
+    double us = 2e6;
+    if (const char* env = std::getenv("MAGPIE_QUEUE_WAIT_US")) us = std::max(0.0, std::atof(env));
+    wait_ticks = (long long)(us * 1e-3 * khz);
+  }
+  int* const q_abort = queue ? c0->qctr + (n_ctr - 1) : nullptr;
   std::vector<hipEvent_t> fork_ev(parts.size(), nullptr), join_ev(parts.size(), nullptr);
   for (size_t g = 0; g < parts.size() && !rc; ++g) {
     if (g == 0) {
@@ -1334,7 +1392,7 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     // round descriptors of the chunk: per partition and round its members' step
     // descriptors, then their accumulation descriptors by tile height; running
     // totals: one block for the step launch, one per tile height (n_members + 1 ints)
-    size_t n_desc = 0, n_pre = 0;
+    size_t n_desc = 0, n_pre = 0, n_q = 0;
     for (auto& p : parts) {
       p.R = 0;
       for (int i : p.members) p.R = std::max(p.R, ne * nb[i]);
@@ -1343,10 +1401,13 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
       p.pre_per_round = (p.members.size() + 1) * (1 + p.ths.size());
       n_desc += (size_t)p.R * p.members.size();
       n_pre += (size_t)p.R * p.pre_per_round;
+      p.q0 = n_q;
+      if (queue) n_q += 2 * (2 * (size_t)p.R * p.members.size()) + 1;   // gpre (G + 1), wait (G)
     }
     const size_t off_a = (n_desc * sizeof(mg::StepArgs) + 255) & ~(size_t)255;
     const size_t off_p = (off_a + n_desc * sizeof(mg::AccumArgs) + 255) & ~(size_t)255;
-    const size_t bytes = off_p + n_pre * sizeof(int);
+    const size_t off_q = (off_p + n_pre * sizeof(int) + 255) & ~(size_t)255;
+    const size_t bytes = off_q + n_q * sizeof(int);
     rc = multi_slot(c0, slot, bytes);
     if (rc) break;
     unsigned char* hbase = static_cast<unsigned char*>(c0->mdesc_host[slot]);
@@ -1396,7 +1457,7 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
           for (size_t j = 0; j < nm; ++j) {
             const int i = p.members[j];
             magpie_ctx* c = ctxs[i];
-            if (c->th != p.ths[h]) continue;
+            if (!queue && c->th != p.ths[h]) continue;
             mg::AccumArgs a{};
             a.z = c->z;
             a.n_rows = c->nr;
@@ -1417,6 +1478,11 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
               a.inv = c->inv + ((size_t)slot * CH + er) * c->n_pos;
               a.batch_index = t;
               a.n_tiles = c->box_nx * c->box_ny;
+              if (queue) {   // the box at the queue's tile height (screened from the records)
+                const int tq = p.ths[0];
+                a.box_y0 = c->scan_r0 / tq;
+                a.n_tiles = c->box_nx * (c->scan_r1 / tq - a.box_y0 + 1);
+              }
               if (B[i] <= mg::ACC_SCAN_MAX) {
                 a.pos = c->posrec + ((size_t)slot * CH + er) * c->n_pos + (size_t)t * B[i];
                 a.count = std::min(B[i], c->n_pos - t * B[i]);
@@ -1428,6 +1494,31 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
             apre[jj + 1] = apre[jj] + a.n_tiles;
             ad[k++] = a;
             ++jj;
+          }
+        }
+      }
+      if (queue) {
+        // queue order: round r, steps of every member, then tiles of every member;
+        // steps wait for the member's tiles of earlier rounds, tiles for its steps so far
+        const size_t G = 2 * (size_t)p.R * nm;
+        int* gpre = reinterpret_cast<int*>(hbase + off_q) + p.q0;
+        int* wait = gpre + G + 1;
+        std::vector<int> steps_so_far(nm, 0), tiles_before(nm, 0);
+        gpre[0] = 0;
+        for (int r = 0; r < p.R; ++r) {
+          const mg::StepArgs* sd = hs + p.desc0 + (size_t)r * nm;
+          const mg::AccumArgs* ad = ha + p.desc0 + (size_t)r * nm;
+          for (size_t j = 0; j < nm; ++j) {
+            const size_t g = (2 * (size_t)r) * nm + j;
+            gpre[g + 1] = gpre[g] + sd[j].count;
+            wait[g] = tiles_before[j];
+            steps_so_far[j] += sd[j].count;
+          }
+          for (size_t j = 0; j < nm; ++j) {
+            const size_t g = (2 * (size_t)r + 1) * nm + j;
+            gpre[g + 1] = gpre[g] + ad[j].n_tiles;
+            wait[g] = steps_so_far[j];
+            tiles_before[j] += ad[j].n_tiles;
           }
         }
       }
@@ -1446,6 +1537,26 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     }
     int R = 0;
     for (auto& p : parts) R = std::max(R, p.R);
+    if (queue) R = 0;   // one work-queue launch per partition instead of the rounds below
+    for (size_t g = 0; queue && g < parts.size() && e == hipSuccess; ++g) {
+      const Part& p = parts[g];
+      const size_t nm = p.members.size();
+      const int* gpre = reinterpret_cast<const int*>(hbase + off_q) + p.q0;
+      mg::QueueArgs q{};
+      q.sdesc = ds + p.desc0;
+      q.adesc = da + p.desc0;
+      q.gpre = reinterpret_cast<const int*>(dbase + off_q) + p.q0;
+      q.n_groups = (int)(2 * (size_t)p.R * nm);
+      q.wait = q.gpre + q.n_groups + 1;
+      q.n_members = (int)nm;
+      q.total = gpre[q.n_groups];
+      q.done = c0->qctr + qctr0[g];
+      q.head = q.done + 2 * nm;
+      q.abort = q_abort;
+      q.wait_ticks = wait_ticks;
+      e = mg::clear_i32(q.done, (int)(2 * nm + 1), p.stream);
+      if (e == hipSuccess) e = mg::launch_queue(p.m, p.rb, q, c0->n_cu, p.stream);
+    }
     for (int r = 0; r < R && e == hipSuccess; ++r) {
       for (size_t g = 0; g < parts.size() && e == hipSuccess; ++g) {
         const Part& p = parts[g];
@@ -1479,6 +1590,14 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
   }
   if (!rc && e == hipSuccess) e = hipStreamSynchronize(st);
   if (!rc && e != hipSuccess) rc = fail(MAGPIE_ERR_HIP, std::string("multi-context run: ") + hipGetErrorString(e));
+  if (!rc && queue) {
+    int aborted = 0;
+    e = hipMemcpy(&aborted, q_abort, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = fail(MAGPIE_ERR_HIP, std::string("multi-context run: ") + hipGetErrorString(e));
+    else if (aborted)
+      rc = fail(MAGPIE_ERR_HIP, "work-queue launch stopped (a wait for earlier items exceeded its bound); the "
+                                "objects are left part-way through the run");
+  }
   if (rc) {
     // a failed run returns only once nothing it queued still runs on the contexts' buffers
     for (auto& p : parts)

@@ -235,6 +235,14 @@ __device__ __forceinline__ float4 bload4(rsrc_t r, int voff, int soff) {
 // store device scope, i.e. written through this XCD's L2.
 constexpr int kPolicyDeviceScope = 0x10;
 
+// Load with a cache policy fixed at compile time; with kPolicyDeviceScope it
+// reads the value at device scope, coherent with device-scope stores that
+// workgroups on other XCDs made earlier in the same launch.
+template <int POL>
+__device__ __forceinline__ float2 bload2p(rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, POL));
+}
+
 __device__ __forceinline__ void bstore2(rsrc_t r, float2 v, int voff, int soff) {
   typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);

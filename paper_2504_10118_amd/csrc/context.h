@@ -122,6 +122,7 @@ struct magpie_ctx {
   int4* tile_ent = nullptr;
   int tiles_x = 0, tiles_y = 0;
   int box_x0 = 0, box_y0 = 0, box_nx = 0, box_ny = 0;   // tiles some window reaches
+  int scan_r0 = 0, scan_r1 = 0;  // first and last object row some window covers
   std::vector<int32_t> h_offs;
 
   float2* stage = nullptr;
@@ -148,6 +149,10 @@ struct magpie_ctx {
   size_t mdesc_cap[2] = {0, 0};
   hipEvent_t mdesc_done[2] = {nullptr, nullptr};
   bool mdesc_pending[2] = {false, false};
+  // work-queue counters of multi-context runs led by this context (per plan
+  // partition: done per member, head; then one abort flag for the run)
+  int* qctr = nullptr;
+  size_t qctr_cap = 0;   // ints
   std::vector<int32_t> h_perm;   // host scratch: one epoch's permutation
   std::vector<int> h_seen;       // host scratch: permutation check
 

@@ -111,6 +111,30 @@ hipError_t launch_step_multi(int m, int rb, const StepArgs* descs, const int* pr
                              hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, const int* prefix, int n_ctx, int total,
                                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Work-queue launch over the rounds of a chunk for the members of one FFT plan
+// (m, rb): in queue order, group g = (2 r + phase) n_members + j holds the step
+// items (phase 0: one per position of member j's round-r minibatch) or the tile
+// items (phase 1: one per tile of member j's box at tile height qtile_rows(m, rb))
+// of member j in round r, items gpre[g] .. gpre[g + 1] - 1.  A group's items wait
+// until done[j + n_members] (tiles finished, for steps) or done[j] (steps
+// finished, for tiles) reaches wait[g].  done, head: zero before the launch.
+struct QueueArgs {
+  const StepArgs* sdesc;    // [rounds][n_members]
+  const AccumArgs* adesc;   // [rounds][n_members], boxes at tile height qtile_rows(m, rb)
+  const int* gpre;          // [n_groups + 1]
+  const int* wait;          // [n_groups]
+  int n_groups, n_members, total;
+  int* done;                // [2 n_members]
+  int* head;                // next item
+  int* abort;               // set by a wait longer than wait_ticks (s_memrealtime ticks); stops the queue
+  long long wait_ticks;
+};
+// Tile height whose 32-wide tiles take all m * rb threads of the plan (0: the
+// plan has fewer than 64 threads and no work-queue launch).
+int qtile_rows(int m, int rb);
+// grid: the plan's resident workgroups on n_cu compute units (at most total)
+hipError_t launch_queue(int m, int rb, const QueueArgs& q, int n_cu, hipStream_t s);
+hipError_t clear_i32(int* p, int n, hipStream_t s);
 // Level constants, the plan's probe table and the probe spectrum (qspec; spec_tmp:
 // m*m + m double2 of scratch).
 hipError_t launch_level_constants(int m, int levels, double alpha, int u_given,

@@ -273,8 +273,7 @@ __device__ __forceinline__ bool modulus_diff(float2 t, float s, float2& out, flo
 // latency overlaps the wait.
 template <int M, int TPB, int P, int RB, int RA>
 __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const float2* v, const float* u0v,
-                          int col, int g, float2* stage_k) {
-  const int tid = threadIdx.x;
+                          int col, int g, float2* stage_k, const int tid) {
   const int L = a.levels;
   constexpr int M1 = M / 2, S1 = M1 + 1;
   constexpr int E1 = (M1 * M1 + TPB - 1) / TPB;               // level-1 bins per thread
@@ -406,7 +405,9 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
 // or its own row slice (row passes) of the transpose tile T, so the register
 // stages exchange data through LDS without workgroup barriers; only the two
 // transposes (forward and back) synchronise the workgroup.
-template <int M, int RBv, int MODE>
+// COH: the object is read at device scope (the work-queue launch, where other
+// workgroups of the same launch update it).
+template <int M, int RBv, int MODE, bool COH = false>
 __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   constexpr int RB = Plan<M, RBv>::RB, RA = Plan<M, RBv>::RA;
   constexpr int TPB = M * RB, CB = RA / RB, P = M + Plan<M, RBv>::PAD;
@@ -423,7 +424,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   extern __shared__ double2 smem_d2[];
   float2* T = reinterpret_cast<float2*>(smem_d2);
 
-  const int tid = threadIdx.x;
+  // In the work-queue launch the body runs in a loop: an opaque copy of the
+  // thread index keeps the compiler from hoisting the index arithmetic out of
+  // the loop and holding it in registers across both item kinds.
+  int tid = threadIdx.x;
+  if constexpr (COH) asm volatile("" : "+v"(tid));
   const int g = tid & (RB - 1);
   const int col = tid / RB;
   const int cl = col & (CPW - 1);
@@ -439,6 +444,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   } else {
     k = a.perm ? a.perm[eoff + wg] : (int)wg;
     off = a.offs[k];
+  }
+  if constexpr (COH) {
+    // loaded inside the queue's loop these are vector loads (earlier items' stores
+    // may alias them); the values are uniform, and the buffer resources built
+    // from them must be scalar
+    k = __builtin_amdgcn_readfirstlane(k);
+    off = make_int2(__builtin_amdgcn_readfirstlane(off.x), __builtin_amdgcn_readfirstlane(off.y));
   }
 
   // exchange index inside the wave's slice: (cl, k1, n2) -> [0, 64 * RA)
@@ -458,6 +470,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   const rsrc_t zr = make_rsrc(zbase, (unsigned)(((size_t)(a.n_rows - off.x) * a.n_cols - off.y) * sizeof(float2)));
   const int zvo = (g * a.n_cols + col) * (int)sizeof(float2);
   const int zso = RB * a.n_cols * (int)sizeof(float2);
+  constexpr int ZPOL = COH ? kPolicyDeviceScope : 0;
   constexpr int qso = RB * M * (int)sizeof(float2);
   const float4* qt = a.qtab + tid;   // [n1][tid]: each load reads one contiguous block
   const float2* qt2 = reinterpret_cast<const float2*>(a.qtab) + tid;            // split table: Q
@@ -530,7 +543,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     const int gso = GR * a.n_cols * (int)sizeof(float2);
     float2* const dst = T + (tid / M) * P + (tid & (M - 1));
 #pragma unroll
-    for (int j = 0; j < RA; ++j) dst[j * GR * P] = bload2(zr, gvo, j * gso);
+    for (int j = 0; j < RA; ++j) dst[j * GR * P] = bload2p<ZPOL>(zr, gvo, j * gso);
   };
   row_gather();
   // The probe table (needed with the patch), the constants (parked in LDS
@@ -763,7 +776,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
         if (a.probe_num) {
           // probe step partials: conj(z_k)(R_k - Q z_k) and |z_k|^2 (the patch
           // is read again for them, at the column stride)
-          const float2 zz = bload2(zr, zvo, n1 * zso);
+          const float2 zz = bload2p<ZPOL>(zr, zvo, n1 * zso);
           const float2 pn = cmulc(zz, make_float2(-dk.x, -dk.y));
           const float pd = zz.x * zz.x + zz.y * zz.y;
           const size_t e = (size_t)wg * M * M + (size_t)(RB * n1 + g) * M + col;
@@ -884,7 +897,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
       for (int n1 = 0; n1 < RA; ++n1) T[(RB * n1 + g) * P + col] = v[n1];
       __syncthreads();
-      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, u0v, col, g, a.stage + (size_t)wg * M * M);
+      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, u0v, col, g, a.stage + (size_t)wg * M * M, tid);
     }
   }
 }
@@ -1019,7 +1032,10 @@ size_t step_lds_bytes(int m, int rb) {
 // that order (FP64 sums of the staged FP32 c_k and an FP32 copy of w0).  Loads are predicated
 // rather than branched so that several positions' loads are in flight.
 // ---------------------------------------------------------------------------
-template <int TH>
+// COH: the staged updates and the object are read, and the object written, at
+// device scope (the work-queue launch, where workgroups on other XCDs produce
+// and consume them within the launch).
+template <int TH, bool COH = false>
 __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b) {
   constexpr int NT = acc_threads(TH);
   constexpr int NW = NT / 64;
@@ -1030,7 +1046,8 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
   __shared__ int s_wcnt[NW];
   const int tx = a.box_x0 + b % a.box_nx, ty = a.box_y0 + b / a.box_nx;
   const int tile = ty * a.tiles_x + tx;
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
+  if constexpr (COH) asm volatile("" : "+v"(tid));   // as in step_body
   const int lane = tid & 63, wave = tid >> 6;
   const int X = tx * ACC_TILE_W + (lane & 31);
   const int Y0 = ty * TH + 2 * wave + (lane >> 5);
@@ -1042,10 +1059,20 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
   // the tile's current object values, fetched first: their latency overlaps
   // the screening and the staged loads
   float2 zo[RPT];
+  [[maybe_unused]] rsrc_t zrs, srs;
+  if constexpr (COH) {
+    zrs = make_rsrc(a.z, (unsigned)((size_t)a.n_rows * a.n_cols * sizeof(float2)));
+    srs = make_rsrc(a.stage, (unsigned)((size_t)a.batch * m * m * sizeof(float2)));
+  }
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int Y = Y0 + 2 * NW * i;
-    zo[i] = (X < a.n_cols && Y < a.n_rows) ? a.z[(size_t)Y * a.n_cols + X] : make_float2(0.0f, 0.0f);
+    if constexpr (COH)
+      zo[i] = (X < a.n_cols && Y < a.n_rows)
+                  ? bload2p<kPolicyDeviceScope>(zrs, (int)((unsigned)(Y * a.n_cols + X) * (unsigned)sizeof(float2)), 0)
+                  : make_float2(0.0f, 0.0f);
+    else
+      zo[i] = (X < a.n_cols && Y < a.n_rows) ? a.z[(size_t)Y * a.n_cols + X] : make_float2(0.0f, 0.0f);
   }
   // candidates: the minibatch's own records (slot = processing index; a window
   // overlaps the tile where it reaches both its column and its row range), or the
@@ -1112,7 +1139,10 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
           const int yy = Y0 + 2 * NW * i - o.x;
           ok[u][i] = okx && ((unsigned)yy < (unsigned)m);
           const int e = ok[u][i] ? (yy * m + xx) : 0;
-          cv[u][i] = a.stage[(size_t)sl * mm + e];
+          if constexpr (COH)
+            cv[u][i] = bload2p<kPolicyDeviceScope>(srs, (int)(((unsigned)sl * (unsigned)mm + e) * sizeof(float2)), 0);
+          else
+            cv[u][i] = a.stage[(size_t)sl * mm + e];
           wv[u][i] = a.w0f[e];
         }
       }
@@ -1132,9 +1162,14 @@ __device__ __forceinline__ void accumulate_body(const AccumArgs& a, const int b)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int Y = Y0 + 2 * NW * i;
-      if (Y < a.n_rows && dd[i] > 0.0)
-        a.z[(size_t)Y * a.n_cols + X] =
+      if (Y < a.n_rows && dd[i] > 0.0) {
+        const float2 zn =
             make_float2((float)((double)zo[i].x + nr[i] / dd[i]), (float)((double)zo[i].y + ni[i] / dd[i]));
+        if constexpr (COH)
+          bstore2_device(zrs, zn, (int)((unsigned)(Y * a.n_cols + X) * (unsigned)sizeof(float2)), 0);
+        else
+          a.z[(size_t)Y * a.n_cols + X] = zn;
+      }
     }
   }
 }
@@ -1151,6 +1186,100 @@ __global__ __launch_bounds__(acc_threads(TH)) void accumulate_multi_kernel(const
   const int j = owner_of(prefix, n_ctx, b);
   const AccumArgs a = load_accum_args(descs + j);
   accumulate_body<TH>(a, b - prefix[j]);
+}
+
+// ---------------------------------------------------------------------------
+// Work-queue launch over many reconstructions' rounds (one launch per FFT plan
+// and chunk of rounds, in place of a step and an accumulation launch per
+// round).  Each workgroup takes the next item from a counter, waits until the
+// items it depends on are done, runs it, and counts it done:
+//   step item (member j, round r, position b): waits for the accumulation of
+//     every tile of j's earlier rounds (it reads the object they wrote, and
+//     writes staging slots they read);
+//   tile item (member j, round r, tile b, tile height M RB / 32 so that its
+//     pixels take all threads): waits for every step of j's rounds up to r.
+// Items are queued round by round, steps before tiles, so every item depends
+// only on items taken before it: the earliest unfinished item always has its
+// dependencies done and is held by a running workgroup, so the queue drains
+// whatever the number of resident workgroups.  Data handed between workgroups
+// (object, staged updates) is stored and loaded at device scope, which keeps
+// it coherent across the XCDs' L2 caches without cache write-back or
+// invalidation; a workgroup counts an item done only after its stores have
+// completed.  A wait longer than wait_ticks sets the abort flag, after which
+// every workgroup stops taking items (the host reports the failure).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ld_agent(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int add_agent(int* p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Four waves per SIMD (two 512-thread workgroups per CU) for the 64 x 64 plan
+// of 8 threads per transform, as for its step kernel (the loop around both item
+// kinds otherwise takes one register more than that allows).
+constexpr int queue_min_waves(int m, int rb) { return (m == 64 && rb == 8) ? 4 : 1; }
+
+template <int M, int RBv>
+__global__ __launch_bounds__(M * RBv, queue_min_waves(M, RBv)) void queue_kernel(QueueArgs q) {
+  constexpr int TH = M * RBv / ACC_TILE_W;
+  static_assert(acc_threads(TH) == M * RBv && TH >= 2, "tile items take every thread");
+  __shared__ int s_item, s_ok;
+  const int tid = threadIdx.x;
+  const int nm = q.n_members;
+  int* prev = nullptr;   // done counter of the item just finished (uniform)
+  // each pass takes a distinct index from head, so a workgroup makes at most
+  // total + 1 passes; more would mean the queue is broken: stop it
+  for (int pass = 0;; ++pass) {
+    if (pass > q.total) {
+      if (tid == 0) __hip_atomic_store(q.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    // one region of thread 0 per iteration, between barriers: count the last item
+    // done (its stores completed before the barrier that ends it), take the next
+    if (tid == 0) {
+      if (prev) add_agent(prev, 1);
+      s_item = ld_agent(q.abort) ? q.total : add_agent(q.head, 1);
+    }
+    __syncthreads();
+    // uniform across the workgroup: the item's descriptors then load into scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= q.total) break;
+    const int g = owner_of(q.gpre, q.n_groups, it);
+    const int gr = g / nm, j = g - gr * nm;
+    const int r = gr >> 1, ph = gr & 1;   // ph 0: step item, 1: tile item
+    if (tid == 0) {
+      const int* ctr = q.done + (ph == 0 ? nm : 0) + j;
+      const int need = q.wait[g];
+      int ok = 1;
+      if (ld_agent(ctr) < need) {
+        const long long t0 = (long long)wall_clock64();
+        while (ld_agent(ctr) < need) {
+          if (ld_agent(q.abort) || (long long)wall_clock64() - t0 > q.wait_ticks) {
+            __hip_atomic_store(q.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
+    const int b = __builtin_amdgcn_readfirstlane(it - q.gpre[g]);
+    if (ph == 0) {
+      StepArgs a = load_step_args(q.sdesc + (size_t)r * nm + j);
+      a.stage_wt = 1;   // staged updates at device scope: tile items on other XCDs read them
+      step_body<M, RBv, MODE_STEP, true>(a, b);
+    } else {
+      const AccumArgs a = load_accum_args(q.adesc + (size_t)r * nm + j);
+      accumulate_body<TH, true>(a, b);
+    }
+    prev = q.done + ph * nm + j;
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's stores have completed
+    __syncthreads();
+  }
 }
 
 template <int TH>
@@ -1204,6 +1333,49 @@ hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, const int* pr
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+int qtile_rows(int m, int rb) {
+  if (!plan_valid(m, rb)) return 0;
+  const int th = m * rb / ACC_TILE_W;
+  return th >= 2 ? th : 0;
+}
+
+__global__ void clear_i32_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+hipError_t clear_i32(int* p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(clear_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+template <int M, int RB>
+static hipError_t launch_queue_t(const QueueArgs& q, int n_cu, hipStream_t s) {
+  if constexpr (M * RB / ACC_TILE_W < 2) {
+    return hipErrorInvalidValue;
+  } else {
+    const size_t lds = lds_bytes_m<M, RB>();
+    hipError_t e = hipFuncSetAttribute((const void*)queue_kernel<M, RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, queue_kernel<M, RB>, M * RB, lds);
+    if (e != hipSuccess) return e;
+    const int grid = std::max(1, std::min(q.total, std::max(1, per_cu) * n_cu));
+    hipLaunchKernelGGL((queue_kernel<M, RB>), dim3(grid), dim3(M * RB), lds, s, q);
+    return hipGetLastError();
+  }
+}
+
+hipError_t launch_queue(int m, int rb, const QueueArgs& q, int n_cu, hipStream_t s) {
+  if (q.total <= 0) return hipSuccess;
+#define MG_LQ(MM, RR) if (m == MM && rb == RR) return launch_queue_t<MM, RR>(q, n_cu, s);
+  MG_FOR_EACH_PLAN(MG_LQ)
+#undef MG_LQ
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_accumulate(const AccumArgs& a, int th, int n_tiles, hipStream_t s, hipEvent_t ev0,

@@ -25,6 +25,7 @@ UPDATE_PROBE = 0x1
 GRAPH = 0x2
 PHASE_RECYCLE = 0x4
 PROBE_ALTERNATE = 0x8
+PERSISTENT = 0x10
 W_F32, W_BF16 = 0, 1
 COARSE_C64, COARSE_C128, COARSE_LOGPOLAR = 0, 1, 2
 
