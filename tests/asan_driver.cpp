@@ -170,6 +170,14 @@ int main() {
   expect(magpie_run_epochs_multi(both, 2, 2, batches, 7), MAGPIE_OK, "run_epochs_multi");
   expect(magpie_set_flags(c2, MAGPIE_PHASE_RECYCLE, 0.0), MAGPIE_OK, "set_flags c2");
   expect(magpie_run_epochs_multi(both, 2, 1, batches, 7), MAGPIE_ERR_UNSUPPORTED, "multi with recycling");
+  // the work-queue launch: mixed flags refused, then both contexts over 10 epochs (chunks
+  // 1 + 8 + 1), then one context alone through run_epochs
+  expect(magpie_set_flags(c2, MAGPIE_PERSISTENT, 0.0), MAGPIE_OK, "set_flags c2 persistent");
+  expect(magpie_run_epochs_multi(both, 2, 1, batches, 7), MAGPIE_ERR_INVALID_ARG, "multi with mixed persistent");
+  expect(magpie_set_flags(c1, MAGPIE_PERSISTENT, 0.0), MAGPIE_OK, "set_flags c1 persistent");
+  expect(magpie_run_epochs_multi(both, 2, 10, batches, 7), MAGPIE_OK, "run_epochs_multi queue");
+  expect(magpie_run_epochs(c2, 2, 5, 3, nullptr), MAGPIE_OK, "run_epochs queue");
+  expect(magpie_run_epochs(c2, 1, 5, 3, notperm.data()), MAGPIE_ERR_UNSUPPORTED, "queue with caller orders");
 
   // the 64-point plans (512- and 256-thread workgroups) with graphs and every flag
   {
@@ -187,6 +195,8 @@ int main() {
     expect(magpie_autotune(ctx64, 13, 1, &su, &au), MAGPIE_OK, "autotune m64");
     expect(magpie_set_tuning(ctx64, 4, 16), MAGPIE_OK, "set_tuning m64");
     expect(magpie_run_epochs(ctx64, 3, 13, 1, nullptr), MAGPIE_OK, "run_epochs m64 plan 4");
+    expect(magpie_set_flags(ctx64, MAGPIE_PERSISTENT, 0.0), MAGPIE_OK, "set_flags m64 persistent");
+    expect(magpie_run_epochs(ctx64, 2, 13, 1, nullptr), MAGPIE_OK, "run_epochs m64 plan 4 queue");
     expect(magpie_objective(ctx64, &phi, &stat), MAGPIE_OK, "objective m64");
     expect(magpie_get_object(ctx64, z64.data(), MAGPIE_C64, 0), MAGPIE_OK, "get_object m64");
     expect(magpie_destroy(ctx64), MAGPIE_OK, "destroy m64");
