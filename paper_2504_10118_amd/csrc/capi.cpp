@@ -1340,9 +1340,9 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     for (size_t g = 0; g < parts.size(); ++g) {
       parts[g].ths.assign(1, mg::qtile_rows(parts[g].m, parts[g].rb));
       qctr0[g] = n_ctr;
-      n_ctr += 2 * parts[g].members.size() + 1;
+      n_ctr += mg::queue_counter_ints((int)parts[g].members.size());
     }
-    ++n_ctr;
+    n_ctr += mg::QSLOT_STRIDE;   // the abort flag, on a line of its own
     if (c0->qctr_cap < n_ctr) {
       dev_free(c0->qctr);
       c0->qctr_cap = 0;
@@ -1365,7 +1365,7 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     if (const char* env = std::getenv("MAGPIE_QUEUE_WAIT_US")) us = std::max(0.0, std::atof(env));
     wait_ticks = (long long)(us * 1e-3 * khz);
   }
-  int* const q_abort = queue ? c0->qctr + (n_ctr - 1) : nullptr;
+  int* const q_abort = queue ? c0->qctr + (n_ctr - mg::QSLOT_STRIDE) : nullptr;
   std::vector<hipEvent_t> fork_ev(parts.size(), nullptr), join_ev(parts.size(), nullptr);
   for (size_t g = 0; g < parts.size() && !rc; ++g) {
     if (g == 0) {
@@ -1551,10 +1551,10 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
       q.n_members = (int)nm;
       q.total = gpre[q.n_groups];
       q.done = c0->qctr + qctr0[g];
-      q.head = q.done + 2 * nm;
+      q.head = q.done + (size_t)2 * nm * mg::QSLOTS * mg::QSLOT_STRIDE;
       q.abort = q_abort;
       q.wait_ticks = wait_ticks;
-      e = mg::clear_i32(q.done, (int)(2 * nm + 1), p.stream);
+      e = mg::clear_i32(q.done, (int)mg::queue_counter_ints((int)nm), p.stream);
       if (e == hipSuccess) e = mg::launch_queue(p.m, p.rb, q, c0->n_cu, p.stream);
     }
     for (int r = 0; r < R && e == hipSuccess; ++r) {

@@ -118,13 +118,20 @@ hipError_t launch_accumulate_multi(int th, const AccumArgs* descs, const int* pr
 // of member j in round r, items gpre[g] .. gpre[g + 1] - 1.  A group's items wait
 // until done[j + n_members] (tiles finished, for steps) or done[j] (steps
 // finished, for tiles) reaches wait[g].  done, head: zero before the launch.
+// Each done counter is split into QSLOTS slots QSLOT_STRIDE ints apart (an item
+// adds to slot b mod QSLOTS, a wait sums the slots): device-scope atomics on one
+// address serialise, and a whole minibatch's items finish at about the same time.
+constexpr int QSLOTS = 16, QSLOT_STRIDE = 32;
+constexpr size_t queue_counter_ints(int n_members) {
+  return ((size_t)2 * n_members * QSLOTS + 1) * QSLOT_STRIDE;   // done slots, then head
+}
 struct QueueArgs {
   const StepArgs* sdesc;    // [rounds][n_members]
   const AccumArgs* adesc;   // [rounds][n_members], boxes at tile height qtile_rows(m, rb)
   const int* gpre;          // [n_groups + 1]
   const int* wait;          // [n_groups]
   int n_groups, n_members, total;
-  int* done;                // [2 n_members]
+  int* done;                // [2 n_members][QSLOTS] slots, QSLOT_STRIDE ints apart
   int* head;                // next item
   int* abort;               // set by a wait longer than wait_ticks (s_memrealtime ticks); stops the queue
   long long wait_ticks;

@@ -1249,12 +1249,18 @@ __global__ __launch_bounds__(M * RBv, queue_min_waves(M, RBv)) void queue_kernel
     const int gr = g / nm, j = g - gr * nm;
     const int r = gr >> 1, ph = gr & 1;   // ph 0: step item, 1: tile item
     if (tid == 0) {
-      const int* ctr = q.done + (ph == 0 ? nm : 0) + j;
+      const int* ctr = q.done + (size_t)((ph == 0 ? nm : 0) + j) * QSLOTS * QSLOT_STRIDE;
+      auto count = [&]() {
+        int c = 0;
+#pragma unroll
+        for (int sl = 0; sl < QSLOTS; ++sl) c += ld_agent(ctr + sl * QSLOT_STRIDE);
+        return c;
+      };
       const int need = q.wait[g];
       int ok = 1;
-      if (ld_agent(ctr) < need) {
+      if (count() < need) {
         const long long t0 = (long long)wall_clock64();
-        while (ld_agent(ctr) < need) {
+        while (count() < need) {
           if (ld_agent(q.abort) || (long long)wall_clock64() - t0 > q.wait_ticks) {
             __hip_atomic_store(q.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ok = 0;
@@ -1276,7 +1282,7 @@ __global__ __launch_bounds__(M * RBv, queue_min_waves(M, RBv)) void queue_kernel
       const AccumArgs a = load_accum_args(q.adesc + (size_t)r * nm + j);
       accumulate_body<TH, true>(a, b);
     }
-    prev = q.done + ph * nm + j;
+    prev = q.done + ((size_t)(ph * nm + j) * QSLOTS + (b & (QSLOTS - 1))) * QSLOT_STRIDE;
     __builtin_amdgcn_s_waitcnt(0);   // this thread's stores have completed
     __syncthreads();
   }
