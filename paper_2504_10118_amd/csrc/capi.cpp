@@ -1326,6 +1326,37 @@ int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, co
     pp->members.push_back(i);
     if (std::find(pp->ths.begin(), pp->ths.end(), c->th) == pp->ths.end()) pp->ths.push_back(c->th);
   }
+  // A plan of 1024-thread workgroups (one per CU) is split into two partitions of
+  // about equal work (positions), so that one half's steps run while the other
+  // half accumulates: 64-reconstruction workload 9.08 -> 9.58 M patterns/s, its 24
+  // reconstructions with 128-point probes alone 4.84 -> 5.27 M.  (Splitting the
+  // 512-thread plan's partition was slower: 19.9 -> 17.3 M on its 40 alone.)
+  {
+    std::vector<Part> split;
+    for (auto& p : parts) {
+      if (p.m * p.rb < 1024 || p.members.size() < 2) {
+        split.push_back(p);
+        continue;
+      }
+      std::vector<int> order(p.members);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int x, int y) { return ctxs[x]->n_pos > ctxs[y]->n_pos; });
+      Part h[2] = {Part{p.m, p.rb, {}, {}}, Part{p.m, p.rb, {}, {}}};
+      long long w[2] = {0, 0};
+      for (int i : order) {
+        const int k = w[1] < w[0] ? 1 : 0;
+        h[k].members.push_back(i);
+        w[k] += ctxs[i]->n_pos;
+      }
+      for (auto& q : h) {
+        std::sort(q.members.begin(), q.members.end());
+        for (int i : q.members)
+          if (std::find(q.ths.begin(), q.ths.end(), ctxs[i]->th) == q.ths.end()) q.ths.push_back(ctxs[i]->th);
+        split.push_back(q);
+      }
+    }
+    parts.swap(split);
+  }
   std::vector<int> B(count), nb(count);
   for (int i = 0; i < count; ++i) {
     B[i] = std::min(batch[i], ctxs[i]->n_pos);
