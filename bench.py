@@ -464,6 +464,8 @@ def batched_summary(r, steps):
     return {"workload": r["workload"], "value": r["value"], "unit": "patterns/s", "ms_per_step": r["ms_per_step"],
             "steps": steps, "step_kernel_frac": (r["achieved"] / HBM_PEAK_GBS) if r["achieved"] else None,
             "step_launch_us": r["step_launch_us"], "accumulate_launch_us": r["acc_launch_us"],
+            "step_kernel_frac_note": "algorithmic bytes over the summed durations of the step launches, "
+                                     "which overlap across the concurrent plan partitions (understates)",
             "work_queue": r["queue"]}
 
 
