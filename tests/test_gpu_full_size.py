@@ -16,8 +16,8 @@ are the probe itself, whose far field no single-precision transform resolves
 (an independent complex64 computation of that step is off by ~4e-5); the kernels
 transform Q (z_k - 1) and add the probe's spectrum computed once in FP64, and the
 flat-start step is held to 1e-5 like every other.  Whole epoch (512 x 512, 7
-minibatches, flat start): FP32 rounding accumulates through 7 dependent steps,
-bounded at 2e-4; the objective of the oracle's object is compared at 1e-5.  Fifty
+dependent minibatches, flat start): held to 1e-5 as well; the objective of the
+oracle's object is compared at 1e-5.  Fifty
 epochs from the flat start with identical permutations: the objective (eq. 2.1) of
 the two trajectories agrees to 1e-4.
 """
@@ -159,7 +159,7 @@ def test_full_size_epoch_and_objective():
                            cfg.batch)
     rel = _rel(zg, zo, mask)
     print(f"epoch rel {rel:.2e}", flush=True)
-    assert rel <= 2e-4
+    assert rel <= 1e-5
     # the objective (eq. 2.1) over all 1600 positions at the oracle's object
     g.set_object(zo.astype(np.complex64))
     phi_g, _ = g.objective()
@@ -172,12 +172,12 @@ def test_full_size_epoch_and_objective():
 def test_full_size_objective_after_50_epochs():
     """512 x 512, 64 x 64 probe, 3 levels, minibatch 256, 1e4 photons: 50 epochs from the
     flat start with the same explicit permutations on both sides; the objective (eq. 2.1,
-    FP64 reduction) of the GPU's object and of the oracle's object agree to 1e-4, or to
-    1.5 times the spread of the oracle's own objective after 50 epochs when its flat
-    start is perturbed at the FP32 rounding level (1e-7), whichever is larger: the
-    stochastic iteration amplifies any rounding-level difference (those oracle runs end
-    2-3 % apart in the object and ~1e-4 apart in the objective), so no single-precision
-    trajectory can be held closer than that band."""
+    FP64 reduction) of the GPU's object and of the oracle's object agree to 1e-4.  The
+    GPU path is deterministic (fixed-order sums), so the figure is a property of the
+    build.  For context the test also prints the spread of the oracle's own objective
+    when its flat start is perturbed at the FP32 rounding level (1e-7): the stochastic
+    iteration amplifies any rounding-level difference (those runs end 2-3 % apart in the
+    object and up to ~2e-4 apart in the objective)."""
     import multiprocessing as mp
     from oracle_runs import objective_after_epochs
     cfg, Q32, offs, sd32, _, mask = _problem("512x512")
@@ -198,7 +198,6 @@ def test_full_size_objective_after_50_epochs():
     band = max(abs(p - phi_o) for p, _ in res[1:])
     phi_0 = oracle.objective(np.ones((cfg.n, cfg.n)), Q, offs, sd)
     drift = _rel(zg, zo, mask)
-    tol = max(1e-4 * phi_o, 1.5 * band)
     print(f"50 epochs: phi gpu {phi_g:.8e} oracle {phi_o:.8e} (start {phi_0:.4e}), rel {abs(phi_g - phi_o) / phi_o:.2e}, "
           f"object drift {drift:.2e}; oracle spread under 1e-7 start perturbations {band / phi_o:.2e}", flush=True)
-    assert abs(phi_g - phi_o) <= tol
+    assert abs(phi_g - phi_o) <= 1e-4 * phi_o
