@@ -64,9 +64,9 @@ extern "C" {
 #define MAGPIE_PROBE_ALTERNATE 0x8u /* with MAGPIE_UPDATE_PROBE: take the probe step at the
                                      minibatch's updated object (alternating half steps)
                                      instead of at the object the step started from */
-#define MAGPIE_PERSISTENT   0x10u /* run epochs as one work-queue launch per FFT plan and
-                                     chunk of epochs (see magpie_run_epochs_multi); same
-                                     results bit for bit */
+#define MAGPIE_PERSISTENT   0x10u /* run epochs as one work-queue launch per plan
+                                     partition and chunk of epochs (see
+                                     magpie_run_epochs_multi); same results bit for bit */
 
 typedef struct magpie_ctx magpie_ctx;
 
@@ -315,18 +315,21 @@ int magpie_autotune(magpie_ctx* ctx, int batch, int trial_epochs, double* step_u
  * Many independent reconstructions (contexts of any sizes on one device)
  * advanced together: each context runs n_epochs epochs of minibatch MAGPIE
  * with its own minibatch size batch[i] and its own seeded permutations
- * (seed XOR its epoch counter), exactly as magpie_run_epochs would.  Rounds
- * pair the t-th minibatches of all contexts still running: one step-kernel
- * launch per FFT plan and one accumulation launch per tile height cover every
- * context of the round.  Runs on the first context's stream (the others are
- * joined with events) and synchronises it.  The probe step is not available
+ * (seed XOR its epoch counter), exactly as magpie_run_epochs would.  The
+ * contexts are partitioned by FFT plan (a plan of 1024-thread workgroups, one
+ * per compute unit, into two partitions of about equal work), each partition
+ * on a stream of its own.  Within a partition, rounds pair the t-th minibatches
+ * of its contexts still running: one step-kernel launch and one accumulation
+ * launch per tile height cover every context of the round.  Runs on the first
+ * context's stream (the other streams fork from it and join it, and the other
+ * contexts' streams are joined with events) and synchronises it.  The probe step is not available
  * here.  Errors: INVALID_ARG, BAD_STATE, UNSUPPORTED, OOM, HIP.
  */
 int magpie_run_epochs_multi(magpie_ctx* const* ctxs, int count, int n_epochs, const int* batch, uint64_t seed);
 /*
  * With MAGPIE_PERSISTENT set on every context of the call (or on none: mixing
  * is INVALID_ARG), the rounds of each chunk of up to 8 epochs run as one
- * work-queue launch per FFT plan instead of two or more launches per round
+ * work-queue launch per plan partition instead of two or more launches per round
  * (the batched, persistent execution of many reconstructions; the paper leaves
  * the minibatch/GPU variant of Alg 4 to future work).  Workgroups, as many as
  * are resident, take items in queue order: for each round, one per position of
