@@ -312,6 +312,27 @@ int magpie_get_tuning(magpie_ctx* ctx, int* threads_per_transform, int* tile_row
 int magpie_autotune(magpie_ctx* ctx, int batch, int trial_epochs, double* step_us, double* accum_us);
 
 /*
+ * Minibatch autotuner.  The minibatch size B is a parameter of the method (the
+ * paper's Alg 4 visits positions one at a time; a minibatch combines B surrogate
+ * minimisations, and its Conclusion leaves the minibatch variant open): a larger
+ * B makes an epoch cheaper on the GPU but each epoch reduces the objective less.
+ * For each of the n_candidates sizes, from the object and epoch counter the call
+ * started with, runs trial_epochs epochs of minibatch MAGPIE (the library's
+ * permutations for a fixed seed and the context's epoch counter, the same for
+ * every candidate) and measures the wall time of those epochs
+ * (records drawn on the host included, objective passes excluded) and the
+ * objective (eq. 2.1) before and after; a candidate's rate is the objective's
+ * decrease per second.  Keeps the candidate with the largest rate in *best_batch,
+ * restores the object and the epoch counter, and writes the rates (nullable,
+ * n_candidates doubles, objective units per second; negative where the objective
+ * rose).  Positions beyond N count as N.  Synchronises.
+ * Errors: BAD_STATE, INVALID_ARG (no candidates, a candidate < 1, trial_epochs < 1,
+ * NULL best_batch), NUMERIC (non-finite objective), OOM, HIP.
+ */
+int magpie_autotune_batch(magpie_ctx* ctx, const int32_t* candidates, int n_candidates, int trial_epochs,
+                          int32_t* best_batch, double* rates);
+
+/*
  * Many independent reconstructions (contexts of any sizes on one device)
  * advanced together: each context runs n_epochs epochs of minibatch MAGPIE
  * with its own minibatch size batch[i] and its own seeded permutations

@@ -1,5 +1,6 @@
 // Host runtime of the MAGPIE C ABI (include/magpie.h): context, device
 // buffers, input validation, epoch scheduling and kernel launches.
+#include <chrono>
 #include <mutex>
 
 #include "context.h"
@@ -1235,6 +1236,69 @@ int magpie_autotune(magpie_ctx* c, int batch, int trial_epochs, double* step_us,
   if (e != hipSuccess) return fail(MAGPIE_ERR_HIP, "autotune restore failed");
   if (step_us) *step_us = best_step;
   if (accum_us) *accum_us = best_acc;
+  return MAGPIE_OK;
+}
+
+int magpie_autotune_batch(magpie_ctx* c, const int32_t* candidates, int n_candidates, int trial_epochs,
+                          int32_t* best_batch, double* rates) {
+  if (!c) return fail(MAGPIE_ERR_INVALID_ARG, "NULL context");
+  if (!candidates || n_candidates < 1 || !best_batch || trial_epochs < 1)
+    return fail(MAGPIE_ERR_INVALID_ARG, "candidates, n_candidates >= 1, trial_epochs >= 1 and best_batch required");
+  for (int i = 0; i < n_candidates; ++i)
+    if (candidates[i] < 1) return fail(MAGPIE_ERR_INVALID_ARG, "minibatch candidates must be >= 1");
+  if (!c->has_probe || !c->has_pos || !c->has_data)
+    return fail(MAGPIE_ERR_BAD_STATE, "set probe, positions and intensities first");
+  int rc = set_dev(c);
+  if (rc) return rc;
+  // buffers for the largest candidate first, so that no trial allocates inside its timing
+  int bmax = 1;
+  for (int i = 0; i < n_candidates; ++i) bmax = std::max(bmax, candidates[i]);
+  rc = ensure_epoch_buffers(c, trial_epochs, bmax, 16);
+  if (!rc) rc = ensure_pinned(c, 8);
+  if (rc) return rc;
+  const size_t nz = (size_t)c->nr * c->nc;
+  float2* zsave = nullptr;
+  rc = dev_alloc(&zsave, nz);
+  if (rc) return rc;
+  const uint64_t ep = c->epoch_index;
+  const bool timing = c->timing;
+  c->timing = false;
+  hipError_t e = hipMemcpyAsync(zsave, c->z, nz * sizeof(float2), hipMemcpyDeviceToDevice, c->stream);
+  double phi0 = 0.0;
+  if (e != hipSuccess) rc = fail(MAGPIE_ERR_HIP, "autotune_batch save failed");
+  if (!rc) rc = magpie_objective(c, &phi0, nullptr);
+  double best_rate = -HUGE_VAL;
+  int best = candidates[0];
+  for (int i = 0; i < n_candidates && !rc; ++i) {
+    e = hipMemcpyAsync(c->z, zsave, nz * sizeof(float2), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      rc = fail(MAGPIE_ERR_HIP, "autotune_batch restore failed");
+      break;
+    }
+    c->epoch_index = ep;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = magpie_run_epochs(c, trial_epochs, candidates[i], 0x5eedull, nullptr);
+    if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(MAGPIE_ERR_HIP, "autotune_batch run failed");
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    double phi1 = 0.0;
+    if (!rc) rc = magpie_objective(c, &phi1, nullptr);
+    if (rc) break;
+    const double rate = (phi0 - phi1) / std::max(secs, 1e-9);
+    if (rates) rates[i] = rate;
+    if (rate > best_rate) {
+      best_rate = rate;
+      best = candidates[i];
+    }
+  }
+  c->timing = timing;
+  e = hipMemcpyAsync(c->z, zsave, nz * sizeof(float2), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(zsave);
+  c->epoch_index = ep;
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(MAGPIE_ERR_HIP, "autotune_batch restore failed");
+  *best_batch = best;
   return MAGPIE_OK;
 }
 

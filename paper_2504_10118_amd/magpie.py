@@ -69,6 +69,7 @@ def _bind(lib):
         "magpie_set_tuning": (i, [vp, i, i]),
         "magpie_get_tuning": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "magpie_autotune": (i, [vp, i, i, ctypes.POINTER(d), ctypes.POINTER(d)]),
+        "magpie_autotune_batch": (i, [vp, vp, i, i, ctypes.POINTER(ctypes.c_int32), vp]),
         "magpie_run_epochs_multi": (i, [ctypes.POINTER(vp), i, i, ctypes.POINTER(i), u64]),
         "magpie_get_timing": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
@@ -320,6 +321,16 @@ class Magpie:
         _check(self.lib.magpie_autotune(self._h, batch, trial_epochs, ctypes.byref(su), ctypes.byref(au)))
         rb, th = self.get_tuning()
         return rb, th, su.value, au.value
+
+    def autotune_batch(self, candidates, trial_epochs: int = 3):
+        """Pick the minibatch size with the fastest objective decrease from the current state;
+        returns (best, rates) with rates[i] the objective decrease per second of candidates[i]."""
+        c = np.ascontiguousarray(candidates, dtype=np.int32)
+        rates = np.zeros(len(c), dtype=np.float64)
+        best = ctypes.c_int32()
+        _check(self.lib.magpie_autotune_batch(self._h, c.ctypes.data_as(ctypes.c_void_p), len(c), trial_epochs,
+                                              ctypes.byref(best), rates.ctypes.data_as(ctypes.c_void_p)))
+        return int(best.value), rates
 
     # -- outputs
     def get_object(self, out=None, dtype=np.complex64):

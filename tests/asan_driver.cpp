@@ -193,6 +193,12 @@ int main() {
     expect(magpie_run_epochs(ctx64, 1, 49, 1, nullptr), MAGPIE_OK, "run_epochs m64 one minibatch");
     expect(magpie_set_flags(ctx64, MAGPIE_GRAPH | MAGPIE_PHASE_RECYCLE, 0.0), MAGPIE_OK, "set_flags m64 graph");
     expect(magpie_autotune(ctx64, 13, 1, &su, &au), MAGPIE_OK, "autotune m64");
+    const int32_t cands[3] = {5, 13, 1000};
+    int32_t bb = 0;
+    double rr[3] = {0.0, 0.0, 0.0};
+    expect(magpie_autotune_batch(ctx64, cands, 3, 1, &bb, rr), MAGPIE_OK, "autotune_batch m64");
+    expect(magpie_autotune_batch(ctx64, cands, 0, 1, &bb, rr), MAGPIE_ERR_INVALID_ARG, "autotune_batch none");
+    expect(magpie_autotune_batch(ctx64, cands, 3, 1, nullptr, rr), MAGPIE_ERR_INVALID_ARG, "autotune_batch NULL");
     expect(magpie_set_tuning(ctx64, 4, 16), MAGPIE_OK, "set_tuning m64");
     expect(magpie_run_epochs(ctx64, 3, 13, 1, nullptr), MAGPIE_OK, "run_epochs m64 plan 4");
     expect(magpie_set_flags(ctx64, MAGPIE_PERSISTENT, 0.0), MAGPIE_OK, "set_flags m64 persistent");

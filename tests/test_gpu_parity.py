@@ -521,6 +521,39 @@ def test_autotune_keeps_state():
     g.close()
 
 
+def test_autotune_batch_keeps_state_and_ranks():
+    """The minibatch autotuner returns the candidate of largest rate (objective decrease
+    per second) among its candidates, reports every rate (each trial lowers the objective
+    from this start), and leaves the object and the epoch counter as they were: a run
+    after it equals the same run without it, bit for bit."""
+    from paper_2504_10118_amd import MagpieError
+    rng = np.random.default_rng(28)
+    c = Case(rng, 160, 160, 32, 8, noise=0.05)
+    g = c.gpu(3, 0.5)
+    g.run_epochs(1, 10, seed=1)
+    z_before = g.get_object()
+    ep = g.epoch_index
+    cands = [4, 16, 64, 1000]
+    best, rates = g.autotune_batch(cands, trial_epochs=2)
+    _print("autotune_batch best", best, "rates", rates)
+    assert best == cands[int(np.argmax(rates))]
+    assert np.all(rates > 0)
+    assert np.array_equal(g.get_object().view(np.uint64), z_before.view(np.uint64))
+    assert g.epoch_index == ep
+    g.run_epochs(2, 16, seed=3)
+    after = g.get_object()
+    with pytest.raises(MagpieError, match="INVALID_ARG"):
+        g.autotune_batch([16, 0])
+    with pytest.raises(MagpieError, match="INVALID_ARG"):
+        g.autotune_batch([16], trial_epochs=0)
+    g.close()
+    g = c.gpu(3, 0.5)
+    g.run_epochs(1, 10, seed=1)
+    g.run_epochs(2, 16, seed=3)
+    assert np.array_equal(after.view(np.uint64), g.get_object().view(np.uint64))
+    g.close()
+
+
 def test_multi_context_equals_separate_runs():
     """Reconstructions of different sizes (probes 16 to 128) advanced together equal their
     separate runs bit for bit, with three accumulation tile-height groups (8, 16, 32)."""
