@@ -1,7 +1,7 @@
 """GPU: the work-queue launch of multi-reconstruction runs (flag MAGPIE_PERSISTENT).
 
 The queue takes the same steps and accumulations as the round-by-round launches in a
-different schedule (one launch per FFT plan and chunk of epochs; each item waits for
+different schedule (one launch per plan partition and chunk of epochs; each item waits for
 the items of its own reconstruction it depends on), so its results must equal theirs
 bit for bit; one epoch of each reconstruction is also checked against the FP64 oracle
 (masked and element-wise, 1e-5).  The failure path (a wait longer than its bound) is
@@ -50,9 +50,10 @@ def _run(cases, levels, batches, epochs, seed, queue, tiles=None):
 
 
 def test_queue_equals_rounds_bitwise():
-    """Six reconstructions (probes 16 to 128: four plan partitions on concurrent streams),
-    ten epochs (chunks of 1, 8 and 1 epochs, so both descriptor slots are reused), tile
-    heights 8, 16 and 32 on the round-by-round side: the queue's objects are identical."""
+    """Six reconstructions (probes 16 to 128: five plan partitions on concurrent streams,
+    the two 128-point reconstructions' plan split in two), ten epochs (chunks of 1, 8 and 1
+    epochs, so both descriptor slots are reused), tile heights 8, 16 and 32 on the
+    round-by-round side: the queue's objects are identical."""
     cases, levels, batches = _cases(91)
     ref, _ = _run(cases, levels, batches, 10, 55, queue=False, tiles=[None, 16, 32, None, 16, None])
     got, eps = _run(cases, levels, batches, 10, 55, queue=True)
