@@ -62,6 +62,29 @@ def test_one_epoch_parity(m, levels, batch):
     assert relx <= 1e-5
 
 
+@pytest.mark.parametrize("m,levels", [(16, 2), (32, 3), (64, 3), (128, 4)])
+@pytest.mark.parametrize("probe", ["synthetic", "random"])
+def test_flat_start_epoch_parity(m, levels, probe):
+    """One epoch from the flat object (every window constant: the exit waves are the
+    probe itself, whose spectrum the step adds from its FP64 copy) with the symmetric
+    synthetic probe (exact spectral zeros, which both sides must leave at theta(0)) and
+    with a complex Gaussian probe (no zeros): masked and element-wise within 1e-5."""
+    rng = np.random.default_rng(7000 + m + (probe == "random"))
+    c = Case(rng, 2 * m + 9, 2 * m + 5, m, max(2, m // 3), probe=probe, noise=0.05)
+    order = rng.permutation(c.n_pos).astype(np.int32)
+    B = max(1, c.n_pos // 3)
+    flat = np.ones((c.n_rows, c.n_cols), dtype=np.complex128)
+    g = c.gpu(levels, 0.5)
+    g.set_object(flat.astype(np.complex64))
+    g.run_epochs(1, B, order=order[None, :])
+    zg = g.get_object().astype(np.complex128)
+    g.close()
+    zo = c.oracle_run(levels, 0.5, [order], B, z0=flat)
+    rel, relx = c.rel(zg, zo), c.rel_max(zg, zo)
+    _print("flat start m", m, "L", levels, probe, "N", c.n_pos, "B", B, "rel", rel, "element-wise", relx)
+    assert rel <= 1e-5 and relx <= 1e-5
+
+
 def test_tiny_amplitudes_modulus_replacement():
     """Object and data scaled by 1e-21: many |F(Q z_k)|^2 fall below the smallest
     normal float (1.2e-38) or underflow, which the modulus replacement (Definition 2.1)
