@@ -6,6 +6,8 @@ oracle's driver with its phase store.
   all-zero exit wave, and their revised exit waves come from the phases stored at their
   previous visit (the oracle's phase store, carried the same way); without the flag the
   same epoch differs from that by far more than the tolerance;
+* from the flat object with the symmetric probe the exit waves' spectra vanish exactly on
+  whole lines at every visit, and the store is consulted there on both sides;
 * switching the flag off and on starts the store over (theta = 0), the autotuner's trial
   epochs leave it alone, and multi-context runs refuse flagged contexts.
 """
@@ -51,6 +53,33 @@ def test_recycling_without_zeros_matches_plain_oracle(m, levels):
     rel = c.rel(zg, zo)
     print("recycle, generic data, m", m, "rel", rel, flush=True)
     assert rel <= TOL
+
+
+@pytest.mark.parametrize("m,levels", [(32, 3), (64, 3)])
+def test_recycling_from_the_flat_object(m, levels):
+    """Two epochs, each from the flat object, with the symmetric synthetic probe: every
+    exit wave is the probe itself, whose spectrum vanishes exactly on whole lines, so the
+    phase store is consulted at those pixels on every visit (and keeps its initial
+    theta = 0 there); the flagged GPU epochs equal the oracle's driver with its store."""
+    from paper_2504_10118_amd import PHASE_RECYCLE
+    rng = np.random.default_rng(340 + m)
+    c = Case(rng, 2 * m + 9, 2 * m + 7, m, max(2, m // 3), noise=0.05)
+    flat = np.ones((c.n_rows, c.n_cols), dtype=np.complex128)
+    orders = [rng.permutation(c.n_pos).astype(np.int32) for _ in range(2)]
+    B = max(1, c.n_pos // 3)
+    u = oracle.u_rpie(c.Q, 0.5)
+    ph = oracle.initial_phases(c.n_pos, c.m)
+    oracle.run_epochs(flat, c.Q, c.offs, c.sd, u, levels, [orders[0]], B, phases=ph)
+    zo = oracle.run_epochs(flat, c.Q, c.offs, c.sd, u, levels, [orders[1]], B, phases=ph)
+    g = _gpu(c, levels, 0.5, PHASE_RECYCLE)
+    for o in orders:
+        g.set_object(flat.astype(np.complex64))
+        g.run_epochs(1, B, order=o[None])
+    zg = g.get_object().astype(np.complex128)
+    g.close()
+    rel, relx = c.rel(zg, zo), c.rel_max(zg, zo)
+    print("recycle from flat, m", m, "rel", rel, "element-wise", relx, flush=True)
+    assert rel <= TOL and relx <= TOL
 
 
 @pytest.mark.parametrize("levels,batch", [(1, 210), (2, 210), (3, 64), (4, 105)])
