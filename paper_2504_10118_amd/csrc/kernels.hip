@@ -313,51 +313,115 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     }
   }
   // restriction down: g^_l = I(V_{l-1} g^_{l-1}); coarsest: e = -r g^
-  int lv_prev = 0, Mp = M1;
-  for (int l = 2; l < L; ++l) {
-    const int Ml = Mp >> 1;
-    const int off_prev = off_of(l - 1), sp = pitch_of(l - 1), off_cur = off_of(l);
-    const int lv_cur = lv_prev + 3 * Mp * Mp;
-    const double* Vp = a.lvl + lv_prev;
-    const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
-    double vq[E2][4], rq[E2];
-#pragma unroll
-    for (int i = 0; i < E2; ++i) {
-      const int e = tid + i * TPB;
-      rq[i] = 0.0;
-      vq[i][0] = vq[i][1] = vq[i][2] = vq[i][3] = 0.0;
-      if (e < Ml * Ml) {
-        const int Y = e / Ml, X = e % Ml;
-        const int i0 = (2 * Y) * Mp + 2 * X, i1 = i0 + Mp;
-        vq[i][0] = Vp[i0];
-        vq[i][1] = Vp[i0 + 1];
-        vq[i][2] = Vp[i1];
-        vq[i][3] = Vp[i1 + 1];
-        if (l == L - 1) rq[i] = rl[e];
-      }
-    }
+  int lv_prev = 0, Mp = M1, l_up = L - 2;
+  // Levels 2 .. L-1 inside the waves (L = 3 or 4): wave w holds the 8 x 8 block
+  // (w % BW, w / BW) of level-2 bins, its lane bits (x0, y0, x1, y1, x2, y2) the bin
+  // inside the block, so the 2 x 2 bins of level l + 1 are the lanes that differ in
+  // bits 2(l - 2) and 2(l - 2) + 1: restriction is two cross-lane sums, prolongation
+  // is free, and level 3 takes no barrier and no LDS (in the same pairing and order
+  // of the sums as through LDS).  Level 2's e_2 goes to its grid in C for the
+  // level-1 prolongation.  (The same block holds levels 4 and 5 as well; carrying
+  // them in registers spilled at the 128-register cap, so deeper hierarchies keep
+  // the path through LDS.)
+  constexpr int M2 = M / 4, BW = M2 / 8;
+  constexpr bool WAVE_OK = (M2 >= 8) && (BW * BW * 64 <= TPB);
+  if (WAVE_OK && (L == 3 || L == 4)) {
+    const int wv = tid >> 6, lane = tid & 63;
+    const bool act = wv < BW * BW;
+    const int X2 = (act ? (wv % BW) * 8 : 0) + ((lane & 1) | ((lane >> 1) & 2) | ((lane >> 2) & 4));
+    const int Y2 = (act ? (wv / BW) * 8 : 0) + (((lane >> 1) & 1) | ((lane >> 2) & 2) | ((lane >> 3) & 4));
+    auto lv_of = [&](int l) {   // offset of level l's (V, rho, r) block in a.lvl
+      int o = 0;
+      for (int j = 1; j < l; ++j) o += 3 * (M >> j) * (M >> j);
+      return o;
+    };
+    auto at = [&](int l, int which) {   // V (0), rho (1) or r (2) of level l at this lane's bin
+      const int Ml = M >> l, sh = l - 2;
+      return a.lvl[lv_of(l) + which * Ml * Ml + (Y2 >> sh) * Ml + (X2 >> sh)];
+    };
+    // constants of the upward pass, loaded before the barrier that makes level 1 visible
+    double v1[4];
+    const double* V1 = a.lvl;
+    const int i0 = (2 * Y2) * M1 + 2 * X2, i1 = i0 + M1;
+    v1[0] = V1[i0];
+    v1[1] = V1[i0 + 1];
+    v1[2] = V1[i1];
+    v1[3] = V1[i1 + 1];
+    const double v2 = (L == 4) ? at(2, 0) : 0.0;
+    const double rc = at(L - 1, 2);
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < E2; ++i) {
-      const int e = tid + i * TPB;
-      if (e < Ml * Ml) {
-        const int Y = e / Ml, X = e % Ml;
-        const int c0 = off_prev + (2 * Y) * sp + 2 * X, c1 = c0 + sp;
-        double2 s;
-        s.x = 0.25 * ((vq[i][0] * C[c0].x + vq[i][1] * C[c0 + 1].x) + (vq[i][2] * C[c1].x + vq[i][3] * C[c1 + 1].x));
-        s.y = 0.25 * ((vq[i][0] * C[c0].y + vq[i][1] * C[c0 + 1].y) + (vq[i][2] * C[c1].y + vq[i][3] * C[c1 + 1].y));
-        if (l == L - 1) {
-          s.x = -rq[i] * s.x;
-          s.y = -rq[i] * s.y;
-        }
-        C[off_cur + e] = s;
+    if (act) {
+      // the downward pass's constants (L = 4), in flight during the upward one
+      const double rh2 = (L == 4) ? at(2, 1) : 0.0, rr2 = (L == 4) ? at(2, 2) : 0.0;
+      const int c0 = (2 * Y2) * S1 + 2 * X2, c1 = c0 + S1;
+      double2 g2;
+      g2.x = 0.25 * ((v1[0] * C[c0].x + v1[1] * C[c0 + 1].x) + (v1[2] * C[c1].x + v1[3] * C[c1 + 1].x));
+      g2.y = 0.25 * ((v1[0] * C[c0].y + v1[1] * C[c0 + 1].y) + (v1[2] * C[c1].y + v1[3] * C[c1 + 1].y));
+      double2 e;
+      if (L == 4) {
+        // g^_3 = I(V_2 g^_2): the 2 x 2 bins of level 3 are the lanes differing in bits 0 and 1
+        const double2 t = make_double2(v2 * g2.x, v2 * g2.y);
+        const double2 o = xor_lane<1>(t);
+        const double2 sx = make_double2(t.x + o.x, t.y + o.y);
+        const double2 q = xor_lane<2>(sx);
+        const double2 g3 = make_double2(0.25 * (sx.x + q.x), 0.25 * (sx.y + q.y));
+        // coarsest e_3 = -r_3 g^_3; then e_2 = rho_2 P(e_3) - r_2 g^_2
+        const double2 e3 = make_double2(-rc * g3.x, -rc * g3.y);
+        e = make_double2(rh2 * e3.x - rr2 * g2.x, rh2 * e3.y - rr2 * g2.y);
+      } else {
+        e = make_double2(-rc * g2.x, -rc * g2.y);   // level 2 is the coarsest
       }
+      C[off_of(2) + Y2 * pitch_of(2) + X2] = e;
     }
-    lv_prev = lv_cur;
-    Mp = Ml;
+    lv_prev = 3 * M1 * M1;   // the level-1 prolongation below starts from level 2
+    Mp = M2;
+    l_up = 1;
+  } else {
+    for (int l = 2; l < L; ++l) {
+      const int Ml = Mp >> 1;
+      const int off_prev = off_of(l - 1), sp = pitch_of(l - 1), off_cur = off_of(l);
+      const int lv_cur = lv_prev + 3 * Mp * Mp;
+      const double* Vp = a.lvl + lv_prev;
+      const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
+      double vq[E2][4], rq[E2];
+  #pragma unroll
+      for (int i = 0; i < E2; ++i) {
+        const int e = tid + i * TPB;
+        rq[i] = 0.0;
+        vq[i][0] = vq[i][1] = vq[i][2] = vq[i][3] = 0.0;
+        if (e < Ml * Ml) {
+          const int Y = e / Ml, X = e % Ml;
+          const int i0 = (2 * Y) * Mp + 2 * X, i1 = i0 + Mp;
+          vq[i][0] = Vp[i0];
+          vq[i][1] = Vp[i0 + 1];
+          vq[i][2] = Vp[i1];
+          vq[i][3] = Vp[i1 + 1];
+          if (l == L - 1) rq[i] = rl[e];
+        }
+      }
+      __syncthreads();
+  #pragma unroll
+      for (int i = 0; i < E2; ++i) {
+        const int e = tid + i * TPB;
+        if (e < Ml * Ml) {
+          const int Y = e / Ml, X = e % Ml;
+          const int c0 = off_prev + (2 * Y) * sp + 2 * X, c1 = c0 + sp;
+          double2 s;
+          s.x = 0.25 * ((vq[i][0] * C[c0].x + vq[i][1] * C[c0 + 1].x) + (vq[i][2] * C[c1].x + vq[i][3] * C[c1 + 1].x));
+          s.y = 0.25 * ((vq[i][0] * C[c0].y + vq[i][1] * C[c0 + 1].y) + (vq[i][2] * C[c1].y + vq[i][3] * C[c1 + 1].y));
+          if (l == L - 1) {
+            s.x = -rq[i] * s.x;
+            s.y = -rq[i] * s.y;
+          }
+          C[off_cur + e] = s;
+        }
+      }
+      lv_prev = lv_cur;
+      Mp = Ml;
+    }
   }
   // prolongation up: e_l = rho_l P(e_{l+1}) - r_l g^_l for l = L-2 .. 1
-  for (int l = L - 2; l >= 1; --l) {
+  for (int l = l_up; l >= 1; --l) {
     const int Ml = Mp << 1;
     const int off_prev = off_of(l + 1), sp = pitch_of(l + 1), off_cur = off_of(l), sc = pitch_of(l);
     const int lv_cur = lv_prev - 3 * Ml * Ml;
