@@ -351,12 +351,18 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     const double rc = at(L - 1, 2);
     __syncthreads();
     if (act) {
-      // the downward pass's constants (L = 4), in flight during the upward one
+      // the downward pass's constants (level 2 when L = 4, and level 1 of this bin's four
+      // children), in flight during the upward one
       const double rh2 = (L == 4) ? at(2, 1) : 0.0, rr2 = (L == 4) ? at(2, 2) : 0.0;
+      const double* rho1 = a.lvl + M1 * M1;
+      const double* r1 = a.lvl + 2 * M1 * M1;
+      const double rh1[4] = {rho1[i0], rho1[i0 + 1], rho1[i1], rho1[i1 + 1]};
+      const double rr1[4] = {r1[i0], r1[i0 + 1], r1[i1], r1[i1 + 1]};
       const int c0 = (2 * Y2) * S1 + 2 * X2, c1 = c0 + S1;
+      const double2 ch[4] = {C[c0], C[c0 + 1], C[c1], C[c1 + 1]};   // g^_1 of the children
       double2 g2;
-      g2.x = 0.25 * ((v1[0] * C[c0].x + v1[1] * C[c0 + 1].x) + (v1[2] * C[c1].x + v1[3] * C[c1 + 1].x));
-      g2.y = 0.25 * ((v1[0] * C[c0].y + v1[1] * C[c0 + 1].y) + (v1[2] * C[c1].y + v1[3] * C[c1 + 1].y));
+      g2.x = 0.25 * ((v1[0] * ch[0].x + v1[1] * ch[1].x) + (v1[2] * ch[2].x + v1[3] * ch[3].x));
+      g2.y = 0.25 * ((v1[0] * ch[0].y + v1[1] * ch[1].y) + (v1[2] * ch[2].y + v1[3] * ch[3].y));
       double2 e;
       if (L == 4) {
         // g^_3 = I(V_2 g^_2): the 2 x 2 bins of level 3 are the lanes differing in bits 0 and 1
@@ -371,11 +377,14 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
       } else {
         e = make_double2(-rc * g2.x, -rc * g2.y);   // level 2 is the coarsest
       }
-      C[off_of(2) + Y2 * pitch_of(2) + X2] = e;
+      // level 1 of the four children: e_1 = rho_1 P(e_2) - r_1 g^_1 (each child is this
+      // lane's alone, so no barrier separates it from level 2)
+      const int cc[4] = {c0, c0 + 1, c1, c1 + 1};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        C[cc[q]] = make_double2(rh1[q] * e.x - rr1[q] * ch[q].x, rh1[q] * e.y - rr1[q] * ch[q].y);
     }
-    lv_prev = 3 * M1 * M1;   // the level-1 prolongation below starts from level 2
-    Mp = M2;
-    l_up = 1;
+    l_up = 0;   // every level done
   } else {
     for (int l = 2; l < L; ++l) {
       const int Ml = Mp >> 1;
