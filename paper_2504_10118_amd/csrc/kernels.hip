@@ -285,44 +285,17 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
     return o;
   };
   auto pitch_of = [&](int l) { return l == 1 ? S1 : (M >> l); };
-  // two grids: level 1 is the coarsest, e_1 = -r_1 g^_1 (r_1 follows V_1, rho_1)
-  const double* r1 = a.lvl + 2 * M1 * M1;
-  double r1v[E1];
-  double2 gh1[E1];
-#pragma unroll
-  for (int i = 0; i < E1; ++i) {
-    const int e = tid + i * TPB;
-    r1v[i] = (L == 2 && e < M1 * M1) ? r1[e] : 0.0;
-    gh1[i] = make_double2(0.0, 0.0);
-    if (e < M1 * M1) {
-      const int Y = e / M1, X = e % M1;
-      const float2 p0 = T[(2 * Y) * P + 2 * X], p1 = T[(2 * Y) * P + 2 * X + 1];
-      const float2 p2 = T[(2 * Y + 1) * P + 2 * X], p3 = T[(2 * Y + 1) * P + 2 * X + 1];
-      gh1[i].x = 0.25 * (((double)p0.x + p1.x) + ((double)p2.x + p3.x));
-      gh1[i].y = 0.25 * (((double)p0.y + p1.y) + ((double)p2.y + p3.y));
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < E1; ++i) {
-    const int e = tid + i * TPB;
-    if (e < M1 * M1) {
-      double2 w = gh1[i];
-      if (L == 2) w = make_double2(-r1v[i] * w.x, -r1v[i] * w.y);
-      C[(e / M1) * S1 + e % M1] = w;
-    }
-  }
-  // restriction down: g^_l = I(V_{l-1} g^_{l-1}); coarsest: e = -r g^
-  int lv_prev = 0, Mp = M1, l_up = L - 2;
-  // Levels 2 .. L-1 inside the waves (L = 3 or 4): wave w holds the 8 x 8 block
-  // (w % BW, w / BW) of level-2 bins, its lane bits (x0, y0, x1, y1, x2, y2) the bin
-  // inside the block, so the 2 x 2 bins of level l + 1 are the lanes that differ in
-  // bits 2(l - 2) and 2(l - 2) + 1: restriction is two cross-lane sums, prolongation
-  // is free, and level 3 takes no barrier and no LDS (in the same pairing and order
-  // of the sums as through LDS).  Level 2's e_2 goes to its grid in C for the
-  // level-1 prolongation.  (The same block holds levels 4 and 5 as well; carrying
-  // them in registers spilled at the 128-register cap, so deeper hierarchies keep
-  // the path through LDS.)
+  // Three or four grids: one lane per level-2 bin does the whole hierarchy for its
+  // bin.  Wave w holds the 8 x 8 block (w % BW, w / BW) of level-2 bins, its lane bits
+  // (x0, y0, x1, y1, x2, y2) give the bin inside the block, so a level-3 bin is the
+  // four lanes that differ in bits 0 and 1 (its restriction two cross-lane sums, its
+  // prolongation free).  The lane reads the 4 x 4 gradient pixels of its bin from the
+  // tile, forms g^_1 of its four level-1 children and g^_2, goes down to the coarsest
+  // level and back, and writes e_1 of its children: one barrier (every lane has read
+  // its pixels before C, which overlays the tile, is written) instead of one per level
+  // and direction.  Sums in the same pairing and order as the path through LDS below.
+  // (Levels 4 and 5 fit the same block, but carrying them in registers spilled at the
+  // 128-register cap: deeper hierarchies take the LDS path.)
   constexpr int M2 = M / 4, BW = M2 / 8;
   constexpr bool WAVE_OK = (M2 >= 8) && (BW * BW * 64 <= TPB);
   if (WAVE_OK && (L == 3 || L == 4)) {
@@ -335,57 +308,95 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
       for (int j = 1; j < l; ++j) o += 3 * (M >> j) * (M >> j);
       return o;
     };
-    auto at = [&](int l, int which) {   // V (0), rho (1) or r (2) of level l at this lane's bin
+    auto at = [&](int l, int which) {   // V (0), rho (1) or r (2) of level l >= 2 at this lane's bin
       const int Ml = M >> l, sh = l - 2;
       return a.lvl[lv_of(l) + which * Ml * Ml + (Y2 >> sh) * Ml + (X2 >> sh)];
     };
-    // constants of the upward pass, loaded before the barrier that makes level 1 visible
-    double v1[4];
-    const double* V1 = a.lvl;
+    // level-1 constants of the four children (i0, i0 + 1, i1, i1 + 1) and the coarse ones
     const int i0 = (2 * Y2) * M1 + 2 * X2, i1 = i0 + M1;
-    v1[0] = V1[i0];
-    v1[1] = V1[i0 + 1];
-    v1[2] = V1[i1];
-    v1[3] = V1[i1 + 1];
+    const int ci[4] = {i0, i0 + 1, i1, i1 + 1};
+    double v1[4], rh1[4], rr1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v1[q] = a.lvl[ci[q]];
+      rh1[q] = a.lvl[M1 * M1 + ci[q]];
+      rr1[q] = a.lvl[2 * M1 * M1 + ci[q]];
+    }
     const double v2 = (L == 4) ? at(2, 0) : 0.0;
+    const double rh2 = (L == 4) ? at(2, 1) : 0.0, rr2 = (L == 4) ? at(2, 2) : 0.0;
     const double rc = at(L - 1, 2);
-    __syncthreads();
+    double2 e1[4];
     if (act) {
-      // the downward pass's constants (level 2 when L = 4, and level 1 of this bin's four
-      // children), in flight during the upward one
-      const double rh2 = (L == 4) ? at(2, 1) : 0.0, rr2 = (L == 4) ? at(2, 2) : 0.0;
-      const double* rho1 = a.lvl + M1 * M1;
-      const double* r1 = a.lvl + 2 * M1 * M1;
-      const double rh1[4] = {rho1[i0], rho1[i0 + 1], rho1[i1], rho1[i1 + 1]};
-      const double rr1[4] = {r1[i0], r1[i0 + 1], r1[i1], r1[i1 + 1]};
-      const int c0 = (2 * Y2) * S1 + 2 * X2, c1 = c0 + S1;
-      const double2 ch[4] = {C[c0], C[c0 + 1], C[c1], C[c1 + 1]};   // g^_1 of the children
+      // g^_1 of the children from their 2 x 2 gradient pixels
+      double2 ch[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int Y = 2 * Y2 + (q >> 1), X = 2 * X2 + (q & 1);
+        const float2 p0 = T[(2 * Y) * P + 2 * X], p1 = T[(2 * Y) * P + 2 * X + 1];
+        const float2 p2 = T[(2 * Y + 1) * P + 2 * X], p3 = T[(2 * Y + 1) * P + 2 * X + 1];
+        ch[q].x = 0.25 * (((double)p0.x + p1.x) + ((double)p2.x + p3.x));
+        ch[q].y = 0.25 * (((double)p0.y + p1.y) + ((double)p2.y + p3.y));
+      }
       double2 g2;
       g2.x = 0.25 * ((v1[0] * ch[0].x + v1[1] * ch[1].x) + (v1[2] * ch[2].x + v1[3] * ch[3].x));
       g2.y = 0.25 * ((v1[0] * ch[0].y + v1[1] * ch[1].y) + (v1[2] * ch[2].y + v1[3] * ch[3].y));
       double2 e;
       if (L == 4) {
-        // g^_3 = I(V_2 g^_2): the 2 x 2 bins of level 3 are the lanes differing in bits 0 and 1
+        // g^_3 = I(V_2 g^_2) over the four lanes of the level-3 bin; coarsest e_3 = -r_3 g^_3;
+        // e_2 = rho_2 P(e_3) - r_2 g^_2
         const double2 t = make_double2(v2 * g2.x, v2 * g2.y);
         const double2 o = xor_lane<1>(t);
         const double2 sx = make_double2(t.x + o.x, t.y + o.y);
-        const double2 q = xor_lane<2>(sx);
-        const double2 g3 = make_double2(0.25 * (sx.x + q.x), 0.25 * (sx.y + q.y));
-        // coarsest e_3 = -r_3 g^_3; then e_2 = rho_2 P(e_3) - r_2 g^_2
+        const double2 w = xor_lane<2>(sx);
+        const double2 g3 = make_double2(0.25 * (sx.x + w.x), 0.25 * (sx.y + w.y));
         const double2 e3 = make_double2(-rc * g3.x, -rc * g3.y);
         e = make_double2(rh2 * e3.x - rr2 * g2.x, rh2 * e3.y - rr2 * g2.y);
       } else {
         e = make_double2(-rc * g2.x, -rc * g2.y);   // level 2 is the coarsest
       }
-      // level 1 of the four children: e_1 = rho_1 P(e_2) - r_1 g^_1 (each child is this
-      // lane's alone, so no barrier separates it from level 2)
-      const int cc[4] = {c0, c0 + 1, c1, c1 + 1};
+      // e_1 = rho_1 P(e_2) - r_1 g^_1 for the four children
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        C[cc[q]] = make_double2(rh1[q] * e.x - rr1[q] * ch[q].x, rh1[q] * e.y - rr1[q] * ch[q].y);
+        e1[q] = make_double2(rh1[q] * e.x - rr1[q] * ch[q].x, rh1[q] * e.y - rr1[q] * ch[q].y);
     }
-    l_up = 0;   // every level done
+    __syncthreads();   // every lane has read its pixels: C may overwrite the tile
+    if (act) {
+      const int c0 = (2 * Y2) * S1 + 2 * X2, c1 = c0 + S1;
+      C[c0] = e1[0];
+      C[c0 + 1] = e1[1];
+      C[c1] = e1[2];
+      C[c1 + 1] = e1[3];
+    }
   } else {
+    // two grids: level 1 is the coarsest, e_1 = -r_1 g^_1 (r_1 follows V_1, rho_1)
+    const double* r1 = a.lvl + 2 * M1 * M1;
+    double r1v[E1];
+    double2 gh1[E1];
+  #pragma unroll
+    for (int i = 0; i < E1; ++i) {
+      const int e = tid + i * TPB;
+      r1v[i] = (L == 2 && e < M1 * M1) ? r1[e] : 0.0;
+      gh1[i] = make_double2(0.0, 0.0);
+      if (e < M1 * M1) {
+        const int Y = e / M1, X = e % M1;
+        const float2 p0 = T[(2 * Y) * P + 2 * X], p1 = T[(2 * Y) * P + 2 * X + 1];
+        const float2 p2 = T[(2 * Y + 1) * P + 2 * X], p3 = T[(2 * Y + 1) * P + 2 * X + 1];
+        gh1[i].x = 0.25 * (((double)p0.x + p1.x) + ((double)p2.x + p3.x));
+        gh1[i].y = 0.25 * (((double)p0.y + p1.y) + ((double)p2.y + p3.y));
+      }
+    }
+    __syncthreads();
+  #pragma unroll
+    for (int i = 0; i < E1; ++i) {
+      const int e = tid + i * TPB;
+      if (e < M1 * M1) {
+        double2 w = gh1[i];
+        if (L == 2) w = make_double2(-r1v[i] * w.x, -r1v[i] * w.y);
+        C[(e / M1) * S1 + e % M1] = w;
+      }
+    }
+    // restriction down: g^_l = I(V_{l-1} g^_{l-1}); coarsest: e = -r g^
+    int lv_prev = 0, Mp = M1;
     for (int l = 2; l < L; ++l) {
       const int Ml = Mp >> 1;
       const int off_prev = off_of(l - 1), sp = pitch_of(l - 1), off_cur = off_of(l);
@@ -428,35 +439,35 @@ __device__ void magps_lds(const StepArgs& a, const float2* T, double2* C, const 
       lv_prev = lv_cur;
       Mp = Ml;
     }
-  }
-  // prolongation up: e_l = rho_l P(e_{l+1}) - r_l g^_l for l = L-2 .. 1
-  for (int l = l_up; l >= 1; --l) {
-    const int Ml = Mp << 1;
-    const int off_prev = off_of(l + 1), sp = pitch_of(l + 1), off_cur = off_of(l), sc = pitch_of(l);
-    const int lv_cur = lv_prev - 3 * Ml * Ml;
-    const double* rhol = a.lvl + lv_cur + Ml * Ml;
-    const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
-    double rh[E1], rr[E1];
-#pragma unroll
-    for (int i = 0; i < E1; ++i) {
-      const int e = tid + i * TPB;
-      const bool in = e < Ml * Ml;
-      rh[i] = in ? rhol[e] : 0.0;
-      rr[i] = in ? rl[e] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < E1; ++i) {
-      const int e = tid + i * TPB;
-      if (e < Ml * Ml) {
-        const int Y = e / Ml, X = e % Ml;
-        const double2 ec = C[off_prev + (Y >> 1) * sp + (X >> 1)];
-        const double2 gh = C[off_cur + Y * sc + X];
-        C[off_cur + Y * sc + X] = make_double2(rh[i] * ec.x - rr[i] * gh.x, rh[i] * ec.y - rr[i] * gh.y);
+    // prolongation up: e_l = rho_l P(e_{l+1}) - r_l g^_l for l = L-2 .. 1
+    for (int l = L - 2; l >= 1; --l) {
+      const int Ml = Mp << 1;
+      const int off_prev = off_of(l + 1), sp = pitch_of(l + 1), off_cur = off_of(l), sc = pitch_of(l);
+      const int lv_cur = lv_prev - 3 * Ml * Ml;
+      const double* rhol = a.lvl + lv_cur + Ml * Ml;
+      const double* rl = a.lvl + lv_cur + 2 * Ml * Ml;
+      double rh[E1], rr[E1];
+  #pragma unroll
+      for (int i = 0; i < E1; ++i) {
+        const int e = tid + i * TPB;
+        const bool in = e < Ml * Ml;
+        rh[i] = in ? rhol[e] : 0.0;
+        rr[i] = in ? rl[e] : 0.0;
       }
+      __syncthreads();
+  #pragma unroll
+      for (int i = 0; i < E1; ++i) {
+        const int e = tid + i * TPB;
+        if (e < Ml * Ml) {
+          const int Y = e / Ml, X = e % Ml;
+          const double2 ec = C[off_prev + (Y >> 1) * sp + (X >> 1)];
+          const double2 gh = C[off_cur + Y * sc + X];
+          C[off_cur + Y * sc + X] = make_double2(rh[i] * ec.x - rr[i] * gh.x, rh[i] * ec.y - rr[i] * gh.y);
+        }
+      }
+      lv_prev = lv_cur;
+      Mp = Ml;
     }
-    lv_prev = lv_cur;
-    Mp = Ml;
   }
   __syncthreads();
   // stage_k (this position's staged update) is uniform, so the resource stays scalar
