@@ -112,7 +112,7 @@ def host_cpu_name() -> str:
 
 
 def usable_cores() -> int:
-    """Host cores this process may use, capped at 16 (a one-GPU machine's share)."""
+    """Host cores this process may use, capped at 16 (the host share of one GPU)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -527,7 +527,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
