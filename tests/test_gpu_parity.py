@@ -39,7 +39,8 @@ def test_forward_model(m):
 
 
 @pytest.mark.parametrize("m,levels", [(8, 1), (8, 4), (16, 2), (16, 5), (32, 1), (32, 2), (32, 3), (32, 6),
-                                      (64, 3), (64, 4), (64, 7), (128, 4), (128, 2), (128, 6)])
+                                      (64, 3), (64, 4), (64, 7), (128, 2), (128, 3), (128, 4), (128, 5),
+                                      (128, 6)])
 @pytest.mark.parametrize("batch", [1, 5, 10_000])
 def test_one_epoch_parity(m, levels, batch):
     rng = np.random.default_rng(1000 * m + 10 * levels + (batch % 97))
@@ -475,8 +476,8 @@ def test_probe_alternate_needs_probe_update():
     g.close()
 
 
-@pytest.mark.parametrize("m,rb,levels", [(16, 2, 3), (32, 2, 3), (64, 4, 3), (64, 4, 5), (32, 2, 6), (128, 4, 4),
-                                          (128, 4, 7)])
+@pytest.mark.parametrize("m,rb,levels", [(16, 2, 3), (32, 2, 3), (64, 4, 3), (64, 4, 5), (32, 2, 6), (128, 4, 3),
+                                          (128, 4, 4), (128, 4, 7)])
 def test_fft_plan_variants(m, rb, levels):
     """Every compiled FFT plan matches the oracle (one epoch from the same z)."""
     from paper_2504_10118_amd import list_plans
