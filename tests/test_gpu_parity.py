@@ -319,6 +319,39 @@ def test_error_paths():
     g.close()
 
 
+def test_degenerate_calls():
+    """Calls that do nothing or are refused leave the reconstruction as it was: zero
+    epochs, minibatch size 0, a negative epoch count, an empty, repeated or out-of-range
+    minibatch, an empty scan.  A minibatch size above the number of positions is one
+    minibatch of all of them, bit for bit."""
+    from paper_2504_10118_amd import MagpieError
+    rng = np.random.default_rng(13)
+    c = Case(rng, 80, 84, 16, 7, noise=0.05)
+    g = c.gpu(3, 0.5)
+    z0 = g.get_object()
+    g.run_epochs(0, 4)
+    assert g.epoch_index == 0
+    assert np.array_equal(g.get_object().view(np.uint64), z0.view(np.uint64))
+    for call in (lambda: g.run_epochs(1, 0), lambda: g.run_epochs(-1, 4), lambda: g.run_minibatch([]),
+                 lambda: g.run_minibatch([1, 1]), lambda: g.run_minibatch([c.n_pos])):
+        with pytest.raises(MagpieError) as e:
+            call()
+        assert e.value.name == "INVALID_ARG"
+    with pytest.raises(MagpieError) as e:
+        g.set_positions(np.zeros((0, 2), np.int32))
+    assert e.value.name == "INVALID_ARG"
+    assert g.epoch_index == 0
+    assert np.array_equal(g.get_object().view(np.uint64), z0.view(np.uint64))
+    order = rng.permutation(c.n_pos).astype(np.int32)
+    g.run_epochs(1, 10 * c.n_pos, order=order[None])
+    whole = g.get_object()
+    g.close()
+    h = c.gpu(3, 0.5)
+    h.run_epochs(1, c.n_pos, order=order[None])
+    assert np.array_equal(whole.view(np.uint64), h.get_object().view(np.uint64))
+    h.close()
+
+
 def test_intensities_not_sqrt_and_explicit_u():
     rng = np.random.default_rng(13)
     c = Case(rng, 72, 72, 16, 6, noise=0.05)
