@@ -921,7 +921,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
             if (l < L) {
               const int Ml = M >> l;
               double2 s[NC];
-              if (l - 1 < LRB) {
+              if (l == 1) {
+                // the partner row's FP32 values, widened after the exchange (half the
+                // cross-lane moves of exchanging the FP64 values; the same sums)
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                  const float2 f = v[n0 + i];
+                  const float ox = __int_as_float(xor_lane<1, XV>(__float_as_int(f.x)));
+                  const float oy = __int_as_float(xor_lane<1, XV>(__float_as_int(f.y)));
+                  s[i] = make_double2((double)f.x + (double)ox, (double)f.y + (double)oy);
+                }
+              } else if (l - 1 < LRB) {
 #pragma unroll
                 for (int i = 0; i < NC; ++i) {
                   const double2 o = xor_lane_rt<XV>(cur[i], 1 << (l - 1));
@@ -935,14 +945,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
                   s[i] = make_double2(cur[i].x + o.x, cur[i].y + o.y);
                 }
               }
-              // A_l and V_l from the block parked in LDS (rows padded by CST_PAD)
+              // A_l and V_l from the block parked in LDS (rows padded by CST_PAD), both
+              // stored times 1/4: gh is the bin's sum, 4 g^_l, and the products with the
+              // scaled constants are the same numbers as those of the mean (scaling by a
+              // power of two is exact)
               const double* A = (const double*)Cst + (size_t)(l - 1) * M1c * (M1c + CST_PAD);
               const double* V = (const double*)Cst + cst_v_off(M, L, l);
               const bool more = (l + 1 < L);
 #pragma unroll
               for (int i = 0; i < NC; ++i) {
                 const double2 o = xor_lane_rt<XV>(s[i], RB << (l - 1));
-                const double2 gh = make_double2(0.25 * (s[i].x + o.x), 0.25 * (s[i].y + o.y));
+                const double2 gh = make_double2(s[i].x + o.x, s[i].y + o.y);
                 const int y = RB * (n0 + i) + g;
                 const double aa = A[(y >> 1) * (M1c + CST_PAD) + (col >> 1)];
                 e1[i] = make_double2(e1[i].x + aa * gh.x, e1[i].y + aa * gh.y);
@@ -1568,7 +1581,8 @@ __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels
   // A_l = -r_l prod_{j<l} rho_j along the ancestors of each level-1 bin, so
   // that e_1 = sum_l A_l g^_l (the upward pass of the V-cycle, unrolled).  The
   // in-wave V-cycle's block: A_1..A_{L-1}, then copies of V_1..V_{L-2}, every
-  // grid row padded to side + CST_PAD doubles (pads zero).
+  // grid row padded to side + CST_PAD doubles (pads zero), all stored times 1/4
+  // (the in-wave V-cycle multiplies them with the sums of 2 x 2 bins, not the means).
   __syncthreads();
   if (levels > 1) {
     const int M1 = m / 2, S1 = M1 + CST_PAD;
@@ -1587,7 +1601,7 @@ __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels
           val = -r * prod;
           prod *= rho;
         }
-        A[(size_t)(l - 1) * M1 * S1 + e] = val;
+        A[(size_t)(l - 1) * M1 * S1 + e] = 0.25 * val;
         off += 3 * Ml * Ml;
       }
     }
@@ -1597,7 +1611,7 @@ __global__ __launch_bounds__(1024) void level_constants_kernel(int m, int levels
       const int Ml = m >> l, Sl = Ml + CST_PAD;
       for (int e = tid; e < Ml * Sl; e += blockDim.x) {
         const int Y = e / Sl, X = e % Sl;
-        Vc[e] = X < Ml ? lvl[off + Y * Ml + X] : 0.0;
+        Vc[e] = X < Ml ? 0.25 * lvl[off + Y * Ml + X] : 0.0;
       }
       Vc += Ml * Sl;
       off += 3 * Ml * Ml;
