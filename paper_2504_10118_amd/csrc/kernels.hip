@@ -237,15 +237,19 @@ __device__ __forceinline__ float wave_max(float v) {
 // amplitude s (Definition 2.1), kept as the difference t - s e with e = t / |t|
 // (= F(Q z_k) - F(R_k)); returns false where t counts as zero (the caller applies
 // its theta(0) rule) only where t is exactly zero.  (|t| - s)^2 is added to
-// phis.  The hardware reciprocal square root does not take single-precision
+// phis, in the accumulator's type PA: FP64 for the objective, FP32 for the per-step
+// terms of a step (each thread sums at most 16 of them before the FP64 sum over the
+// workgroup, about 1e-6 relative, below the FP32 transform's own error).  The
+// hardware reciprocal square root does not take single-precision
 // denormals, and |t|^2 underflows for |t| < 2^-75, so where |t|^2 < 2^-100 the
 // value is first scaled by 2^100 (exactly): every nonzero t then has a normal
 // squared magnitude in [2^-98, 2^100).
-__device__ __forceinline__ bool modulus_diff(float2 t, float s, float2& out, float2& e, double& phis) {
+template <typename PA>
+__device__ __forceinline__ bool modulus_diff(float2 t, float s, float2& out, float2& e, PA& phis) {
   const float a2 = t.x * t.x + t.y * t.y;
   if (a2 >= 0x1p-100f) {
     const float ra = __builtin_amdgcn_rsqf(a2);
-    const double dlt = (double)(a2 * ra) - (double)s;
+    const PA dlt = (PA)(a2 * ra) - (PA)s;
     phis += dlt * dlt;
     e = make_float2(t.x * ra, t.y * ra);
     const float f = fmaf(-s, ra, 1.0f);
@@ -256,7 +260,7 @@ __device__ __forceinline__ bool modulus_diff(float2 t, float s, float2& out, flo
   const float b2 = tx * tx + ty * ty;
   if (!(b2 > 0.0f)) return false;
   const float rb = __builtin_amdgcn_rsqf(b2);
-  const double dlt = (double)(b2 * rb) * 0x1p-100 - (double)s;
+  const PA dlt = (PA)(b2 * rb) * (PA)0x1p-100 - (PA)s;
   phis += dlt * dlt;
   e = make_float2(tx * rb, ty * rb);
   out = make_float2(fmaf(-s, e.x, t.x), fmaf(-s, e.y, t.y));
@@ -746,12 +750,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       }
     return;
   } else {
-    // ---- modulus replacement (Definition 2.1, theta(0) = 0); Phi_k partial in FP64.
+    // ---- modulus replacement (Definition 2.1, theta(0) = 0); Phi_k partial (summed
+    // in FP64 for the objective; for a step's own terms per thread in FP32, then FP64).
     // The spectrum is replaced by the difference F(Q z_k) - F(R_k) = F(Q z_k)
     // (1 - sqrt(d) / |F(Q z_k)|) (-sqrt(d) theta where the spectrum vanishes), so
     // the inverse transform yields Q z_k - R_k itself: the gradient needs
     // neither the exit wave kept nor the patch read again.
-    double phis = 0.0;
+    using PA = std::conditional_t<MODE == MODE_OBJECTIVE, double, float>;
+    PA phis = 0;
     if constexpr (MODE == MODE_STEP_PR) {
       // eq. (3.2): every phase factor is kept for the position's next visit and
       // read back where the spectrum vanishes exactly (theta = 0 before the
@@ -767,7 +773,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
           ph[kx] = e;
           v[j] = dv;
         } else {
-          phis += (double)s * (double)s;
+          phis += (PA)s * (PA)s;
           e = ph[kx];
           v[j] = make_float2(-s * e.x, -s * e.y);
         }
@@ -780,13 +786,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       if (modulus_diff(v[j], s, dv, e, phis)) {
         v[j] = dv;
       } else {
-        phis += (double)s * (double)s;
+        phis += (PA)s * (PA)s;
         v[j] = make_float2(-s, 0.0f);
       }
     }
     }
     if (a.phi_part) {
-      const double tot = wave_sum<LANES, XV>(phis);
+      const double tot = wave_sum<LANES, XV>((double)phis);
       if ((tid & 63) == 0) a.phi_part[(size_t)k * MAX_WAVES + wave] = tot * (0.5 / ((double)M * (double)M));
     }
 
