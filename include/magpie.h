@@ -202,9 +202,11 @@ int magpie_run_epochs_noalloc(magpie_ctx* ctx, int n_epochs, int batch, uint64_t
 int magpie_objective(magpie_ctx* ctx, double* phi, double* grad_stat);
 
 /*
- * Per-position objective terms Phi_k (FP64, [n_pos]) at the object as it was
- * when each position was last visited by magpie_run_epochs (NaN if never).
- * Host output; synchronises.
+ * Per-position objective terms Phi_k (eq. 2.1's term of position k; [n_pos],
+ * returned as FP64) at the object as it was when each position was last visited
+ * by magpie_run_epochs (NaN if never).  Summed by the step itself: per thread in
+ * FP32 over at most 16 spectrum values, then in FP64 (about 1e-6 relative; use
+ * magpie_objective for the FP64 objective).  Host output; synchronises.
  */
 int magpie_get_step_phi(magpie_ctx* ctx, double* phi_k);
 
