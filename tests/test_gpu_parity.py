@@ -160,15 +160,20 @@ def test_objective_and_stat():
     assert abs(stat - stat_o) <= 1e-5 * stat_o
 
 
-def test_step_phi_matches_objective_terms():
-    rng = np.random.default_rng(6)
-    c = Case(rng, 80, 80, 16, 6, noise=0.05)
+@pytest.mark.parametrize("m", [16, 64, 128])
+def test_step_phi_matches_objective_terms(m):
+    """The per-step objective terms (summed per thread in FP32 over 4, 8 or 16
+    spectrum values, then in FP64) against the oracle's Phi_k at the same object."""
+    rng = np.random.default_rng(6 + m)
+    n = 5 * m
+    c = Case(rng, n, n, m, m // 3, noise=0.05)
     g = c.gpu(3, 0.5)
     order = np.arange(c.n_pos, dtype=np.int32)
     g.run_epochs(1, c.n_pos, order=order[None, :])   # one minibatch: all read z0
     ph = g.step_phi()
     g.close()
-    want = np.array([oracle.phi_k(oracle.extract(c.z0, o, 16), c.Q, c.sd[k]) for k, o in enumerate(c.offs)])
+    want = np.array([oracle.phi_k(oracle.extract(c.z0, o, m), c.Q, c.sd[k]) for k, o in enumerate(c.offs)])
+    _print("step phi m", m, "N", c.n_pos, "max rel", np.max(np.abs(ph - want) / want))
     np.testing.assert_allclose(ph, want, rtol=2e-5)
 
 
