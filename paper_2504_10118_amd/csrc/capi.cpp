@@ -299,6 +299,7 @@ int magpie_destroy(magpie_ctx* c) {
   dev_free(c->pmax);
   dev_free(c->pacc);
   dev_free(c->posrec);
+  dev_free(c->posx);
   dev_free(c->inv);
   dev_free(c->lrn_sd);
   dev_free(c->lrn_stats);
@@ -540,12 +541,15 @@ static int ensure_epoch_buffers(magpie_ctx* c, int n_epochs, int batch, size_t r
     MG_HIP(hipStreamSynchronize(c->stream));
     drop_graph(c);
     dev_free(c->posrec);
+    dev_free(c->posx);
     dev_free(c->inv);
     rc = dev_alloc(&c->inv, nrec);
     if (!rc) rc = dev_alloc(&c->posrec, nrec);
+    if (!rc) rc = dev_alloc(&c->posx, nrec);
     if (rc) {
       dev_free(c->inv);
       dev_free(c->posrec);
+      dev_free(c->posx);
       c->perm_cap = 0;
       return rc;
     }
@@ -555,10 +559,10 @@ static int ensure_epoch_buffers(magpie_ctx* c, int n_epochs, int batch, size_t r
 }
 
 // Pinned host area for the records of `epochs` epochs in each of the two slots
-// (inverse permutation, then 4 ints per position record), grown as needed once
-// both slots' uploads are done.
+// (inverse permutation, then 4 ints per position record in processing order and 4
+// in workgroup order), grown as needed once both slots' uploads are done.
 static int ensure_pinned(magpie_ctx* c, size_t epochs) {
-  const size_t need = 2 * epochs * (size_t)c->n_pos * 5;
+  const size_t need = 2 * epochs * (size_t)c->n_pos * 9;
   if (need <= c->h_pin_cap) return MAGPIE_OK;
   for (int s = 0; s < 2; ++s)
     if (c->pin_pending[s]) {
@@ -592,13 +596,47 @@ static int check_orders(magpie_ctx* c, int n_epochs, const int32_t* order) {
   return MAGPIE_OK;
 }
 
+// Workgroup order of one minibatch's records (bt records of 4 ints, processing
+// order) into `out`: (k, row, col, slot).  A launch's consecutive workgroups go to
+// the GPU's eight XCDs in turn, and each XCD has its own L2.  The windows are
+// bucketed by the 16 x 16 cells (side 2^cs) of their corners, the buckets taken
+// along a Morton curve (slot order within a bucket), and the result cut into eight
+// contiguous runs, run x going to the workgroups x, x + 8, x + 16, ...: the windows
+// one L2 serves are neighbours, so their patches overlap.  Every staged update and
+// every sum stays at its slot, so the results do not change.
+static void workgroup_order(const int32_t* rec, int bt, int cs, int32_t* out, std::vector<int>& cnt,
+                            std::vector<int>& sorted) {
+  auto key = [&](int i) {
+    const uint32_t y = std::min(15u, (uint32_t)rec[4 * i + 1] >> cs);
+    const uint32_t x = std::min(15u, (uint32_t)rec[4 * i + 2] >> cs);
+    uint32_t k = 0;
+    for (int b = 0; b < 4; ++b) k |= (((x >> b) & 1u) << (2 * b)) | (((y >> b) & 1u) << (2 * b + 1));
+    return (int)k;
+  };
+  cnt.assign(257, 0);
+  sorted.resize((size_t)bt);
+  for (int i = 0; i < bt; ++i) ++cnt[(size_t)key(i) + 1];
+  for (int k = 0; k < 256; ++k) cnt[(size_t)k + 1] += cnt[(size_t)k];
+  for (int i = 0; i < bt; ++i) sorted[(size_t)cnt[(size_t)key(i)]++] = i;
+  const int q = bt / 8, r = bt % 8;
+  for (int w = 0; w < bt; ++w) {
+    const int x = w % 8, j = x * q + std::min(x, r) + w / 8;
+    const int sl = sorted[(size_t)j];
+    out[4 * w] = rec[4 * sl];
+    out[4 * w + 1] = rec[4 * sl + 1];
+    out[4 * w + 2] = rec[4 * sl + 2];
+    out[4 * w + 3] = sl;
+  }
+}
+
 // Inverse permutations and position records (k, row, col) in processing order of
 // epochs e0 .. e0+ne-1 (permutations from `order`, already checked, or the
 // library's seeded ones for epoch counter c->epoch_index + e), built in pinned
 // slot `slot` (slot_epochs epochs wide) and uploaded to the device records from
-// epoch offset dev_epoch; the slot's event marks the end of its upload.
+// epoch offset dev_epoch; the slot's event marks the end of its upload.  With
+// batch > 0 the records of its minibatches in workgroup order go to c->posx too.
 static int fill_records(magpie_ctx* c, int e0, int ne, uint64_t seed, const int32_t* order, int slot,
-                        size_t slot_epochs, size_t dev_epoch, hipStream_t s) {
+                        size_t slot_epochs, size_t dev_epoch, hipStream_t s, int batch = 0) {
   const int N = c->n_pos;
   // a slot's region moves with its width: then both slots' uploads must be done
   for (int s = 0; s < 2; ++s)
@@ -607,8 +645,11 @@ static int fill_records(magpie_ctx* c, int e0, int ne, uint64_t seed, const int3
       c->pin_pending[s] = false;
     }
   c->pin_width = slot_epochs;
-  int32_t* hi = c->h_pin + (size_t)slot * slot_epochs * N * 5;
+  int32_t* hi = c->h_pin + (size_t)slot * slot_epochs * N * 9;
   int32_t* hr = hi + slot_epochs * N;
+  int32_t* hx = hr + slot_epochs * N * 4;
+  int cs = 0;   // cell side 2^cs: corners fall in a 16 x 16 grid of cells
+  while (((std::max(c->nr, c->nc) - 1) >> cs) >= 16) ++cs;
   c->h_perm.resize((size_t)N);
   for (int e = 0; e < ne; ++e) {
     const int32_t* p;
@@ -628,10 +669,15 @@ static int fill_records(magpie_ctx* c, int e0, int ne, uint64_t seed, const int3
       r[4 * i + 2] = c->h_offs[2 * (size_t)k + 1];
       r[4 * i + 3] = 0;
     }
+    if (batch > 0)
+      for (int t0 = 0; t0 < N; t0 += batch)
+        workgroup_order(r + 4 * (size_t)t0, std::min(batch, N - t0), cs, hx + ((size_t)e * N + t0) * 4, c->h_cnt,
+                        c->h_sorted);
   }
   const size_t n = (size_t)ne * N;
   MG_HIP(hipMemcpyAsync(c->inv + dev_epoch * N, hi, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
   MG_HIP(hipMemcpyAsync(c->posrec + dev_epoch * N, hr, n * sizeof(int4), hipMemcpyHostToDevice, s));
+  if (batch > 0) MG_HIP(hipMemcpyAsync(c->posx + dev_epoch * N, hx, n * sizeof(int4), hipMemcpyHostToDevice, s));
   MG_HIP(hipEventRecord(c->pin_done[slot], s));
   c->pin_pending[slot] = true;
   return MAGPIE_OK;
@@ -698,6 +744,7 @@ int mgrt::launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoc
   }
   auto probe_pass = [&]() -> hipError_t {
     sp.pos = sa.pos;
+    sp.posx = sa.posx;
     sp.count = sa.count;
     sp.epoch = sa.epoch;
     sp.epoch_stride = sa.epoch_stride;
@@ -783,6 +830,7 @@ int mgrt::launch_epochs(magpie_ctx* c, int n_epochs, int B, int batches_per_epoc
   for (int e = 0; e < n_epochs; ++e) {
     for (int t = 0; t < nbatch; ++t) {
       sa.pos = buf.posrec + (size_t)e * N + (size_t)t * B;
+      sa.posx = buf.posx ? buf.posx + (size_t)e * N + (size_t)t * B : nullptr;
       sa.count = std::min(B, N - t * B);
       int ti = timed_slot(c, 0, sa.count);
       MG_HIP(mg::launch_step(m, c->rb, mg::MODE_STEP, sa, c->stream, ti >= 0 ? c->timed[ti].a : nullptr,
@@ -818,7 +866,8 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
     rc = prepare_epochs(c, n_epochs, batch, seed, order);
     if (rc) return rc;
     const int B = std::min(batch, c->n_pos);
-    rc = launch_epochs(c, n_epochs, B, (c->n_pos + B - 1) / B, true, EpochBuffers{c->stage, c->posrec, c->inv});
+    rc = launch_epochs(c, n_epochs, B, (c->n_pos + B - 1) / B, true,
+                       EpochBuffers{c->stage, c->posrec, c->inv, nullptr});
     if (rc) return rc;
     c->epoch_index += (uint64_t)n_epochs;
     return MAGPIE_OK;
@@ -837,14 +886,18 @@ int magpie_run_epochs(magpie_ctx* c, int n_epochs, int batch, uint64_t seed, con
   if (rc) return rc;
   const int N = c->n_pos;
   const int B = std::min(batch, N);
+  // workgroup order for the 128-point plans, whose gathers are bound by the patches'
+  // L2 misses (measured no faster at m = 64)
+  const bool xorder = c->m >= 128;
   int chunk = 0;
   for (int e0 = 0; e0 < n_epochs; ++chunk) {
     const int ne = chunk == 0 ? 1 : std::min(CH, n_epochs - e0);
     const int slot = chunk & 1;
-    rc = fill_records(c, e0, ne, seed, order, slot, ch, (size_t)slot * ch, c->stream);
+    rc = fill_records(c, e0, ne, seed, order, slot, ch, (size_t)slot * ch, c->stream, xorder ? B : 0);
     if (rc) return rc;
     const size_t off = (size_t)slot * ch * N;
-    rc = launch_epochs(c, ne, B, (N + B - 1) / B, false, EpochBuffers{c->stage, c->posrec + off, c->inv + off});
+    rc = launch_epochs(c, ne, B, (N + B - 1) / B, false,
+                       EpochBuffers{c->stage, c->posrec + off, c->inv + off, xorder ? c->posx + off : nullptr});
     if (rc) return rc;
     e0 += ne;
   }
@@ -874,7 +927,7 @@ int magpie_run_minibatch(magpie_ctx* c, int count, const int32_t* positions) {
     if (!seen[(size_t)k]) order.push_back(k);
   int rc = prepare_epochs(c, 1, count, 0, order.data());
   if (rc) return rc;
-  return launch_epochs(c, 1, count, 1, false, EpochBuffers{c->stage, c->posrec, c->inv});
+  return launch_epochs(c, 1, count, 1, false, EpochBuffers{c->stage, c->posrec, c->inv, nullptr});
 }
 
 int magpie_objective(magpie_ctx* c, double* phi, double* grad_stat) {

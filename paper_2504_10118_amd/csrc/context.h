@@ -135,6 +135,7 @@ struct magpie_ctx {
   double* pacc = nullptr;   // probe step: per-chunk partial sums (mg::probe_scratch_doubles)
   size_t pcap = 0;
   int4* posrec = nullptr;  // [E][N] (k, row, col, 0) in processing order
+  int4* posx = nullptr;    // [E][N] the same records in workgroup order, (k, row, col, slot)
   int* inv = nullptr;    // [E][N] position -> index in its epoch's permutation
   size_t perm_cap = 0;   // entries per array
   // pinned host records in two slots (filled while the GPU runs the other one)
@@ -155,6 +156,7 @@ struct magpie_ctx {
   size_t qctr_cap = 0;   // ints
   std::vector<int32_t> h_perm;   // host scratch: one epoch's permutation
   std::vector<int> h_seen;       // host scratch: permutation check
+  std::vector<int> h_cnt, h_sorted;   // host scratch: a minibatch's windows bucketed by cell
 
   // optional per-launch timing
   bool timing = false;
@@ -200,6 +202,7 @@ struct EpochBuffers {
   float2* stage;
   const int4* posrec;
   const int* inv;
+  const int4* posx;   // nullable: records in workgroup order (step launches read them if given)
 };
 
 // noalloc.hip: resolves the device address of the no-allocation entry point's

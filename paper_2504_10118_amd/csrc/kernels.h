@@ -36,6 +36,8 @@ struct StepArgs {
   const float* sqrtd;     // sqrt(d) in kernel order [N][m*m]
   const int2* offs;       // (row, col) per position [N]
   const int4* pos;        // MODE_STEP: (k, row, col, 0) of the positions handled, one per workgroup
+  const int4* posx;       // MODE_STEP, nullable: the same records in workgroup order, .w = the slot
+                          // (index in pos) the workgroup handles; NULL: workgroup i handles slot i
   const int* perm;        // other modes: positions handled; NULL = identity
   const int* epoch;       // nullable: perm is advanced by (*epoch) * epoch_stride (graph replays)
   int epoch_stride;

@@ -148,6 +148,7 @@ __device__ __forceinline__ StepArgs load_step_args(const StepArgs* p) {
   a.sqrtd = d->sqrtd;
   a.offs = d->offs;
   a.pos = d->pos;
+  a.posx = nullptr;    // multi-context runs keep workgroup = slot
   a.perm = d->perm;
   a.epoch = d->epoch;
   a.epoch_stride = d->epoch_stride;
@@ -523,9 +524,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
   const int c0w = col - cl;
   const int wave = tid >> 6;
   const size_t eoff = a.epoch ? (size_t)(*a.epoch) * a.epoch_stride : 0;
-  int k;
+  int k, slot = wg;   // slot: where this position's staged update (and probe partials) go
   int2 off;
-  if (a.pos) {
+  if (a.posx) {
+    const int4 pr = a.posx[eoff + wg];
+    k = pr.x;
+    off = make_int2(pr.y, pr.z);
+    slot = pr.w;
+  } else if (a.pos) {
     const int4 pr = a.pos[eoff + wg];
     k = pr.x;
     off = make_int2(pr.y, pr.z);
@@ -538,6 +544,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     // may alias them); the values are uniform, and the buffer resources built
     // from them must be scalar
     k = __builtin_amdgcn_readfirstlane(k);
+    slot = __builtin_amdgcn_readfirstlane(slot);
     off = make_int2(__builtin_amdgcn_readfirstlane(off.x), __builtin_amdgcn_readfirstlane(off.y));
   }
 
@@ -869,7 +876,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
           const float2 zz = bload2p<ZPOL>(zr, zvo, n1 * zso);
           const float2 pn = cmulc(zz, make_float2(-dk.x, -dk.y));
           const float pd = zz.x * zz.x + zz.y * zz.y;
-          const size_t e = (size_t)wg * M * M + (size_t)(RB * n1 + g) * M + col;
+          const size_t e = (size_t)slot * M * M + (size_t)(RB * n1 + g) * M + col;
           a.probe_num[e] = pn;
           a.probe_den[e] = pd;
           pmx = fmaxf(pmx, pd);
@@ -880,7 +887,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
     if constexpr (STEPM) {
       if (a.probe_num) {
         const float wm = wave_max<LANES, XV>(pmx);
-        if ((tid & 63) == 0) a.probe_max[(size_t)wg * MAX_WAVES + wave] = wm;
+        if ((tid & 63) == 0) a.probe_max[(size_t)slot * MAX_WAVES + wave] = wm;
       }
     }
 
@@ -892,7 +899,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
       if ((tid & 63) == 0) a.gn_part[(size_t)k * MAX_WAVES + wave] = tot;
       return;
     } else {
-      const rsrc_t outr = make_rsrc(a.stage + (size_t)wg * M * M, (unsigned)(M * M * sizeof(float2)));
+      const rsrc_t outr = make_rsrc(a.stage + (size_t)slot * M * M, (unsigned)(M * M * sizeof(float2)));
       const int ovo = (g * M + col) * (int)sizeof(float2);
       const int L = a.levels;
       if (L <= 1) {
@@ -1000,7 +1007,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int wg) {
 #pragma unroll
       for (int n1 = 0; n1 < RA; ++n1) T[(RB * n1 + g) * P + col] = v[n1];
       __syncthreads();
-      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, u0v, col, g, a.stage + (size_t)wg * M * M, tid);
+      magps_lds<M, TPB, P, RB, RA>(a, T, smem_d2, v, u0v, col, g, a.stage + (size_t)slot * M * M, tid);
     }
   }
 }

@@ -137,7 +137,7 @@ extern "C" int magpie_run_epochs_noalloc(magpie_ctx* c, int n_epochs, int batch,
       rc = fail(MAGPIE_ERR_HIP, std::string("permutation kernel: ") + hipGetErrorString(le));
       break;
     }
-    rc = launch_epochs(c, ne, B, (N + B - 1) / B, false, EpochBuffers{stage, posrec, inv});
+    rc = launch_epochs(c, ne, B, (N + B - 1) / B, false, EpochBuffers{stage, posrec, inv, nullptr});
   }
   c->timing = timing;
   if (rc) return rc;
